@@ -1,0 +1,851 @@
+/*
+ * glint_oracle.c -- plain, slow, FP64 CPU reference of per-pixel glint shading
+ * (Deliot & Belcour, "Real-Time Rendering of Glinty Appearances using
+ * Distributed Binomial Laws on Anisotropic Grids", HPG 2023).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP path is
+ * checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the product library never does.  It
+ * shares no code, header, table or constant generator with the HIP path.
+ *
+ * Every step follows the paper in its own order and notation, in FP64, from
+ * the same FP32 inputs the GPU reads.  Where the paper leaves a choice open,
+ * the reading taken is the one written next to the step (the design notes
+ * list all of them).  Nothing here is blocked, fused or reordered for speed.
+ *
+ *   step                                        paper passage
+ *   footprint ellipse from screen derivatives   Sec. 5.1 (major/minor axes, rotation, ratio)
+ *   probe split of over-long footprints         Sec. 4.2 (distribute over more than 2 areas)
+ *   area level enclosure P_lo / P_hi            Sec. 5.2, Eq. 13; weights of Eq. 10
+ *   ratio / orientation cell, pentagon          Sec. 5.2, Fig. 4; Sec. 6.1, Fig. 5
+ *   prism -> tetrahedra split                   Sec. 6.1
+ *   anisotropic grid transform                  Sec. 5.1, Eq. 12 (rotate then scale)
+ *   simplex surface lattice                     Sec. 6.2, Fig. 6
+ *   success probability p = R D(h)/D(n)         Sec. 3, Eq. 4
+ *   angular bilinear grid over projected h      Sec. 5.2, Eq. 14
+ *   per-texel random numbers                    Sec. 3 (seeds on spatial / angular grids)
+ *   gated Gaussian binomial                     Sec. 6.3, Eqs. 16-18
+ *   distributed sum over grids                  Sec. 4.2, Eq. 10; Sec. 5.2
+ *   glint NDF, BRDF, radiance                   Sec. 3, Eqs. 1-3
+ *
+ * Parity pins (tests that hold this file to the paper and to mathematics,
+ * not to itself): footprint vs numpy SVD; NDF normalisation and Smith
+ * masking integrals by quadrature; inverse normal CDF vs scipy; gated
+ * binomial pmf vs its closed form through Phi; P(c=0) = (1-p)^n; area
+ * conservation of the distributed weights; brute-force stratified flake
+ * simulation for mean and variance of the distributed count; convergence
+ * of the seed-averaged glint NDF to D(h); continuity across level, ratio,
+ * orientation and lattice boundaries; frozen-branch finite differences
+ * against free finite differences.  The hash and the angular cell size are
+ * definitions of this implementation: parity unpinned beyond their
+ * statistical tests (uniformity, independence) and the bit-exact match.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OG_PI 3.14159265358979323846
+#define OG_MAX_NODES 4
+
+/* ------------------------------------------------------------------ */
+/* Public structures (mirrored by the ctypes wrapper in __init__.py).  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t width, height;
+    int64_t stride;
+    const float *u, *v, *dudx, *dvdx, *dudy, *dvdy;
+    const float *nx, *ny, *nz, *wx, *wy, *wz;
+    const int32_t *material_id;   /* NULL: every pixel uses material 0 */
+    const float *alpha_px;        /* NULL or per-pixel roughness */
+    const float *log10_density_px;/* NULL or per-pixel log10 flake density */
+} og_gbuffer;
+
+typedef struct {
+    int32_t ndf;                  /* 0 GGX, 1 Beckmann */
+    float alpha, R, log10_density, micro_roughness, F0;
+    uint32_t seed;
+} og_material;
+
+typedef struct { float dir[3]; float radiance[3]; } og_light;
+
+typedef struct { int32_t k_max, n_probe_max, rounding; } og_params;
+
+typedef struct {                  /* every plane is [height*stride] or NULL */
+    uint32_t *flags;
+    int32_t *n_probe, *level;
+    uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
+    double *margin;
+    int32_t *margin_kind;
+    double *b_light;              /* [n_light][height*stride]: raw distributed counts */
+} og_debug;
+
+/* flags */
+#define OGF_SHADED      1u
+#define OGF_CLAMP_RATIO 2u
+#define OGF_CLAMP_P     4u
+#define OGF_BAD_INPUT   8u
+#define OGF_BACKFACING  16u
+#define OGF_SKIPPED     32u
+#define OGF_BAD_MAT     64u
+
+/* margin kinds (which discrete decision came closest to its boundary) */
+enum { MK_NONE = 0, MK_NPROBE, MK_RATIO, MK_ORIENT, MK_TRIANGLE, MK_TETRA,
+       MK_LATTICE, MK_ANGULAR, MK_GATE, MK_COUNT, MK_LIGHT, MK_VIEW };
+
+/* ------------------------------------------------------------------ */
+/* Decision tape: records every light-dependent discrete decision of a */
+/* pixel so that gradients can be taken with those branches frozen     */
+/* (relaxed count, straight-through floor).                            */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t *buf;
+    size_t len, cap, pos;
+    int mode;                     /* 0 off, 1 record, 2 replay */
+} og_tape;
+
+static int32_t tape_dec(og_tape *T, int32_t computed)
+{
+    if (!T || T->mode == 0) return computed;
+    if (T->mode == 1) {
+        if (T->len == T->cap) {
+            size_t nc = T->cap ? 2 * T->cap : 256;
+            int32_t *nb = (int32_t *)realloc(T->buf, nc * sizeof(int32_t));
+            if (!nb) abort();
+            T->buf = nb; T->cap = nc;
+        }
+        T->buf[T->len++] = computed;
+        return computed;
+    }
+    if (T->pos >= T->len) abort();
+    return T->buf[T->pos++];
+}
+
+/* ------------------------------------------------------------------ */
+/* Random numbers attached to grid texels (Sec. 3: seeds distributed   */
+/* on a spatial and an angular grid).  The paper reads them from a     */
+/* precomputed texture (Sec. 6.3); here they are an integer hash of    */
+/* the texel key, with uint32 wraparound and no floating point.        */
+/* Mixer: the MurmurHash3 32-bit finaliser (A. Appleby, public domain) */
+/* ------------------------------------------------------------------ */
+uint32_t og_fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* one chaining step: absorb word w into state h */
+uint32_t og_hash_step(uint32_t h, uint32_t w)
+{
+    return og_fmix32((h ^ w) + 0x9E3779B9u);
+}
+
+/* key word of grid node (area level l, ratio level k, orientation m) */
+static uint32_t node_word(int l, int k, int m)
+{
+    return (uint32_t)(l + 1024) | ((uint32_t)k << 11) | ((uint32_t)m << 14);
+}
+
+/* key word of angular texel (ai, aj) and random-number slot s in {0,1} */
+static uint32_t angular_word(int ai, int aj, int s)
+{
+    return ((uint32_t)(ai + 16384) & 0x7FFFu) | (((uint32_t)(aj + 16384) & 0x7FFFu) << 15)
+           | ((uint32_t)s << 30);
+}
+
+/* the full key chain of one random number: material seed, grid node
+ * (l, k, m), simplex lattice vertex (i, j), angular texel (ai, aj), slot s */
+uint32_t og_texel_hash(uint32_t seed, int l, int k, int m, int i, int j, int ai, int aj, int s)
+{
+    uint32_t s0 = og_hash_step(0x243F6A88u, seed);
+    uint32_t base = og_hash_step(s0, node_word(l, k, m));
+    uint32_t pre = og_hash_step(og_hash_step(base, (uint32_t)i), (uint32_t)j);
+    uint32_t ak = og_hash_step(0x13198A2Eu, angular_word(ai, aj, s));
+    return og_hash_step(pre, ak);
+}
+
+/* 23 random bits -> uniform strictly inside (0,1), exact in FP32 and FP64 */
+static double uniform_of(uint32_t h)
+{
+    return (2.0 * (double)(h >> 9) + 1.0) * 0x1p-24;
+}
+
+/* ------------------------------------------------------------------ */
+/* Standard normal inverse CDF, FP64.  Definition: the z with          */
+/* Phi(z) = q, Phi(z) = erfc(-z/sqrt 2)/2.  Start from the Abramowitz  */
+/* & Stegun 26.2.23 rational estimate (|err| < 4.5e-4) and refine with */
+/* Halley steps on Phi(z) - q, using the lower tail for accuracy.      */
+/* ------------------------------------------------------------------ */
+double og_ndtri(double q)
+{
+    if (!(q > 0.0 && q < 1.0)) return q == 0.0 ? -INFINITY : (q == 1.0 ? INFINITY : NAN);
+    if (q > 0.5) return -og_ndtri(1.0 - q);   /* 1-q exact for q in (0.5,1) */
+    double t = sqrt(-2.0 * log(q));
+    double z = -(t - (2.515517 + 0.802853 * t + 0.010328 * t * t) /
+                      (1.0 + 1.432788 * t + 0.189269 * t * t + 0.001308 * t * t * t));
+    for (int it = 0; it < 4; ++it) {
+        double F = 0.5 * erfc(-z / sqrt(2.0));
+        double f = exp(-0.5 * z * z) / sqrt(2.0 * OG_PI);
+        double e = (F - q) / f;                    /* Newton step */
+        z = z - e / (1.0 + 0.5 * z * e);           /* Halley correction */
+    }
+    return z;
+}
+
+/* ------------------------------------------------------------------ */
+/* Microfacet pieces (Sec. 3, Eqs. 2-4).                               */
+/* ------------------------------------------------------------------ */
+/* NDF D(m) given cos(theta_m) = <n,m> */
+double og_ndf(int ndf, double alpha, double cos_m)
+{
+    if (cos_m <= 0.0) return 0.0;
+    double a2 = alpha * alpha, c2 = cos_m * cos_m;
+    if (ndf == 0) {                                /* GGX / Trowbridge-Reitz */
+        double d = c2 * (a2 - 1.0) + 1.0;
+        return a2 / (OG_PI * d * d);
+    } else {                                       /* Beckmann */
+        double tan2 = (1.0 - c2) / c2;
+        return exp(-tan2 / a2) / (OG_PI * a2 * c2 * c2);
+    }
+}
+
+/* Smith Lambda for the same NDF, direction with cos(theta) = c */
+double og_smith_lambda(int ndf, double alpha, double c)
+{
+    if (c >= 1.0) return 0.0;
+    double tan2 = (1.0 - c * c) / (c * c);
+    if (ndf == 0) return 0.5 * (-1.0 + sqrt(1.0 + alpha * alpha * tan2));
+    double a = 1.0 / (alpha * sqrt(tan2));
+    return 0.5 * (erf(a) - 1.0) + exp(-a * a) / (2.0 * a * sqrt(OG_PI));
+}
+
+static double smith_g1(int ndf, double alpha, double c)
+{
+    return 1.0 / (1.0 + og_smith_lambda(ndf, alpha, c));
+}
+
+/* Orthonormal basis around a unit normal: Duff et al., JCGT 6(1), 2017 */
+static void onb(const double n[3], double t[3], double b[3])
+{
+    double sgn = copysign(1.0, n[2]);
+    double a = -1.0 / (sgn + n[2]);
+    double bb = n[0] * n[1] * a;
+    t[0] = 1.0 + sgn * n[0] * n[0] * a; t[1] = sgn * bb; t[2] = -sgn * n[0];
+    b[0] = bb; b[1] = sgn + n[1] * n[1] * a; b[2] = -n[1];
+}
+
+static double dot3(const double a[3], const double b[3]) { return a[0]*b[0] + a[1]*b[1] + a[2]*b[2]; }
+
+static int normalize3(double a[3])
+{
+    double l = sqrt(dot3(a, a));
+    if (!(l > 0.0) || !isfinite(l)) return 0;
+    a[0] /= l; a[1] /= l; a[2] /= l;
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Footprint (Sec. 5.1): ellipse of the pixel's image under the UV     */
+/* Jacobian J = [du/dx du/dy; dv/dx dv/dy].  Axes are the singular     */
+/* vectors of J; the area is |det J|; the rotation is the major axis   */
+/* angle taken mod pi; the ratio is sigma0/sigma1.                     */
+/* ------------------------------------------------------------------ */
+int og_footprint(double dudx, double dvdx, double dudy, double dvdy,
+                 double *P, double *r, double *phi, double *sigma0)
+{
+    double a = dudx * dudx + dudy * dudy;          /* J J^T */
+    double b = dudx * dvdx + dudy * dvdy;
+    double c = dvdx * dvdx + dvdy * dvdy;
+    double det = dudx * dvdy - dudy * dvdx;
+    *P = fabs(det);
+    if (!(*P > 0.0) || !isfinite(*P)) return 0;
+    double hm = 0.5 * (a + c), hd = 0.5 * (a - c);
+    double s0sq = hm + sqrt(hd * hd + b * b);      /* larger eigenvalue */
+    double rr = s0sq / *P;                         /* sigma0/sigma1 = sigma0^2/|det| */
+    *r = rr < 1.0 ? 1.0 : rr;
+    double ph = 0.5 * atan2(2.0 * b, a - c);
+    if (ph < 0.0) ph += OG_PI;
+    *phi = ph;
+    *sigma0 = sqrt(s0sq);
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Grid nodes of the anisotropic family enclosing a sub-footprint of   */
+/* area Pk, ratio rk, orientation phi (Sec. 5.2 + Sec. 6.1).           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int n;                         /* number of tetrahedron vertices (<= 4) */
+    int l[OG_MAX_NODES], k[OG_MAX_NODES], m[OG_MAX_NODES];
+    double w[OG_MAX_NODES];
+    int level, kappa, j, tri, pivot, D;
+} og_nodes;
+
+static void upd_margin(double *mg, int *mk, double value, int kind)
+{
+    if (value < *mg) { *mg = value; *mk = kind; }
+}
+
+/* distance of x to the nearest integer in [lo, hi] */
+static double dist_int(double x, double lo, double hi)
+{
+    double k = floor(x + 0.5);
+    if (k < lo) k = lo;
+    if (k > hi) k = hi;
+    return fabs(x - k);
+}
+
+void og_grid_nodes(double Pk, double rk, double phi, int K, og_nodes *out,
+                   double *mg, int *mk)
+{
+    /* area levels: P_lo = 2^floor(log2 P), P_hi = 2^ceil(log2 P) (Eq. 13);
+     * the weight of the top level is (P - P_lo)/(P_hi - P_lo) (Eq. 10). */
+    int ex;
+    double fr = frexp(Pk, &ex);                    /* Pk = fr 2^ex, fr in [0.5,1) */
+    int l = ex - 1;
+    double ts = 2.0 * fr - 1.0;                    /* (Pk - 2^l) / 2^l in [0,1) */
+    out->level = l;
+
+    /* ratio / orientation cell and barycentric weights over its nodes */
+    int nk[3], nm[3];
+    double lam[3];
+    int nv;
+    if (K == 0) {                                   /* isotropic family only */
+        nv = 1; nk[0] = 0; nm[0] = 0; lam[0] = 1.0;
+        out->kappa = 0; out->j = 0; out->tri = 0;
+    } else {
+        double rho = log2(rk);                      /* circle k <-> r = 2^k */
+        if (rho < 0.0) rho = 0.0;
+        if (rho > K) rho = K;
+        int kap = (int)floor(rho);
+        if (kap > K - 1) kap = K - 1;
+        upd_margin(mg, mk, dist_int(rho, 1.0, K - 1.0), MK_RATIO);
+        double u = rho - kap;
+        int M = 1 << (kap + 1);                     /* orientations on ring kap over [0,pi) */
+        double q = phi / (OG_PI / M);
+        int j = (int)floor(q);
+        if (j < 0) j = 0;
+        if (j > M - 1) j = M - 1;
+        upd_margin(mg, mk, dist_int(q, 0.0, (double)M), MK_ORIENT);
+        double t = q - j;
+        int Mo = 2 * M;                              /* outer ring has twice as many */
+        /* pentagon (u,t): I0=(0,0) I1=(0,1) O0=(1,0) O1=(1,1/2) O2=(1,1) */
+        int I0k = kap, I0m = j, I1k = kap, I1m = (j + 1) % M;
+        int O0k = kap + 1, O0m = 2 * j, O1k = kap + 1, O1m = 2 * j + 1, O2k = kap + 1, O2m = (2 * j + 2) % Mo;
+        upd_margin(mg, mk, fabs(t - 0.5 * u), MK_TRIANGLE);
+        upd_margin(mg, mk, fabs(t - (1.0 - 0.5 * u)), MK_TRIANGLE);
+        if (t <= 0.5 * u) {                          /* T1 = (I0, O0, O1) */
+            out->tri = 0;
+            nk[0] = I0k; nm[0] = I0m; lam[0] = 1.0 - u;
+            nk[1] = O0k; nm[1] = O0m; lam[1] = u - 2.0 * t;
+            nk[2] = O1k; nm[2] = O1m; lam[2] = 2.0 * t;
+        } else if (t >= 1.0 - 0.5 * u) {             /* T3 = (I1, O2, O1) */
+            out->tri = 2;
+            nk[0] = I1k; nm[0] = I1m; lam[0] = 1.0 - u;
+            nk[1] = O2k; nm[1] = O2m; lam[1] = u - 2.0 * (1.0 - t);
+            nk[2] = O1k; nm[2] = O1m; lam[2] = 2.0 * (1.0 - t);
+        } else {                                     /* T2 = (I0, I1, O1) */
+            out->tri = 1;
+            nk[0] = I0k; nm[0] = I0m; lam[0] = 1.0 - t - 0.5 * u;
+            nk[1] = I1k; nm[1] = I1m; lam[1] = t - 0.5 * u;
+            nk[2] = O1k; nm[2] = O1m; lam[2] = u;
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (lam[a] < 0.0) lam[a] = 0.0;
+            if (nk[a] == 0) nm[a] = 0;               /* every ring-0 node is the isotropic grid */
+        }
+        nv = 3;
+        out->kappa = kap; out->j = j;
+    }
+
+    /* merge coincident nodes, then sort by global key (k, m) ascending */
+    int dk[3], dm[3];
+    double dl[3];
+    int D = 0;
+    for (int a = 0; a < nv; ++a) {
+        int found = -1;
+        for (int b = 0; b < D; ++b)
+            if (dk[b] == nk[a] && dm[b] == nm[a]) found = b;
+        if (found >= 0) dl[found] += lam[a];
+        else { dk[D] = nk[a]; dm[D] = nm[a]; dl[D] = lam[a]; ++D; }
+    }
+    for (int a = 1; a < D; ++a)                      /* insertion sort */
+        for (int b = a; b > 0 && (dk[b - 1] * 64 + dm[b - 1]) > (dk[b] * 64 + dm[b]); --b) {
+            int tk = dk[b]; dk[b] = dk[b - 1]; dk[b - 1] = tk;
+            int tm = dm[b]; dm[b] = dm[b - 1]; dm[b - 1] = tm;
+            double tl = dl[b]; dl[b] = dl[b - 1]; dl[b - 1] = tl;
+        }
+
+    /* prism (triangle x scale) -> tetrahedron: move the top-level mass ts
+     * onto the nodes from the highest key down.  The three tetrahedra this
+     * selects tile the prism and agree on shared faces (split by key order). */
+    double top[3] = {0, 0, 0};
+    double rem = ts;
+    int pivot = 0;
+    for (int a = D - 1; a >= 0; --a) {
+        if (a > 0) upd_margin(mg, mk, fabs(rem - dl[a]), MK_TETRA);
+        if (rem <= dl[a] || a == 0) {
+            top[a] = rem < dl[a] ? rem : dl[a];
+            pivot = a;
+            break;
+        }
+        top[a] = dl[a];
+        rem -= dl[a];
+    }
+    int n = 0;
+    for (int a = 0; a <= pivot; ++a) {               /* bottom level l */
+        out->l[n] = l; out->k[n] = dk[a]; out->m[n] = dm[a];
+        out->w[n] = dl[a] - top[a];
+        ++n;
+    }
+    for (int a = pivot; a < D; ++a) {                /* top level l+1 */
+        out->l[n] = l + 1; out->k[n] = dk[a]; out->m[n] = dm[a];
+        out->w[n] = top[a];
+        ++n;
+    }
+    out->n = n;
+    out->pivot = pivot;
+    out->D = D;
+}
+
+/* ------------------------------------------------------------------ */
+/* Simplex lattice of one grid node (Sec. 5.1 Eq. 12 + Sec. 6.2):      */
+/* rotate the point by -phi_g, scale to cells of area A = 2^l and      */
+/* aspect r = 2^k, skew to the triangular lattice and locate the       */
+/* triangle.  Returns three lattice vertices and barycentric weights.  */
+/* ------------------------------------------------------------------ */
+void og_simplex(double cx, double cy, int l, int k, int m,
+                int vi[3], int vj[3], double beta[3], double *mg, int *mk)
+{
+    double phig = (k == 0) ? 0.0 : (double)m * OG_PI / (double)(1 << (k + 1));
+    double cph = cos(phig), sph = sin(phig);
+    double qx = cph * cx + sph * cy;
+    double qy = -sph * cx + cph * cy;
+    double wx = sqrt(ldexp(1.0, l + k));           /* cell side along the major axis */
+    double wy = sqrt(ldexp(1.0, l - k));           /* cell side along the minor axis */
+    double x = qx / wx, y = qy / wy;
+    double Lx = x + 0.5 * y, Ly = y;               /* skew: triangular lattice -> integer lattice */
+    double fi = floor(Lx), fj = floor(Ly);
+    double f = Lx - fi, g = Ly - fj;
+    int i = (int)fi, j = (int)fj;
+    upd_margin(mg, mk, fabs(Lx - floor(Lx + 0.5)), MK_LATTICE);
+    upd_margin(mg, mk, fabs(Ly - floor(Ly + 0.5)), MK_LATTICE);
+    upd_margin(mg, mk, fabs(f - g), MK_LATTICE);
+    if (f >= g) {
+        vi[0] = i; vj[0] = j; vi[1] = i + 1; vj[1] = j; vi[2] = i + 1; vj[2] = j + 1;
+        beta[0] = 1.0 - f; beta[1] = f - g; beta[2] = g;
+    } else {
+        vi[0] = i; vj[0] = j; vi[1] = i; vj[1] = j + 1; vi[2] = i + 1; vj[2] = j + 1;
+        beta[0] = 1.0 - g; beta[1] = g - f; beta[2] = f;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Gated Gaussian binomial (Sec. 6.3, Eqs. 16-18).  Success of the     */
+/* gate is theta0 < P>=1 (the paper's trials succeed when X < p).      */
+/* rounding 0: c = max(1, floor(1 + mu + sigma Phi^-1(theta1)));       */
+/* rounding 1 (relaxed): c = max(1, 1 + mu + sigma Phi^-1(theta1)).    */
+/* ------------------------------------------------------------------ */
+double og_gated_count(double n, double p, double theta0, double theta1, int rounding)
+{
+    double pg;
+    if (!(n > 0.0) || !(p > 0.0)) pg = 0.0;
+    else if (p >= 1.0) pg = 1.0;
+    else pg = -expm1(n * log1p(-p));
+    if (!(theta0 < pg)) return 0.0;
+    double mm = n - 1.0 > 0.0 ? n - 1.0 : 0.0;
+    double mu = mm * p, sigma = sqrt(mm * p * (1.0 - p));
+    double x = 1.0 + mu + sigma * og_ndtri(theta1);
+    if (rounding == 0) x = floor(x);
+    return x > 1.0 ? x : 1.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* One pixel.                                                          */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double u, v, dudx, dvdx, dudy, dvdy, n[3], wi[3];
+    int mat;
+    double alpha, log10N;          /* effective values (material or per-pixel) */
+} og_px_in;
+
+typedef struct {
+    double alpha_shift;            /* added to the pixel's alpha (gradients) */
+    double lnN_shift;              /* added to ln N */
+    const double *dirs;            /* [n_light][3] raw light directions (perturbable) */
+} og_perturb;
+
+typedef struct {
+    double rgb[3];
+    uint32_t flags, cell, key_sum, akey_sum, theta_sum, count_sum, n_open, n_gate, n_live;
+    int32_t n_probe, level;
+    double margin;
+    int32_t margin_kind;
+    double b[64];                  /* raw distributed count per light (first 64 lights) */
+} og_px_out;
+
+static void shade_pixel(const og_px_in *in, const og_material *mat, const og_light *lights,
+                        int n_light, const og_params *prm, const og_perturb *pt,
+                        og_tape *T, og_px_out *o)
+{
+    memset(o, 0, sizeof(*o));
+    o->margin = INFINITY;
+    o->margin_kind = MK_NONE;
+    double *mg = &o->margin;
+    int *mk = &o->margin_kind;
+
+    const int K = prm->k_max;
+    const double alpha = in->alpha + (pt ? pt->alpha_shift : 0.0);
+    const double lnN = in->log10N * log(10.0) + (pt ? pt->lnN_shift : 0.0);
+    const double N = exp(lnN);                      /* flakes per unit UV area */
+    const double R = mat->R;
+
+    double nrm[3] = {in->n[0], in->n[1], in->n[2]};
+    double wi[3] = {in->wi[0], in->wi[1], in->wi[2]};
+    if (!normalize3(nrm) || !normalize3(wi)) { o->flags |= OGF_BAD_INPUT; return; }
+
+    double P, r, phi, sigma0;
+    if (!og_footprint(in->dudx, in->dvdx, in->dudy, in->dvdy, &P, &r, &phi, &sigma0)) {
+        o->flags |= OGF_BAD_INPUT;
+        return;
+    }
+    double cos_i = dot3(nrm, wi);
+    upd_margin(mg, mk, fabs(cos_i), MK_VIEW);
+    if (!(cos_i > 0.0)) { o->flags |= OGF_BACKFACING; return; }
+
+    /* footprints longer than the family's largest ratio are distributed
+     * over n_pr equal sub-footprints along the major axis (Sec. 4.2) */
+    double qn = r / ldexp(1.0, K);
+    int n_pr = (int)ceil(qn);
+    if (n_pr < 1) n_pr = 1;
+    if (n_pr > prm->n_probe_max) n_pr = prm->n_probe_max;
+    upd_margin(mg, mk, dist_int(qn, 1.0, (double)prm->n_probe_max) / (qn > 1.0 ? qn : 1.0), MK_NPROBE);
+    double Pk = P / n_pr;
+    double rk = r / n_pr;
+    if (rk > ldexp(1.0, K)) { rk = ldexp(1.0, K); o->flags |= OGF_CLAMP_RATIO; }
+    o->n_probe = n_pr;
+
+    og_nodes nodes;
+    og_grid_nodes(Pk, rk, phi, K, &nodes, mg, mk);
+    o->level = nodes.level;
+    o->cell = (uint32_t)nodes.kappa | ((uint32_t)nodes.j << 3) | ((uint32_t)nodes.tri << 9)
+              | ((uint32_t)nodes.pivot << 11) | ((uint32_t)nodes.D << 13) | ((uint32_t)nodes.n << 15);
+
+    /* per-light quantities that do not depend on the probe */
+    double tt[3], bb[3];
+    onb(nrm, tt, bb);
+    const double mr = mat->micro_roughness;
+    const double Dn = 1.0 / (OG_PI * alpha * alpha);  /* D(n) for GGX and Beckmann */
+    const uint32_t s0 = og_hash_step(0x243F6A88u, mat->seed);
+
+    int lv[64], ai[64], aj[64];
+    double vw[64][4], pl[64], Fl[64], Gl[64];
+    uint32_t akey[64][4][2];
+    int NL = n_light < 64 ? n_light : 64;
+    for (int li = 0; li < NL; ++li) {
+        double wo[3];
+        if (pt && pt->dirs) { wo[0] = pt->dirs[3*li]; wo[1] = pt->dirs[3*li+1]; wo[2] = pt->dirs[3*li+2]; }
+        else { wo[0] = lights[li].dir[0]; wo[1] = lights[li].dir[1]; wo[2] = lights[li].dir[2]; }
+        int ok = normalize3(wo);
+        double cos_o = ok ? dot3(nrm, wo) : -1.0;
+        double h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+        ok = ok && (cos_o > 0.0) && normalize3(h);
+        if (ok) upd_margin(mg, mk, fabs(cos_o), MK_LIGHT);
+        lv[li] = tape_dec(T, ok);
+        if (!lv[li]) continue;
+        double cos_h = dot3(nrm, h);
+        /* Eq. 4: p = R D(h)/D(n), clamped to a probability */
+        double praw = R * og_ndf(mat->ndf, alpha, cos_h) / Dn;
+        int pc = tape_dec(T, praw > 1.0);
+        if (pc) o->flags |= OGF_CLAMP_P;
+        pl[li] = pc ? 1.0 : praw;
+        /* Eq. 14: bilinear over the 4 nearest texels of the angular grid,
+         * indexed by the orthographic projection of h, cell size mr */
+        double ax = dot3(h, tt) / mr - 0.5, ay = dot3(h, bb) / mr - 0.5;
+        upd_margin(mg, mk, fabs(ax - floor(ax + 0.5)), MK_ANGULAR);
+        upd_margin(mg, mk, fabs(ay - floor(ay + 0.5)), MK_ANGULAR);
+        ai[li] = tape_dec(T, (int32_t)floor(ax));
+        aj[li] = tape_dec(T, (int32_t)floor(ay));
+        double fx = ax - ai[li], fy = ay - aj[li];
+        vw[li][0] = (1.0 - fx) * (1.0 - fy);
+        vw[li][1] = fx * (1.0 - fy);
+        vw[li][2] = (1.0 - fx) * fy;
+        vw[li][3] = fx * fy;
+        for (int a = 0; a < 4; ++a)
+            for (int s = 0; s < 2; ++s) {
+                akey[li][a][s] = og_hash_step(0x13198A2Eu, angular_word(ai[li] + (a & 1), aj[li] + (a >> 1), s));
+            }
+        for (int a = 0; a < 4; ++a) o->akey_sum += akey[li][a][0];
+        /* Schlick Fresnel and separable Smith masking (Eq. 2) */
+        double ch = dot3(wi, h);
+        double F0 = mat->F0;
+        double om = 1.0 - ch;
+        Fl[li] = F0 + (1.0 - F0) * om * om * om * om * om;
+        Gl[li] = smith_g1(mat->ndf, alpha, cos_i) * smith_g1(mat->ndf, alpha, cos_o);
+    }
+
+    double bsum[64];
+    for (int li = 0; li < NL; ++li) bsum[li] = 0.0;
+
+    for (int kp = 0; kp < n_pr; ++kp) {
+        /* probe centre: uniform along the major axis over length sigma0 */
+        double off = ((kp + 0.5) / n_pr - 0.5) * sigma0;
+        double cx = in->u + off * cos(phi), cy = in->v + off * sin(phi);
+        int vi[OG_MAX_NODES][3], vj[OG_MAX_NODES][3];
+        double beta[OG_MAX_NODES][3];
+        uint32_t pre[OG_MAX_NODES][3];
+        for (int g = 0; g < nodes.n; ++g) {
+            og_simplex(cx, cy, nodes.l[g], nodes.k[g], nodes.m[g], vi[g], vj[g], beta[g], mg, mk);
+            uint32_t base = og_hash_step(s0, node_word(nodes.l[g], nodes.k[g], nodes.m[g]));
+            for (int e = 0; e < 3; ++e) {
+                pre[g][e] = og_hash_step(og_hash_step(base, (uint32_t)vi[g][e]), (uint32_t)vj[g][e]);
+                o->key_sum += pre[g][e];
+            }
+        }
+        for (int li = 0; li < NL; ++li) {
+            if (!lv[li]) continue;
+            double p = pl[li];
+            for (int g = 0; g < nodes.n; ++g) {
+                /* Eq. 10: node g receives w_g N A_g trials */
+                double ng = nodes.w[g] * N * ldexp(1.0, nodes.l[g]);
+                double pg;
+                if (!(ng > 0.0) || !(p > 0.0)) pg = 0.0;
+                else if (p >= 1.0) pg = 1.0;
+                else pg = -expm1(ng * log1p(-p));    /* Eq. 16 */
+                double mm = ng - 1.0 > 0.0 ? ng - 1.0 : 0.0;
+                double mu = mm * p;                   /* Eq. 17 */
+                double sg = sqrt(mm * p * (1.0 - p));
+                int live = pg > 0x1p-24;
+                for (int e = 0; e < 3; ++e)
+                    for (int a = 0; a < 4; ++a) {
+                        uint32_t h0 = og_hash_step(pre[g][e], akey[li][a][0]);
+                        double th0 = uniform_of(h0);
+                        o->theta_sum += h0;
+                        o->n_gate++;
+                        if (live) {
+                            o->n_live++;
+                            upd_margin(mg, mk, fabs(th0 - pg) / (pg > 0x1p-24 ? pg : 0x1p-24), MK_GATE);
+                        }
+                        int open = tape_dec(T, th0 < pg);
+                        double c = 0.0;
+                        if (open) {                   /* Eq. 18 with the gate read as theta0 < P>=1 */
+                            o->n_open++;
+                            uint32_t h1 = og_hash_step(pre[g][e], akey[li][a][1]);
+                            double x = 1.0 + mu + sg * og_ndtri(uniform_of(h1));
+                            if (x >= 1.5) {
+                                double k = floor(x + 0.5);
+                                upd_margin(mg, mk, fabs(x - k) / (x > 1.0 ? x : 1.0), MK_COUNT);
+                            }
+                            if (prm->rounding == 0) {
+                                double xf = floor(x);
+                                c = xf > 1.0 ? xf : 1.0;
+                                o->count_sum += (uint32_t)c;
+                            } else {
+                                int br = tape_dec(T, x >= 1.0);
+                                c = br ? x : 1.0;
+                            }
+                        }
+                        bsum[li] += beta[g][e] * vw[li][a] * c;
+                    }
+            }
+        }
+    }
+
+    /* Eqs. 1-4: D_P = D(n) b / (R N P); L = sum_l E_l F G D_P / (4 <wi,n>) */
+    for (int li = 0; li < NL; ++li) {
+        o->b[li] = bsum[li];
+        if (!lv[li]) continue;
+        double DP = Dn * bsum[li] / (R * N * P);
+        double f = Fl[li] * Gl[li] * DP / (4.0 * cos_i);
+        for (int ch = 0; ch < 3; ++ch) o->rgb[ch] += (double)lights[li].radiance[ch] * f;
+    }
+    o->flags |= OGF_SHADED;
+}
+
+static int load_pixel(const og_gbuffer *gb, const og_material *mats, int n_mat, int64_t idx,
+                      og_px_in *in, uint32_t *flags)
+{
+    int mat = gb->material_id ? gb->material_id[idx] : 0;
+    if (mat < 0) { *flags = OGF_SKIPPED; return 0; }
+    if (mat >= n_mat) { *flags = OGF_BAD_MAT; return 0; }
+    in->mat = mat;
+    in->u = gb->u[idx]; in->v = gb->v[idx];
+    in->dudx = gb->dudx[idx]; in->dvdx = gb->dvdx[idx];
+    in->dudy = gb->dudy[idx]; in->dvdy = gb->dvdy[idx];
+    in->n[0] = gb->nx[idx]; in->n[1] = gb->ny[idx]; in->n[2] = gb->nz[idx];
+    in->wi[0] = gb->wx[idx]; in->wi[1] = gb->wy[idx]; in->wi[2] = gb->wz[idx];
+    in->alpha = gb->alpha_px ? (double)gb->alpha_px[idx] : (double)mats[mat].alpha;
+    in->log10N = gb->log10_density_px ? (double)gb->log10_density_px[idx] : (double)mats[mat].log10_density;
+    double vals[14] = {in->u, in->v, in->dudx, in->dvdx, in->dudy, in->dvdy, in->n[0], in->n[1],
+                       in->n[2], in->wi[0], in->wi[1], in->wi[2], in->alpha, in->log10N};
+    for (int i = 0; i < 14; ++i)
+        if (!isfinite(vals[i])) { *flags = OGF_BAD_INPUT; return 0; }
+    if (!(in->alpha > 0.0)) { *flags = OGF_BAD_INPUT; return 0; }
+    return 1;
+}
+
+static void set_threads(int n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+}
+
+/* Forward shading of rows [row0, row1).  out_rgb: [3][height*stride]. */
+int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_light *lights,
+             int n_light, const og_params *prm, double *out_rgb, og_debug *dbg,
+             int row0, int row1, int n_threads)
+{
+    if (!gb || !mats || n_mat <= 0 || n_light < 0 || n_light > 64 || !prm || !out_rgb) return -1;
+    if (prm->k_max < 0 || prm->k_max > 4 || prm->n_probe_max < 1) return -1;
+    if (row0 < 0) row0 = 0;
+    if (row1 > gb->height) row1 = gb->height;
+    const int64_t npx = (int64_t)gb->height * gb->stride;
+    set_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = row0; y < row1; ++y) {
+        for (int x = 0; x < gb->width; ++x) {
+            int64_t idx = (int64_t)y * gb->stride + x;
+            og_px_in in;
+            og_px_out o;
+            uint32_t lflags = 0;
+            if (load_pixel(gb, mats, n_mat, idx, &in, &lflags)) {
+                shade_pixel(&in, &mats[in.mat], lights, n_light, prm, NULL, NULL, &o);
+            } else {
+                memset(&o, 0, sizeof(o));
+                o.flags = lflags;
+                o.margin = INFINITY;
+            }
+            for (int c = 0; c < 3; ++c) out_rgb[c * npx + idx] = o.rgb[c];
+            if (dbg) {
+                if (dbg->flags) dbg->flags[idx] = o.flags;
+                if (dbg->n_probe) dbg->n_probe[idx] = o.n_probe;
+                if (dbg->level) dbg->level[idx] = o.level;
+                if (dbg->cell) dbg->cell[idx] = o.cell;
+                if (dbg->key_sum) dbg->key_sum[idx] = o.key_sum;
+                if (dbg->akey_sum) dbg->akey_sum[idx] = o.akey_sum;
+                if (dbg->theta_sum) dbg->theta_sum[idx] = o.theta_sum;
+                if (dbg->count_sum) dbg->count_sum[idx] = o.count_sum;
+                if (dbg->n_open) dbg->n_open[idx] = o.n_open;
+                if (dbg->n_gate) dbg->n_gate[idx] = o.n_gate;
+                if (dbg->n_live) dbg->n_live[idx] = o.n_live;
+                if (dbg->margin) dbg->margin[idx] = o.margin;
+                if (dbg->margin_kind) dbg->margin_kind[idx] = o.margin_kind;
+                if (dbg->b_light)
+                    for (int li = 0; li < n_light; ++li) dbg->b_light[li * npx + idx] = o.b[li];
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Gradients of  sum_px sum_rgb g_rgb(px) L_rgb(px)  with respect to    */
+/* each material's alpha and ln N and each light's raw direction, by   */
+/* central differences of the relaxed forward (rounding 1).            */
+/* frozen = 1: every light-dependent branch (light validity, p clamp,  */
+/*   angular cell, gates, the max(1,x) clamp) is recorded at the base  */
+/*   point and replayed at the shifted points: the derivative of the   */
+/*   relaxed count with discrete branches held fixed.  The geometric   */
+/*   decisions (probes, levels, cells, lattice) do not depend on these */
+/*   parameters at all.                                                */
+/* frozen = 0: plain central differences; a pixel whose branches flip  */
+/*   between the base and a shifted point is left out and marked in    */
+/*   flip[] (nullable).                                                */
+/* grad_out: [3][height*stride] (double).  Outputs are overwritten.    */
+/* The pixel sums are reduced row by row in a fixed order.             */
+/* ------------------------------------------------------------------ */
+static int same_tape(const og_tape *a, const og_tape *b)
+{
+    return a->len == b->len && memcmp(a->buf, b->buf, a->len * sizeof(int32_t)) == 0;
+}
+
+int og_grad(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_light *lights,
+            int n_light, const og_params *prm_in, const double *grad_out, double step,
+            int frozen, double *g_alpha, double *g_lnN, double *g_dir, uint8_t *flip,
+            int n_threads)
+{
+    if (!gb || !mats || n_mat <= 0 || n_light <= 0 || n_light > 64 || !grad_out || !(step > 0.0)) return -1;
+    og_params prm = *prm_in;
+    prm.rounding = 1;
+    const int64_t npx = (int64_t)gb->height * gb->stride;
+    const int np = 2 * n_mat + 3 * n_light;
+    double *rows = (double *)calloc((size_t)np * (size_t)gb->height, sizeof(double));
+    double *base_dirs = (double *)malloc(sizeof(double) * 3 * n_light);
+    if (!rows || !base_dirs) { free(rows); free(base_dirs); return -2; }
+    for (int li = 0; li < n_light; ++li)
+        for (int c = 0; c < 3; ++c) base_dirs[3 * li + c] = lights[li].dir[c];
+    set_threads(n_threads);
+#pragma omp parallel
+    {
+        const int npp = 2 + 3 * n_light;           /* parameters seen by one pixel */
+        double *dpx = (double *)malloc(sizeof(double) * npp);
+        double *dirs_p = (double *)malloc(sizeof(double) * 3 * n_light);
+        double *dirs_m = (double *)malloc(sizeof(double) * 3 * n_light);
+        og_tape tb = {0}, tp = {0}, tm = {0};
+#pragma omp for schedule(dynamic, 1)
+        for (int y = 0; y < gb->height; ++y) {
+            double *racc = rows + (size_t)y * np;
+            for (int x = 0; x < gb->width; ++x) {
+                int64_t idx = (int64_t)y * gb->stride + x;
+                og_px_in in;
+                uint32_t lflags = 0;
+                if (flip) flip[idx] = 0;
+                if (!load_pixel(gb, mats, n_mat, idx, &in, &lflags)) continue;
+                const double go[3] = {grad_out[idx], grad_out[npx + idx], grad_out[2 * npx + idx]};
+                og_px_out op, om;
+                og_perturb pb = {0.0, 0.0, base_dirs};
+                tb.len = 0; tb.pos = 0; tb.mode = 1;
+                shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pb, &tb, &op);
+                if (!(op.flags & OGF_SHADED)) continue;
+                int flipped = 0;
+                for (int pi = 0; pi < npp; ++pi) {
+                    memcpy(dirs_p, base_dirs, sizeof(double) * 3 * n_light);
+                    memcpy(dirs_m, base_dirs, sizeof(double) * 3 * n_light);
+                    og_perturb pp = {0.0, 0.0, dirs_p}, pm = {0.0, 0.0, dirs_m};
+                    double hs;
+                    if (pi == 0) { hs = step * in.alpha; pp.alpha_shift = hs; pm.alpha_shift = -hs; }
+                    else if (pi == 1) { hs = step; pp.lnN_shift = hs; pm.lnN_shift = -hs; }
+                    else { hs = step; dirs_p[pi - 2] += hs; dirs_m[pi - 2] -= hs; }
+                    if (frozen) {
+                        tb.mode = 2; tb.pos = 0;
+                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pp, &tb, &op);
+                        tb.pos = 0;
+                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pm, &tb, &om);
+                    } else {
+                        tp.len = 0; tp.pos = 0; tp.mode = 1;
+                        tm.len = 0; tm.pos = 0; tm.mode = 1;
+                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pp, &tp, &op);
+                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pm, &tm, &om);
+                        if (!same_tape(&tp, &tb) || !same_tape(&tm, &tb)) flipped = 1;
+                    }
+                    double d = 0.0;
+                    for (int c = 0; c < 3; ++c) d += go[c] * (op.rgb[c] - om.rgb[c]) / (2.0 * hs);
+                    dpx[pi] = d;
+                }
+                if (flipped) { if (flip) flip[idx] = 1; continue; }
+                racc[2 * in.mat] += dpx[0];
+                racc[2 * in.mat + 1] += dpx[1];
+                for (int i = 0; i < 3 * n_light; ++i) racc[2 * n_mat + i] += dpx[2 + i];
+            }
+        }
+        free(dpx); free(dirs_p); free(dirs_m);
+        free(tb.buf); free(tp.buf); free(tm.buf);
+    }
+    double *acc = (double *)calloc((size_t)np, sizeof(double));
+    for (int y = 0; y < gb->height; ++y)
+        for (int i = 0; i < np; ++i) acc[i] += rows[(size_t)y * np + i];
+    for (int m = 0; m < n_mat; ++m) { g_alpha[m] = acc[2 * m]; g_lnN[m] = acc[2 * m + 1]; }
+    for (int i = 0; i < 3 * n_light; ++i) g_dir[i] = acc[2 * n_mat + i];
+    free(acc); free(rows); free(base_dirs);
+    return 0;
+}

@@ -1,0 +1,302 @@
+"""Pins of the FP64 oracle to the paper and to mathematics (CPU only).
+
+Each test checks the oracle against something other than itself: a library
+routine, a closed form, an invariant, quadrature, or brute force.  A plausible
+mistake in the oracle (a dropped term, a wrong sign, index or operand order)
+breaks at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import ndtri as sp_ndtri
+
+import oracle
+from oracle import bruteforce as bf
+
+
+# ---------------------------------------------------------------------------
+# Footprint (Sec. 5.1): axes of the pixel ellipse vs numpy's SVD
+# ---------------------------------------------------------------------------
+def test_footprint_matches_svd():
+    rng = np.random.default_rng(1)
+    for _ in range(2000):
+        J = rng.normal(size=(2, 2)) * 10.0 ** rng.uniform(-6, 0)
+        res = oracle.footprint(J[0, 0], J[1, 0], J[0, 1], J[1, 1])
+        U, S, Vt = np.linalg.svd(J)
+        P, r, phi, s0 = res
+        assert P == pytest.approx(abs(np.linalg.det(J)), rel=1e-10)
+        assert s0 == pytest.approx(S[0], rel=1e-10)
+        assert r == pytest.approx(max(S[0] / S[1], 1.0), rel=1e-8)
+        e0 = U[:, 0]
+        ref = math.atan2(e0[1], e0[0]) % math.pi
+        d = abs(phi - ref)
+        d = min(d, math.pi - d)
+        cond = (S[0] + S[1]) / max(S[0] - S[1], 1e-300)
+        assert d < 1e-9 * cond + 1e-12
+        assert 0.0 <= phi < math.pi
+
+
+def test_footprint_special_cases():
+    # isotropic, axis aligned: ratio 1, orientation 0
+    P, r, phi, s0 = oracle.footprint(0.5, 0.0, 0.0, 0.5)
+    assert (P, r, phi, s0) == (0.25, 1.0, 0.0, 0.5)
+    # stretched along v: major axis at pi/2
+    P, r, phi, s0 = oracle.footprint(0.25, 0.0, 0.0, 1.0)
+    assert P == 0.25 and r == 4.0 and phi == pytest.approx(math.pi / 2)
+    assert oracle.footprint(1.0, 2.0, 2.0, 4.0) is None     # det J = 0
+
+
+# ---------------------------------------------------------------------------
+# Inverse normal CDF vs scipy; the 2^23 uniforms used by the method
+# ---------------------------------------------------------------------------
+def test_ndtri_matches_scipy():
+    ks = np.unique(np.concatenate([np.arange(0, 64), 2**23 - 1 - np.arange(0, 64),
+                                   np.random.default_rng(2).integers(0, 2**23, 4000)]))
+    for k in ks:
+        q = (2.0 * k + 1.0) * 2.0**-24
+        z, ref = oracle.ndtri(q), sp_ndtri(q)
+        assert abs(z - ref) <= 2e-14 * max(1.0, abs(ref)), (q, z, ref)
+
+
+# ---------------------------------------------------------------------------
+# Microfacet NDFs (Eq. 4): projected-area normalisation by quadrature;
+# Smith Lambda: int D(m) <w,m>+ dm = (1 + Lambda(w)) <w,n>
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("alpha", [0.05, 0.3, 1.0])
+def test_ndf_normalisation(kind, alpha):
+    # substitution t = tan(theta) spreads the nodes over the lobe
+    from scipy.integrate import quad
+    f = lambda th: oracle.ndf(kind, alpha, math.cos(th)) * math.cos(th) * math.sin(th) * 2 * math.pi
+    val = quad(f, 0, math.pi / 2, points=[math.atan(alpha)], limit=400, epsabs=1e-13, epsrel=1e-11)[0]
+    assert val == pytest.approx(1.0, rel=2e-7)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("alpha", [0.1, 0.4, 0.9])
+@pytest.mark.parametrize("theta_deg", [20.0, 60.0, 80.0])
+def test_smith_lambda_identity(kind, alpha, theta_deg):
+    th = math.radians(theta_deg)
+    w = np.array([math.sin(th), 0.0, math.cos(th)])
+    nt, npp = 700, 720
+    # Gauss-Legendre in theta_m (in tan space) and midpoint in phi_m
+    x, wx = np.polynomial.legendre.leggauss(nt)
+    thm = 0.5 * (x + 1) * (math.pi / 2)
+    wth = wx * (math.pi / 4)
+    ph = (np.arange(npp) + 0.5) * (2 * math.pi / npp)
+    TH, PH = np.meshgrid(thm, ph, indexing="ij")
+    M = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], -1)
+    D = np.vectorize(lambda c: oracle.ndf(kind, alpha, c))(np.cos(TH))
+    proj = np.maximum(M @ w, 0.0)
+    integ = np.sum(D * proj * np.sin(TH) * wth[:, None]) * (2 * math.pi / npp)
+    lam = oracle.smith_lambda(kind, alpha, math.cos(th))
+    assert integ == pytest.approx((1.0 + lam) * math.cos(th), rel=5e-4)
+
+
+# ---------------------------------------------------------------------------
+# Gated binomial (Eqs. 16-18)
+# ---------------------------------------------------------------------------
+def _grid_thetas(n):
+    k = (np.arange(n) * (2**23 // n)) + (2**23 // n) // 2
+    return (2.0 * k + 1.0) * 2.0**-24
+
+
+def test_gate_probability_is_one_minus_q_pow_n():
+    th = _grid_thetas(1 << 16)
+    for n, p in [(1.0, 0.3), (2.0, 0.1), (7.5, 0.02), (40.0, 0.05), (0.4, 0.5)]:
+        opened = np.array([oracle.gated_count(n, p, t0, 0.5) > 0 for t0 in th])
+        assert opened.mean() == pytest.approx(1.0 - (1.0 - p) ** n, abs=2.0 / th.size)
+
+
+def test_one_trial_is_bernoulli():
+    th = _grid_thetas(1 << 14)
+    for p in (0.05, 0.5, 0.9):
+        c = np.array([[oracle.gated_count(1.0, p, t0, t1) for t1 in th[::512]] for t0 in th[::64]])
+        assert set(np.unique(c)) <= {0.0, 1.0}
+        assert c.mean() == pytest.approx(p, abs=2.0 / 256)
+
+
+@pytest.mark.parametrize("n,p", [(2.0, 0.1), (6.0, 0.3), (30.0, 0.2), (200.0, 0.05), (3.3, 0.7)])
+def test_gated_pmf_closed_form(n, p):
+    """Realised histogram over a dense theta1 grid (gate forced open) against the
+    closed form through Phi."""
+    th1 = _grid_thetas(1 << 16)
+    c = np.array([oracle.gated_count(n, p, 0.0, t1) for t1 in th1]).astype(int)
+    pmf = bf.gated_pmf(n, p)
+    pg = pmf[1:].sum()
+    hist = np.bincount(c, minlength=pmf.size)[: pmf.size] / c.size
+    # conditional on an open gate
+    assert np.all(c >= 1)
+    assert np.max(np.abs(hist[1:] - pmf[1:] / pg)) < 3.0 / th1.size + 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Hash: uniformity and independence of the per-texel uniforms
+# ---------------------------------------------------------------------------
+def test_hash_avalanche():
+    rng = np.random.default_rng(3)
+    flips = []
+    for _ in range(300):
+        h, w = int(rng.integers(0, 2**32)), int(rng.integers(0, 2**32))
+        base = oracle.hash_step(h, w)
+        for b in range(32):
+            flips.append(bin(base ^ oracle.hash_step(h, w ^ (1 << b))).count("1"))
+            flips.append(bin(base ^ oracle.hash_step(h ^ (1 << b), w)).count("1"))
+    assert np.mean(flips) == pytest.approx(16.0, abs=0.15)
+
+
+def test_hash_uniform_and_independent_on_texel_keys():
+    # neighbouring texels of one grid and neighbouring angular cells
+    vals = np.array([oracle.hash_step(oracle.hash_step(oracle.hash_step(0x1234, i), j), a)
+                     for i in range(64) for j in range(64) for a in range(4)], dtype=np.uint64)
+    u = ((vals >> 9) * 2 + 1) / 2.0**24
+    hist = np.bincount((u * 64).astype(int), minlength=64)
+    chi2 = np.sum((hist - u.size / 64) ** 2 / (u.size / 64))
+    assert chi2 < 120.0                       # 63 dof, p ~ 1e-5 cut
+    g = u.reshape(64, 64, 4)
+    for a, b in [(g[1:, :, 0], g[:-1, :, 0]), (g[:, 1:, 0], g[:, :-1, 0]), (g[..., 1], g[..., 0])]:
+        assert abs(np.corrcoef(a.ravel(), b.ravel())[0, 1]) < 0.05
+
+
+# ---------------------------------------------------------------------------
+# Grid family: distributed weights (Eq. 10, Sec. 5.2, Sec. 6.1)
+# ---------------------------------------------------------------------------
+def _cell_uv(rk, phi, K):
+    rho = min(max(math.log2(rk), 0.0), K)
+    kap = min(int(math.floor(rho)), K - 1)
+    M = 2 ** (kap + 1)
+    q = phi / (math.pi / M)
+    j = min(int(math.floor(q)), M - 1)
+    return kap, j, rho - kap, q - j, M
+
+
+def test_area_conservation_and_weights():
+    rng = np.random.default_rng(4)
+    for _ in range(4000):
+        Pk = 10.0 ** rng.uniform(-12, 1)
+        rk = 2.0 ** rng.uniform(0, 4)
+        phi = rng.uniform(0, math.pi)
+        nodes, cell, _ = oracle.grid_nodes(Pk, rk, phi, 4)
+        w = np.array([n[3] for n in nodes])
+        assert len(nodes) <= 4 and np.all(w >= 0)
+        assert w.sum() == pytest.approx(1.0, abs=1e-13)
+        area = sum(n[3] * 2.0 ** n[0] for n in nodes)
+        assert area == pytest.approx(Pk, rel=1e-13)
+        l = cell["level"]
+        assert 2.0 ** l <= Pk < 2.0 ** (l + 1)
+        assert {n[0] for n in nodes} <= {l, l + 1}
+
+
+def test_tetra_barycentric_reconstruction():
+    """For cells away from ring 0 the weights are barycentric coordinates of the
+    point (u, t, s) in the cell's (ratio, orientation, scale) coordinates."""
+    rng = np.random.default_rng(5)
+    for _ in range(3000):
+        Pk = 10.0 ** rng.uniform(-9, -3)
+        rk = 2.0 ** rng.uniform(1.0, 4.0)
+        phi = rng.uniform(0, math.pi)
+        kap, j, u, t, M = _cell_uv(rk, phi, 4)
+        nodes, cell, _ = oracle.grid_nodes(Pk, rk, phi, 4)
+        l = cell["level"]
+        ts = Pk / 2.0**l - 1.0
+        pos = np.zeros(3)
+        for (nl, nk, nm, w) in nodes:
+            if nk == kap:
+                tt = (nm - j) % M            # 0 or 1
+                uu = 0.0
+            else:
+                assert nk == kap + 1
+                tt = ((nm - 2 * j) % (2 * M)) / 2.0
+                uu = 1.0
+            assert tt in (0.0, 0.5, 1.0)
+            pos += w * np.array([uu, tt, nl - l])
+        assert np.allclose(pos, [u, t, ts], atol=1e-12), (pos, u, t, ts)
+
+
+def test_isotropic_reductions():
+    # r = 1: only the isotropic grid (ratio level 0) carries weight (the
+    # two-level law of Sec. 4.2); K = 0: isotropic family only.
+    rng = np.random.default_rng(6)
+    for _ in range(500):
+        Pk, phi = 10.0 ** rng.uniform(-9, -3), rng.uniform(0, math.pi)
+        nodes, _, _ = oracle.grid_nodes(Pk, 1.0, phi, 4)
+        assert all(n[1] == 0 for n in nodes if n[3] > 0)
+        nodes, _, _ = oracle.grid_nodes(Pk, 8.0, phi, 0)
+        assert len(nodes) == 2 and all(n[1] == 0 and n[2] == 0 for n in nodes)
+        ts = Pk / 2.0 ** nodes[0][0] - 1.0
+        assert nodes[1][3] == pytest.approx(ts, abs=1e-15)  # Eq. 10 weight of the top level
+    # exact power of two and r = 1: a single grid
+    nodes, _, _ = oracle.grid_nodes(2.0**-10, 1.0, 0.3, 4)
+    assert [n for n in nodes if n[3] > 0] == [(-10, 0, 0, 1.0)]
+
+
+def _wmap(nodes):
+    out = {}
+    for (l, k, m, w) in nodes:
+        out[(l, k, m)] = out.get((l, k, m), 0.0) + w
+    return out
+
+
+def _wdist(a, b):
+    keys = set(a) | set(b)
+    return max(abs(a.get(k, 0.0) - b.get(k, 0.0)) for k in keys)
+
+
+def test_weights_continuous_across_cells():
+    """Coherence between consecutive LODs, ratios and orientations: the weight
+    of each grid is continuous (Sec. 1: coherence between consecutive LODs)."""
+    eps = 1e-9
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        phi = rng.uniform(0.01, math.pi - 0.01)
+        rk = 2.0 ** rng.uniform(0.1, 3.9)
+        l = int(rng.integers(-30, -5))
+        Pb = 2.0**l
+        a = _wmap(oracle.grid_nodes(Pb * (1 - eps), rk, phi)[0])
+        b = _wmap(oracle.grid_nodes(Pb * (1 + eps), rk, phi)[0])
+        assert _wdist(a, b) < 1e-7
+        kb = int(rng.integers(1, 4))
+        a = _wmap(oracle.grid_nodes(3e-7, 2.0 ** (kb - eps), phi)[0])
+        b = _wmap(oracle.grid_nodes(3e-7, 2.0 ** (kb + eps), phi)[0])
+        assert _wdist(a, b) < 1e-7
+        kap = int(rng.integers(0, 4))
+        M = 2 ** (kap + 1)
+        jb = int(rng.integers(1, M))
+        rr = 2.0 ** (kap + rng.uniform(0.05, 0.95))
+        a = _wmap(oracle.grid_nodes(3e-7, rr, jb * math.pi / M - eps)[0])
+        b = _wmap(oracle.grid_nodes(3e-7, rr, jb * math.pi / M + eps)[0])
+        assert _wdist(a, b) < 1e-7
+    # orientation wraps at pi: 0+ and pi- select the same grids
+    a = _wmap(oracle.grid_nodes(3e-7, 5.0, eps)[0])
+    b = _wmap(oracle.grid_nodes(3e-7, 5.0, math.pi - eps)[0])
+    assert _wdist(a, b) < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Simplex lattice (Sec. 6.2): barycentric reconstruction of the point
+# ---------------------------------------------------------------------------
+def test_simplex_reconstruction():
+    rng = np.random.default_rng(8)
+    for _ in range(3000):
+        l, k = int(rng.integers(-30, -5)), int(rng.integers(0, 5))
+        m = int(rng.integers(0, 2 ** (k + 1))) if k > 0 else 0
+        cx, cy = rng.uniform(-2, 2, 2)
+        verts, beta, _ = oracle.simplex(cx, cy, l, k, m)
+        beta = np.array(beta)
+        assert np.all(beta >= 0) and beta.sum() == pytest.approx(1.0, abs=1e-12)
+        # lattice vertex (i, j) sits at ((i - j/2) wx, j wy) in the grid frame,
+        # rotated back by +phi_g into uv space
+        phig = m * math.pi / 2 ** (k + 1) if k > 0 else 0.0
+        wx, wy = math.sqrt(2.0 ** (l + k)), math.sqrt(2.0 ** (l - k))
+        pts = []
+        for (i, j) in verts:
+            gx, gy = (i - 0.5 * j) * wx, j * wy
+            pts.append((math.cos(phig) * gx - math.sin(phig) * gy, math.sin(phig) * gx + math.cos(phig) * gy))
+        rec = beta @ np.array(pts)
+        scale = max(abs(cx), abs(cy), 1.0)
+        assert np.allclose(rec, [cx, cy], atol=1e-12 * scale / min(wx, wy) * wx), (rec, cx, cy)
+        # the three vertices form a triangle of area A/2 (cell area A = 2^l)
+        (x0, y0), (x1, y1), (x2, y2) = pts
+        tri = 0.5 * abs((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0))
+        assert tri == pytest.approx(0.5 * 2.0**l, rel=1e-9)
