@@ -1,0 +1,203 @@
+/*
+ * glint.h -- C ABI of the MI355X (gfx950) per-pixel glint shading library.
+ *
+ * Method: Deliot & Belcour, "Real-Time Rendering of Glinty Appearances using
+ * Distributed Binomial Laws on Anisotropic Grids" (HPG 2023).  For every pixel
+ * of a G-buffer the library takes the UV footprint from the screen-space
+ * derivatives (Sec. 5.1), picks the enclosing grids of the anisotropic
+ * (area, ratio, orientation) grid family (Sec. 5.2, Eq. 13, Fig. 4, Sec. 6.1),
+ * enumerates the simplex texels under the footprint (Sec. 6.2), hashes one
+ * pair of uniforms per texel and angular texel, counts reflecting flakes with
+ * the distributed gated binomial law (Eqs. 10, 14, 16-18) using
+ * p = R D(h)/D(n) (Eq. 4), and returns the glint BRDF's radiance (Eqs. 1-3).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers inside glint_gbuffer, output arrays, gradients, workspaces and
+ *    debug planes are DEVICE pointers on the current HIP device, owned by the
+ *    caller.  glint_material / glint_light / glint_params / glint_tune
+ *    arrays are HOST pointers; their contents are copied at the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously; no entry point synchronises.  Device
+ *    faults surface at the caller's next synchronisation.
+ *  - Return value: GLINT_OK (0) or a negative GLINT_E* status.  No exception
+ *    crosses the ABI.  On GLINT_EHIP, glint_last_hip_error() gives the
+ *    hipError_t of the failing call (per thread).
+ *  - Planes are row-major [height][stride] with stride >= width (elements).
+ *    out_rgb is SoA: three planes [3][height*stride] (R, G, B).
+ *  - The library keeps no mutable global state; it allocates device memory
+ *    only inside glint_plan objects.
+ */
+#ifndef GLINT_H
+#define GLINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GLINT_OK = 0,
+    GLINT_EINVAL = -1,        /* a parameter is out of its documented range        */
+    GLINT_ENULL = -2,         /* a required pointer is NULL                        */
+    GLINT_ESHAPE = -3,        /* width/height/stride/count inconsistent             */
+    GLINT_EHIP = -4,          /* a HIP runtime call failed (glint_last_hip_error)  */
+    GLINT_EUNSUPPORTED = -5,  /* valid request this build does not implement       */
+    GLINT_ENOMEM = -6         /* device allocation inside a plan failed            */
+};
+
+#define GLINT_MAX_MATERIALS 32
+#define GLINT_MAX_LIGHTS 16
+#define GLINT_MAX_K 4              /* largest ratio level: r_max = 2^4 = 16 (Fig. 4)   */
+#define GLINT_MAX_PROBES 64
+
+/* G-buffer of one view (Sec. 5.1 reads footprints from screen derivatives).
+ * u, v: texture coordinates; dudx..dvdy: their screen-space derivatives
+ * (the columns of J are d(uv)/dx and d(uv)/dy); n: shading normal; w: view
+ * direction toward the eye (both normalised inside).  material_id < 0 skips
+ * the pixel (output 0); material_id >= n_mat marks it invalid (output 0);
+ * NULL material_id means material 0 everywhere.  alpha_px and
+ * log10_density_px, when non-NULL, override the material's roughness and
+ * flake density per pixel.  Non-finite inputs, det J = 0 or a view below
+ * the surface give output 0. */
+typedef struct {
+    int32_t width, height;
+    int64_t stride;
+    const float *u, *v, *dudx, *dvdx, *dudy, *dvdy;
+    const float *nx, *ny, *nz, *wx, *wy, *wz;
+    const int32_t *material_id;
+    const float *alpha_px;
+    const float *log10_density_px;
+} glint_gbuffer;
+
+/* Glint material (Sec. 3).  ndf: 0 GGX, 1 Beckmann.  alpha > 0: roughness of
+ * D.  R in (0,1]: ratio of Eq. 4.  log10_density: flakes per unit UV area
+ * (log10).  micro_roughness in [1e-4, 1]: angular cell size over the
+ * orthographic projection of h (Eq. 14).  F0 in [0,1]: Schlick Fresnel at
+ * normal incidence.  seed: selects the random numbers of the material. */
+typedef struct {
+    int32_t ndf;
+    float alpha, R, log10_density, micro_roughness, F0;
+    uint32_t seed;
+} glint_material;
+
+/* Directional light: dir points toward the light (normalised inside; the
+ * gradient is taken with respect to the raw vector); radiance is RGB. */
+typedef struct {
+    float dir[3];
+    float radiance[3];
+} glint_light;
+
+/* k_max in [0, 4]: largest ratio level of the grid family (0 = isotropic
+ * grids only).  n_probe_max in [1, 64]: footprints with ratio above 2^k_max
+ * are split into ceil(r / 2^k_max) sub-footprints, at most n_probe_max.
+ * rounding: 0 = counts floor(1 + mu + sigma z) (Eq. 18); 1 = relaxed counts
+ * max(1, 1 + mu + sigma z) (the function the backward differentiates).
+ * flags: reserved, must be 0. */
+typedef struct {
+    int32_t k_max, n_probe_max, rounding;
+    uint32_t flags;
+} glint_params;
+
+/* Optional per-pixel debug planes of glint_shade (each [height*stride] or
+ * NULL).  They hold exact integer fingerprints of every discrete decision, so
+ * that a reference implementation can be compared bit for bit:
+ *  flags      bit0 shaded, bit1 ratio clamped at n_probe_max, bit2 p clamped
+ *             to 1, bit3 invalid input, bit4 view below surface, bit5 skipped
+ *             (material_id < 0), bit6 material_id >= n_mat
+ *  n_probe    number of sub-footprints; level: area level l = floor(log2 P_k)
+ *  cell       kappa | j<<3 | triangle<<9 | pivot<<11 | D<<13 | n_nodes<<15
+ *  key_sum    sum (mod 2^32) of the texel key hashes of every probe
+ *  akey_sum   sum (mod 2^32) of the angular key hashes (slot 0) of every light
+ *  theta_sum  sum (mod 2^32) of every gate hash (all 48 per probe and light)
+ *  count_sum  sum of all integer counts (rounding 0)
+ *  n_open     number of open gates; n_gate: number of gated binomials
+ *  b_light    [n_light][height*stride] distributed count sum b per light
+ * Asking for debug planes runs an instrumented kernel (slower, same image). */
+typedef struct {
+    uint32_t *flags;
+    int32_t *n_probe, *level;
+    uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate;
+    float *b_light;
+} glint_debug;
+
+/* Launch configuration of the batched path (autotuner output).
+ * tile_w x tile_h pixels per work unit (tile_w*tile_h == 64 * waves);
+ * blocks_per_cu: persistent workgroups per compute unit. */
+typedef struct {
+    int32_t tile_w, tile_h, blocks_per_cu, reserved;
+} glint_tune;
+
+typedef struct glint_plan glint_plan;
+
+/* Forward shading of one view: out_rgb[3][height*stride] <- radiance
+ * L = sum_l E_l F G D_P / (4 <w,n>) with D_P = D(n) b / (R N P)
+ * (Eqs. 1-4, 10, 14, 16-18).  n_mat in [1, 32], n_light in [0, 16].
+ * dbg may be NULL.  Errors: ENULL (gbuf, planes, mats, out_rgb, lights when
+ * n_light > 0), ESHAPE (width/height < 0, stride < width), EINVAL (params or
+ * material values out of range), EHIP (launch failure). */
+int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
+                const glint_light *lights, int32_t n_light, const glint_params *params,
+                float *out_rgb, const glint_debug *dbg, void *stream);
+
+/* Workspace for glint_shade_backward, in bytes. */
+size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_mat, int32_t n_light);
+
+/* Adjoint of the relaxed forward (rounding forced to 1): given
+ * grad_out_rgb = dLoss/dL ([3][height*stride]), writes (overwriting)
+ *   grad_alpha[n_mat]       dLoss/d alpha of each material
+ *   grad_ln_density[n_mat]  dLoss/d ln N of each material
+ *   grad_light_dir[3*n_light] dLoss/d dir (raw, unnormalised) of each light
+ * Every discrete branch (level, cell, triangle, tetrahedron, lattice,
+ * angular cell, gate, the max(1,.) clamp) is held at its value at the
+ * current parameters.  Gradients are accumulated in FP32 per pixel and
+ * reduced in a fixed order (deterministic).  Per-pixel overrides
+ * (alpha_px, log10_density_px) are not supported (EUNSUPPORTED).
+ * workspace: device memory of glint_backward_workspace_bytes(). */
+int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
+                         const glint_light *lights, int32_t n_light, const glint_params *params,
+                         const float *grad_out_rgb, float *grad_alpha, float *grad_ln_density,
+                         float *grad_light_dir, void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Batched shading of many views of uneven size in one persistent launch.
+ * glint_plan_create copies the view descriptors (device pointers inside
+ * gbufs/out_rgb stay owned by the caller and must outlive the plan), the
+ * materials, lights and params, builds the tile table on the device, and
+ * (tune may be NULL for defaults) fixes the launch shape.
+ * glint_shade_batched enqueues [counter reset kernel, persistent kernel] on
+ * `stream`; with use_graph != 0 it captures them once into a hipGraph and
+ * replays the graph afterwards.  Each view's output is bit-identical to
+ * glint_shade on that view.  The plan must not be used by two streams at
+ * once (its tile counter is shared). */
+int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t n_views,
+                      const glint_material *mats, int32_t n_mat, const glint_light *lights,
+                      int32_t n_light, const glint_params *params, const glint_tune *tune,
+                      glint_plan **plan);
+int glint_shade_batched(glint_plan *plan, int32_t use_graph, void *stream);
+int glint_plan_destroy(glint_plan *plan);
+/* number of tiles and of persistent workgroups of a plan (for reports) */
+int glint_plan_info(const glint_plan *plan, int64_t *n_tiles, int32_t *n_blocks);
+
+/* The per-texel random numbers, for bit-exact checks: keys is a device array
+ * [n][9] of int32 (seed, l, k, m, i, j, ai, aj, slot); out[n] receives the
+ * 32-bit hash whose top 23 bits give the uniform (2 (h >> 9) + 1) 2^-24. */
+int glint_texel_hash(const int32_t *keys, int64_t n, uint32_t *out, void *stream);
+
+/* One hash chaining step H(h, w) on device arrays (bit-exact checks). */
+int glint_hash_step(const uint32_t *h, const uint32_t *w, int64_t n, uint32_t *out, void *stream);
+
+/* Standard normal inverse CDF of the FP32 path, evaluated at the uniform
+ * (2 (bits >> 9) + 1) 2^-24 that each 32-bit hash word stands for. */
+int glint_ndtri(const uint32_t *bits, int64_t n, float *out, void *stream);
+
+const char *glint_status_string(int status);
+int glint_last_hip_error(void);
+/* ABI version: major*10000 + minor*100 + patch */
+int glint_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLINT_H */

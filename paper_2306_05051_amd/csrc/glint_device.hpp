@@ -1,0 +1,421 @@
+// glint_device.hpp -- device-side building blocks of per-pixel glint shading
+// for CDNA4 (gfx950).  Internal header of the HIP library; not installed.
+//
+// Precision plan.  Every discrete decision of the method is taken from values
+// whose error stays far below the 1e-5 decision margins:
+//  * FP64 (full rate on CDNA4): footprint moments and |det J|, footprint
+//    orientation, probe centres, the rotate/scale/skew into each grid's
+//    simplex lattice (cell coordinates reach 1e4..1e6), the half vector and
+//    its projection on the angular grid, 1 - cos^2 of the half vector.
+//  * FP32: everything continuous after that (barycentric weights, p, gate
+//    probabilities, Gaussian parameters, counts, BRDF) and the uniforms'
+//    inverse CDF.  The gate is compared in exact integer form.
+//  * integer (exact): texel keys and the hash.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace glint {
+
+constexpr int kMaxMat = 32;
+constexpr int kMaxLight = 16;
+constexpr int kWave = 64;
+constexpr float kPiF = 3.14159265358979323846f;
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Kernel-argument blocks (prepared by the host, passed by value)
+// ---------------------------------------------------------------------------
+struct DevMaterial {
+    int32_t ndf;
+    float alpha, R, log10N, F0;
+    uint32_t root;            // hash state after absorbing the material seed
+    double inv_micro;         // 1 / angular cell size
+};
+
+struct DevLight {
+    double wo[3];             // unit direction toward the light (FP64 normalised)
+    float rad[3];
+    int32_t ok;               // 0 when the raw direction has zero length
+};
+
+struct Shared {
+    DevMaterial mats[kMaxMat];
+    DevLight lights[kMaxLight];
+    double cs[32][2];         // cos, sin of m pi / 32: every grid orientation up to ratio level 4
+    int32_t n_mat, n_light, k_max, n_probe_max, rounding;
+};
+
+struct ViewDesc {
+    int32_t width, height;
+    int64_t stride;
+    const float *u, *v, *dudx, *dvdx, *dudy, *dvdy, *nx, *ny, *nz, *wx, *wy, *wz;
+    const int32_t *mat;
+    const float *alpha_px, *log10N_px;
+    float *out;
+};
+
+struct DebugPlanes {
+    uint32_t *flags;
+    int32_t *n_probe, *level;
+    uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate;
+    float *b_light;
+};
+
+enum : uint32_t {
+    F_SHADED = 1u, F_CLAMP_RATIO = 2u, F_CLAMP_P = 4u, F_BAD_INPUT = 8u,
+    F_BACKFACING = 16u, F_SKIPPED = 32u, F_BAD_MAT = 64u
+};
+
+// ---------------------------------------------------------------------------
+// Per-texel random numbers.  H(h, w) = fmix32((h ^ w) + golden), fmix32 the
+// MurmurHash3 finaliser; chains absorb one key word per step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__host__ __device__ __forceinline__ uint32_t fmix32_hd(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ uint32_t hstep(uint32_t h, uint32_t w)
+{
+    return fmix32((h ^ w) + 0x9E3779B9u);
+}
+
+constexpr uint32_t kRootSalt = 0x243F6A88u;     // material seed chain start
+constexpr uint32_t kAngularSalt = 0x13198A2Eu;  // angular key chain start
+
+__device__ __forceinline__ uint32_t node_word(int l, int k, int m)
+{
+    return (uint32_t)(l + 1024) | ((uint32_t)k << 11) | ((uint32_t)m << 14);
+}
+
+__device__ __forceinline__ uint32_t angular_word(int ai, int aj, int s)
+{
+    return ((uint32_t)(ai + 16384) & 0x7FFFu) | (((uint32_t)(aj + 16384) & 0x7FFFu) << 15) |
+           ((uint32_t)s << 30);
+}
+
+// Standard normal inverse CDF of the uniform (2 (h >> 9) + 1) 2^-24 that the
+// hash word h stands for.  Two-region erfinv approximation after Giles
+// (2011) with coefficients fitted for this library (fit_ndtri.py):
+// max relative error 3.1e-7 over all 2^23 uniforms.  x = 2q - 1, 1 - x and
+// 1 + x are exact in FP32.
+__device__ __forceinline__ float ndtri_bits(uint32_t h)
+{
+    const int k = (int)(h >> 9);
+    const float x = (float)(2 * k + 1 - 8388608) * 0x1p-23f;
+    const float omx = (float)(16777215 - 2 * k) * 0x1p-23f;   // 1 - x
+    const float opx = (float)(2 * k + 1) * 0x1p-23f;          // 1 + x
+    float w = -logf(omx * opx);
+    float p;
+    if (w < 5.0f) {
+        const float s = w - 2.5f;
+        p = 2.798955556e-08f;
+        p = fmaf(p, s, 3.430734239e-07f);
+        p = fmaf(p, s, -3.522236511e-06f);
+        p = fmaf(p, s, -4.389634341e-06f);
+        p = fmaf(p, s, 2.185773774e-04f);
+        p = fmaf(p, s, -1.253729803e-03f);
+        p = fmaf(p, s, -4.177678842e-03f);
+        p = fmaf(p, s, 2.466407418e-01f);
+        p = fmaf(p, s, 1.501409411e+00f);
+    } else {
+        const float s = sqrtf(w) - 3.0f;
+        p = -2.158486895e-04f;
+        p = fmaf(p, s, 1.057877307e-04f);
+        p = fmaf(p, s, 1.370809623e-03f);
+        p = fmaf(p, s, -3.677487373e-03f);
+        p = fmaf(p, s, 5.730178207e-03f);
+        p = fmaf(p, s, -7.621666417e-03f);
+        p = fmaf(p, s, 9.440163150e-03f);
+        p = fmaf(p, s, 1.001674056e+00f);
+        p = fmaf(p, s, 2.832976818e+00f);
+    }
+    return 1.41421356237309505f * p * x;
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel setup: footprint (Sec. 5.1), probe count (Sec. 4.2), the grid
+// nodes of the tetrahedron enclosing (area, ratio, orientation) (Eq. 13,
+// Fig. 4, Sec. 6.1) and the distributed weights (Eq. 10).
+// ---------------------------------------------------------------------------
+struct Pixel {
+    uint32_t flags;
+    int mat;
+    float alpha, N;            // roughness, flakes per unit UV area
+    double n[3], wi[3];
+    double cos_i;
+    double u, v, P;            // uv and |det J|
+    double ex, ey;             // sigma0 * major axis direction
+    int npr;
+    int n_nodes;
+    int nl[4], nk[4], nm[4];
+    float nw[4];
+    int level;
+    uint32_t cell;
+};
+
+__device__ __forceinline__ bool finitef(float x) { return (__float_as_uint(x) & 0x7f800000u) != 0x7f800000u; }
+
+template <bool DEBUG>
+__device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, const Shared &sh, Pixel &px)
+{
+    px.flags = 0;
+    px.npr = 0;
+    px.n_nodes = 0;
+    px.level = 0;
+    px.cell = 0;
+    const int mat = vw.mat ? vw.mat[idx] : 0;
+    px.mat = mat;
+    if (mat < 0) { px.flags = F_SKIPPED; return; }
+    if (mat >= sh.n_mat) { px.flags = F_BAD_MAT; return; }
+    const DevMaterial &M = sh.mats[mat];
+    const float fu = vw.u[idx], fv = vw.v[idx];
+    const float dux = vw.dudx[idx], dvx = vw.dvdx[idx], duy = vw.dudy[idx], dvy = vw.dvdy[idx];
+    const float fnx = vw.nx[idx], fny = vw.ny[idx], fnz = vw.nz[idx];
+    const float fwx = vw.wx[idx], fwy = vw.wy[idx], fwz = vw.wz[idx];
+    const float alpha = vw.alpha_px ? vw.alpha_px[idx] : M.alpha;
+    const float l10 = vw.log10N_px ? vw.log10N_px[idx] : M.log10N;
+    bool fin = finitef(fu) & finitef(fv) & finitef(dux) & finitef(dvx) & finitef(duy) & finitef(dvy) &
+               finitef(fnx) & finitef(fny) & finitef(fnz) & finitef(fwx) & finitef(fwy) & finitef(fwz) &
+               finitef(alpha) & finitef(l10);
+    if (!fin || !(alpha > 0.0f)) { px.flags = F_BAD_INPUT; return; }
+    px.alpha = alpha;
+    px.N = exp10f(l10);
+    // normal and view, FP64 normalised
+    double nn = (double)fnx * fnx + (double)fny * fny + (double)fnz * fnz;
+    double ww = (double)fwx * fwx + (double)fwy * fwy + (double)fwz * fwz;
+    if (!(nn > 0.0) || !(ww > 0.0)) { px.flags = F_BAD_INPUT; return; }
+    nn = sqrt(nn);
+    ww = sqrt(ww);
+    px.n[0] = fnx / nn; px.n[1] = fny / nn; px.n[2] = fnz / nn;
+    px.wi[0] = fwx / ww; px.wi[1] = fwy / ww; px.wi[2] = fwz / ww;
+    // footprint: J J^T moments and |det J| in FP64 (products of FP32 are exact)
+    const double a = (double)dux * dux + (double)duy * duy;
+    const double b = (double)dux * dvx + (double)duy * dvy;
+    const double c = (double)dvx * dvx + (double)dvy * dvy;
+    const double P = fabs((double)dux * dvy - (double)duy * dvx);
+    if (!(P > 0.0) || !(P < 1.0e300)) { px.flags = F_BAD_INPUT; return; }
+    px.cos_i = px.n[0] * px.wi[0] + px.n[1] * px.wi[1] + px.n[2] * px.wi[2];
+    if (!(px.cos_i > 0.0)) { px.flags = F_BACKFACING; return; }
+    const double hd = 0.5 * (a - c);
+    const double s0sq = 0.5 * (a + c) + sqrt(hd * hd + b * b);
+    double r = s0sq / P;
+    if (r < 1.0) r = 1.0;
+    double phi = 0.5 * atan2(2.0 * b, a - c);
+    if (phi < 0.0) phi += kPi;
+    const double s0 = sqrt(s0sq);
+    px.u = fu; px.v = fv; px.P = P;
+    px.ex = s0 * cos(phi);
+    px.ey = s0 * sin(phi);
+    // sub-footprints along the major axis when r exceeds the family's 2^K
+    const int K = sh.k_max;
+    const double rmax = (double)(1 << K);
+    int npr = (int)ceil(r / rmax);
+    if (npr < 1) npr = 1;
+    if (npr > sh.n_probe_max) npr = sh.n_probe_max;
+    px.npr = npr;
+    const double Pk = P / npr;
+    double rk = r / npr;
+    if (rk > rmax) { rk = rmax; px.flags |= F_CLAMP_RATIO; }
+    // area level (Eq. 13): Pk = fr 2^ex exactly, l = ex - 1, top weight ts (Eq. 10)
+    int ex;
+    const double fr = frexp(Pk, &ex);
+    const int l = ex - 1;
+    const double ts = 2.0 * fr - 1.0;
+    px.level = l;
+    // ratio / orientation cell (Fig. 4): ring kap holds 2^(kap+1) orientations.
+    // FP64 here: small barycentric weights keep their relative precision.
+    int tk[3], tm[3];
+    double lam[3];
+    int nv;
+    int kap = 0, j = 0, tri = 0;
+    if (K == 0) {
+        nv = 1; tk[0] = 0; tm[0] = 0; lam[0] = 1.0;
+        tk[1] = tk[2] = 0; tm[1] = tm[2] = 0; lam[1] = lam[2] = 0.0;
+    } else {
+        double rho = log2(rk);
+        rho = fmin(fmax(rho, 0.0), (double)K);
+        kap = min((int)floor(rho), K - 1);
+        const double u = rho - (double)kap;
+        const int M = 1 << (kap + 1);
+        const double q = phi / (kPi / (double)M);   // exact boundary hits reproduce (pi/M is exact)
+        j = (int)floor(q);
+        j = max(0, min(j, M - 1));
+        const double t = q - (double)j;
+        const int jn = (j + 1) & (M - 1);
+        const int o2 = (2 * j + 2) & (2 * M - 1);
+        // pentagon (u,t): I0=(0,0) I1=(0,1) O0=(1,0) O1=(1,1/2) O2=(1,1), three triangles (Fig. 5)
+        if (t <= 0.5 * u) {
+            tri = 0;
+            tk[0] = kap; tm[0] = j; lam[0] = 1.0 - u;
+            tk[1] = kap + 1; tm[1] = 2 * j; lam[1] = u - 2.0 * t;
+            tk[2] = kap + 1; tm[2] = 2 * j + 1; lam[2] = 2.0 * t;
+        } else if (t >= 1.0 - 0.5 * u) {
+            tri = 2;
+            tk[0] = kap; tm[0] = jn; lam[0] = 1.0 - u;
+            tk[1] = kap + 1; tm[1] = o2; lam[1] = u - 2.0 * (1.0 - t);
+            tk[2] = kap + 1; tm[2] = 2 * j + 1; lam[2] = 2.0 * (1.0 - t);
+        } else {
+            tri = 1;
+            tk[0] = kap; tm[0] = j; lam[0] = 1.0 - t - 0.5 * u;
+            tk[1] = kap; tm[1] = jn; lam[1] = t - 0.5 * u;
+            tk[2] = kap + 1; tm[2] = 2 * j + 1; lam[2] = u;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lam[i] = fmax(lam[i], 0.0);
+            if (tk[i] == 0) tm[i] = 0;      // the isotropic grid has no orientation
+        }
+        nv = 3;
+    }
+    // merge coincident grids (only ring 0 of triangle I0-I1-O1 can coincide),
+    // then order by key (k, m): a 3-element sorting network on registers
+    int k0 = tk[0], k1 = tk[1], k2 = tk[2], m0 = tm[0], m1 = tm[1], m2 = tm[2];
+    double l0 = lam[0], l1 = lam[1], l2 = lam[2];
+    int D = nv;
+    if (nv == 3 && k0 == k1 && m0 == m1) { l0 += l1; k1 = k2; m1 = m2; l1 = l2; D = 2; }
+    if (D == 1) { k1 = k2 = 255; m1 = m2 = 0; l1 = l2 = 0.0; }
+    if (D == 2) { k2 = 255; m2 = 0; l2 = 0.0; }
+#define GLINT_CSWAP(ka, ma, la, kb, mb, lb)                                      \
+    if ((ka) * 64 + (ma) > (kb) * 64 + (mb)) {                                   \
+        int _k = ka; ka = kb; kb = _k; int _m = ma; ma = mb; mb = _m;            \
+        double _l = la; la = lb; lb = _l;                                        \
+    }
+    GLINT_CSWAP(k0, m0, l0, k1, m1, l1)
+    GLINT_CSWAP(k1, m1, l1, k2, m2, l2)
+    GLINT_CSWAP(k0, m0, l0, k1, m1, l1)
+#undef GLINT_CSWAP
+    // prism -> tetrahedron: top-level mass ts goes to the highest keys first
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    int pivot;
+    {
+        double rem = ts;
+        if (D == 3) {
+            if (rem <= l2) { t2 = rem; pivot = 2; }
+            else {
+                t2 = l2; rem -= l2;
+                if (rem <= l1) { t1 = rem; pivot = 1; }
+                else { t1 = l1; rem -= l1; t0 = fmin(rem, l0); pivot = 0; }
+            }
+        } else if (D == 2) {
+            if (rem <= l1) { t1 = rem; pivot = 1; }
+            else { t1 = l1; rem -= l1; t0 = fmin(rem, l0); pivot = 0; }
+        } else {
+            t0 = fmin(rem, l0); pivot = 0;
+        }
+    }
+    // tetrahedron vertices: bottoms of sorted[0..pivot], tops of sorted[pivot..D-1]
+    const int n = D + 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const bool bottom = v <= pivot;
+        const int src = bottom ? v : v - 1;
+        const int kk = src == 0 ? k0 : (src == 1 ? k1 : k2);
+        const int mmv = src == 0 ? m0 : (src == 1 ? m1 : m2);
+        const double ll = src == 0 ? l0 : (src == 1 ? l1 : l2);
+        const double tt = src == 0 ? t0 : (src == 1 ? t1 : t2);
+        px.nl[v] = bottom ? l : l + 1;
+        px.nk[v] = v < n ? kk : 0;
+        px.nm[v] = v < n ? mmv : 0;
+        px.nw[v] = v < n ? (float)(bottom ? ll - tt : tt) : 0.0f;
+    }
+    px.n_nodes = n;
+    if (DEBUG)
+        px.cell = (uint32_t)kap | ((uint32_t)j << 3) | ((uint32_t)tri << 9) | ((uint32_t)pivot << 11) |
+                  ((uint32_t)D << 13) | ((uint32_t)n << 15);
+    px.flags |= F_SHADED;
+}
+
+// ---------------------------------------------------------------------------
+// Simplex lattice of grid node (l, k, m) around point c (Eq. 12 read as
+// rotate-then-scale, Sec. 6.2 simplex grid): three vertices and barycentrics.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double pow2_half(int e)   // 2^(e/2)
+{
+    const double r2 = 1.41421356237309504880;
+    const int h = e >> 1;                 // floor(e/2)
+    return (e & 1) ? ldexp(r2, h) : ldexp(1.0, h);
+}
+
+__device__ __forceinline__ void simplex_locate(double cx, double cy, int l, int k, int m, const Shared &sh,
+                                               int vi[3], int vj[3], float beta[3])
+{
+    const int mi = k ? (m << (4 - k)) : 0;
+    const double cph = sh.cs[mi][0], sph = sh.cs[mi][1];
+    const double qx = cph * cx + sph * cy;
+    const double qy = -sph * cx + cph * cy;
+    const double x = qx / pow2_half(l + k);
+    const double y = qy / pow2_half(l - k);
+    const double Lx = x + 0.5 * y, Ly = y;
+    const double fi = floor(Lx), fj = floor(Ly);
+    const double f = Lx - fi, g = Ly - fj;
+    const int i = (int)fi, j = (int)fj;
+    if (f >= g) {
+        vi[0] = i; vj[0] = j; vi[1] = i + 1; vj[1] = j; vi[2] = i + 1; vj[2] = j + 1;
+        beta[0] = (float)(1.0 - f); beta[1] = (float)(f - g); beta[2] = (float)g;
+    } else {
+        vi[0] = i; vj[0] = j; vi[1] = i; vj[1] = j + 1; vi[2] = i + 1; vj[2] = j + 1;
+        beta[0] = (float)(1.0 - g); beta[1] = (float)(g - f); beta[2] = (float)f;
+    }
+}
+
+// Orthonormal basis around a unit normal (Duff et al., JCGT 6(1), 2017)
+__device__ __forceinline__ void onb(const double n[3], double t[3], double b[3])
+{
+    const double sgn = copysign(1.0, n[2]);
+    const double a = -1.0 / (sgn + n[2]);
+    const double bb = n[0] * n[1] * a;
+    t[0] = 1.0 + sgn * n[0] * n[0] * a; t[1] = sgn * bb; t[2] = -sgn * n[0];
+    b[0] = bb; b[1] = sgn + n[1] * n[1] * a; b[2] = -n[1];
+}
+
+// Smith Lambda of the NDF for a direction with cos theta = c, 1 - c^2 = s2
+__device__ __forceinline__ float smith_lambda(int ndf, float alpha, float c, float s2)
+{
+    if (s2 <= 0.0f) return 0.0f;
+    const float tan2 = s2 / (c * c);
+    if (ndf == 0) return 0.5f * (-1.0f + sqrtf(1.0f + alpha * alpha * tan2));
+    const float a = 1.0f / (alpha * sqrtf(tan2));
+    return 0.5f * (erff(a) - 1.0f) + expf(-a * a) / (2.0f * a * 1.7724538509055160f);
+}
+
+// p = min(1, R D(h)/D(n)) (Eq. 4) from cos^2 and 1 - cos^2 of the half vector
+__device__ __forceinline__ float success_prob(int ndf, float alpha, float R, float c2, float s2, bool &clamped)
+{
+    const float a2 = alpha * alpha;
+    float ratio;
+    if (ndf == 0) {
+        const float d = s2 + c2 * a2;          // (n.h)^2 (a^2 - 1) + 1, cancellation-free
+        ratio = (a2 * a2) / (d * d);
+    } else {
+        ratio = expf(-(s2 / c2) / a2) / (c2 * c2);
+    }
+    float p = R * ratio;
+    clamped = p > 1.0f;
+    return clamped ? 1.0f : p;
+}
+
+// gate threshold: the uniform (2k+1) 2^-24 is below pg  <=>  k < K
+__device__ __forceinline__ uint32_t gate_threshold(float pg)
+{
+    const float kf = ceilf((pg * 16777216.0f - 1.0f) * 0.5f);
+    return kf <= 0.0f ? 0u : (kf >= 8388608.0f ? 8388608u : (uint32_t)kf);
+}
+
+}  // namespace glint

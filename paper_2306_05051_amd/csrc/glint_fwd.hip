@@ -1,0 +1,571 @@
+// glint_fwd.hip -- forward glint shading kernels for gfx950 and the C ABI
+// entry points glint_shade, glint_plan_*, glint_shade_batched and the
+// bit-exactness utilities.
+//
+// Work decomposition.  One wavefront (64 lanes) owns a tile of 64 pixels.
+//  1. lane = pixel: footprint and number of sub-footprints n_pr (1..n_probe_max).
+//  2. a wave prefix sum flattens the tile's (pixel, probe) items; lanes then
+//     take items 64 at a time, so pixels with very different footprint
+//     lengths (1..21 probes, 12..252 texels) keep every lane busy.
+//  3. lane = item: grid nodes, 12 simplex texels and their key hashes, then
+//     for every light 48 gated binomials (4 grids x 3 texels x 4 angular
+//     texels, Sec. 6.2); gates whose probability is below the smallest
+//     uniform 2^-24 cannot open and are skipped without hashing.
+//  4. item contributions go through LDS and each pixel lane sums its own
+//     probes in probe order (deterministic), then writes RGB planes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "glint_device.hpp"
+#include "glint_host.hpp"
+
+namespace glint {
+
+thread_local int g_last_hip_error = 0;
+
+int set_hip_error(hipError_t e)
+{
+    g_last_hip_error = (int)e;
+    return GLINT_EHIP;
+}
+
+struct ItemOut {
+    float rgb[3];
+    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate;
+    float b[kMaxLight];
+};
+
+// ---------------------------------------------------------------------------
+// One (pixel, probe) item: simplex texels of every grid node, then per light
+// the distributed gated binomial sum b and its radiance contribution.
+// ---------------------------------------------------------------------------
+template <bool DEBUG>
+__device__ __forceinline__ void shade_item(const Pixel &px, int kp, const Shared &sh, ItemOut &o)
+{
+    o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
+    if (DEBUG) {
+        o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = 0;
+        for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
+    }
+    const DevMaterial &M = sh.mats[px.mat];
+    // probe centre, uniform along the major axis over length sigma0
+    const double off = ((double)kp + 0.5) / (double)px.npr - 0.5;
+    const double cx = px.u + off * px.ex, cy = px.v + off * px.ey;
+    uint32_t pre[4][3];
+    float beta[4][3];
+    const int nn = px.n_nodes;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if (g < nn) {
+            int vi[3], vj[3];
+            simplex_locate(cx, cy, px.nl[g], px.nk[g], px.nm[g], sh, vi, vj, beta[g]);
+            const uint32_t base = hstep(M.root, node_word(px.nl[g], px.nk[g], px.nm[g]));
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
+                if (DEBUG) o.key_sum += pre[g][e];
+            }
+        }
+    }
+    double tt[3], bb[3];
+    onb(px.n, tt, bb);
+    const double cos_i = px.cos_i;
+    // D_P = D(n) b / (R N P) with D(n) = 1/(pi alpha^2); L = E F G D_P / (4 <wi,n>)
+    const float kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha *
+                                     (double)px.alpha * 4.0 * cos_i));
+    const float ci = (float)cos_i, si2 = (float)(1.0 - cos_i * cos_i);
+    const float lam_i = smith_lambda(M.ndf, px.alpha, ci, si2);
+    for (int li = 0; li < sh.n_light; ++li) {
+        const DevLight &L = sh.lights[li];
+        if (!L.ok) continue;
+        const double cos_o = px.n[0] * L.wo[0] + px.n[1] * L.wo[1] + px.n[2] * L.wo[2];
+        if (!(cos_o > 0.0)) continue;
+        double h[3] = {px.wi[0] + L.wo[0], px.wi[1] + L.wo[1], px.wi[2] + L.wo[2]};
+        const double hl = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+        if (!(hl > 0.0)) continue;
+        h[0] /= hl; h[1] /= hl; h[2] /= hl;
+        const double ch = px.n[0] * h[0] + px.n[1] * h[1] + px.n[2] * h[2];
+        bool pclamp;
+        const float p = success_prob(M.ndf, px.alpha, M.R, (float)(ch * ch), (float)(1.0 - ch * ch), pclamp);
+        // angular grid over the projected half vector (Eq. 14)
+        const double ax = (h[0] * tt[0] + h[1] * tt[1] + h[2] * tt[2]) * M.inv_micro - 0.5;
+        const double ay = (h[0] * bb[0] + h[1] * bb[1] + h[2] * bb[2]) * M.inv_micro - 0.5;
+        const double fax = floor(ax), fay = floor(ay);
+        const int ai = (int)fax, aj = (int)fay;
+        // bilinear weights; both complements from FP64 so small weights stay accurate
+        const float fx = (float)(ax - fax), fy = (float)(ay - fay);
+        const float gx = (float)(fax + 1.0 - ax), gy = (float)(fay + 1.0 - ay);
+        const float v[4] = {gx * gy, fx * gy, gx * fy, fx * fy};
+        uint32_t ak0[4], ak1[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            ak0[a] = hstep(kAngularSalt, angular_word(ai + (a & 1), aj + (a >> 1), 0));
+            ak1[a] = hstep(kAngularSalt, angular_word(ai + (a & 1), aj + (a >> 1), 1));
+        }
+        const float lp = log1pf(-p);
+        float bsum = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            if (g >= nn) continue;
+            // Eq. 10: node g receives w_g N 2^l_g trials; Eqs. 16-17
+            const float ng = px.nw[g] * ldexpf(px.N, px.nl[g]);
+            float pg = 0.0f;
+            if (ng > 0.0f && p > 0.0f) pg = (p >= 1.0f) ? 1.0f : -expm1f(ng * lp);
+            const uint32_t K = gate_threshold(pg);
+            if (!DEBUG && K == 0u) continue;
+            const float mm = fmaxf(ng - 1.0f, 0.0f);
+            const float mu1 = 1.0f + mm * p;
+            const float sg = sqrtf(mm * p * (1.0f - p));
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const uint32_t h0 = hstep(pre[g][e], ak0[a]);
+                    if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; }
+                    if ((h0 >> 9) < K) {                       // theta0 < P>=1 (Eq. 18 gate)
+                        const uint32_t h1 = hstep(pre[g][e], ak1[a]);
+                        const float x = fmaf(sg, ndtri_bits(h1), mu1);
+                        const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
+                        bsum = fmaf(beta[g][e] * v[a], c, bsum);
+                        if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
+                    }
+                }
+            }
+        }
+        // Schlick Fresnel, separable Smith masking (Eq. 2)
+        const float om = (float)(1.0 - (px.wi[0] * h[0] + px.wi[1] * h[1] + px.wi[2] * h[2]));
+        const float om2 = om * om;
+        const float F = M.F0 + (1.0f - M.F0) * om2 * om2 * om;
+        const float lam_o = smith_lambda(M.ndf, px.alpha, (float)cos_o, (float)(1.0 - cos_o * cos_o));
+        const float G = 1.0f / ((1.0f + lam_i) * (1.0f + lam_o));
+        const float f = F * G * kpx * bsum;
+        o.rgb[0] = fmaf(L.rad[0], f, o.rgb[0]);
+        o.rgb[1] = fmaf(L.rad[1], f, o.rgb[1]);
+        o.rgb[2] = fmaf(L.rad[2], f, o.rgb[2]);
+        if (DEBUG) o.b[li] = bsum;
+    }
+}
+
+// per-pixel angular fingerprint (debug only): sum of slot-0 angular keys
+__device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
+{
+    const DevMaterial &M = sh.mats[px.mat];
+    double tt[3], bb[3];
+    onb(px.n, tt, bb);
+    uint32_t s = 0;
+    for (int li = 0; li < sh.n_light; ++li) {
+        const DevLight &L = sh.lights[li];
+        if (!L.ok) continue;
+        const double cos_o = px.n[0] * L.wo[0] + px.n[1] * L.wo[1] + px.n[2] * L.wo[2];
+        if (!(cos_o > 0.0)) continue;
+        double h[3] = {px.wi[0] + L.wo[0], px.wi[1] + L.wo[1], px.wi[2] + L.wo[2]};
+        const double hl = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+        if (!(hl > 0.0)) continue;
+        h[0] /= hl; h[1] /= hl; h[2] /= hl;
+        const double ax = (h[0] * tt[0] + h[1] * tt[1] + h[2] * tt[2]) * M.inv_micro - 0.5;
+        const double ay = (h[0] * bb[0] + h[1] * bb[1] + h[2] * bb[2]) * M.inv_micro - 0.5;
+        const int ai = (int)floor(ax), aj = (int)floor(ay);
+        for (int a = 0; a < 4; ++a) s += hstep(kAngularSalt, angular_word(ai + (a & 1), aj + (a >> 1), 0));
+    }
+    return s;
+}
+
+template <bool DEBUG>
+struct TileSmem {
+    int off[kWave];
+    ItemOut slot[kWave];
+};
+
+// ---------------------------------------------------------------------------
+// One tile of 64 pixels (tile_w x 64/tile_w) at (x0, y0) of a view.
+// ---------------------------------------------------------------------------
+template <bool DEBUG>
+__device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
+                           int tile_w, TileSmem<DEBUG> &sm)
+{
+    const int lane = threadIdx.x;
+    const int x = x0 + (lane % tile_w), y = y0 + (lane / tile_w);
+    const bool inb = (x < vw.width) && (y < vw.height);
+    const int64_t idx = (int64_t)y * vw.stride + x;
+    Pixel px;
+    px.flags = 0;
+    px.npr = 0;
+    if (inb) setup_pixel<DEBUG>(vw, idx, sh, px);
+    const int npr = (px.flags & F_SHADED) ? px.npr : 0;
+    int incl = npr;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+    }
+    const int off = incl - npr;
+    const int S = __shfl(incl, kWave - 1);
+    sm.off[lane] = off;
+    __syncthreads();
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0;
+    float db[kMaxLight];
+    if (DEBUG)
+        for (int l = 0; l < kMaxLight; ++l) db[l] = 0.0f;
+    for (int base = 0; base < S; base += kWave) {
+        const int q = base + lane;
+        if (q < S) {
+            int p = 0;
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1)
+                if (sm.off[p + st] <= q) p += st;
+            const int kp = q - sm.off[p];
+            const int px_x = x0 + (p % tile_w), px_y = y0 + (p / tile_w);
+            Pixel ip;
+            setup_pixel<false>(vw, (int64_t)px_y * vw.stride + px_x, sh, ip);
+            ItemOut o;
+            shade_item<DEBUG>(ip, kp, sh, o);
+            sm.slot[lane].rgb[0] = o.rgb[0];
+            sm.slot[lane].rgb[1] = o.rgb[1];
+            sm.slot[lane].rgb[2] = o.rgb[2];
+            if (DEBUG) {
+                sm.slot[lane].key_sum = o.key_sum;
+                sm.slot[lane].theta_sum = o.theta_sum;
+                sm.slot[lane].count_sum = o.count_sum;
+                sm.slot[lane].n_open = o.n_open;
+                sm.slot[lane].n_gate = o.n_gate;
+                for (int l = 0; l < kMaxLight; ++l) sm.slot[lane].b[l] = o.b[l];
+            }
+        }
+        __syncthreads();
+        if (npr > 0) {
+            const int i0 = max(off, base), i1 = min(off + npr, base + kWave);
+            for (int i = i0; i < i1; ++i) {
+                const ItemOut &s = sm.slot[i - base];
+                acc[0] += s.rgb[0];
+                acc[1] += s.rgb[1];
+                acc[2] += s.rgb[2];
+                if (DEBUG) {
+                    dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
+                    for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (inb) {
+        const int64_t npx = (int64_t)vw.height * vw.stride;
+        vw.out[idx] = acc[0];
+        vw.out[npx + idx] = acc[1];
+        vw.out[2 * npx + idx] = acc[2];
+        if (DEBUG) {
+            if (dp.flags) dp.flags[idx] = px.flags;
+            if (dp.n_probe) dp.n_probe[idx] = npr;
+            if (dp.level) dp.level[idx] = npr ? px.level : 0;
+            if (dp.cell) dp.cell[idx] = npr ? px.cell : 0;
+            if (dp.key_sum) dp.key_sum[idx] = dks;
+            if (dp.akey_sum) dp.akey_sum[idx] = npr ? akey_fingerprint(px, sh) : 0u;
+            if (dp.theta_sum) dp.theta_sum[idx] = dts;
+            if (dp.count_sum) dp.count_sum[idx] = dcs;
+            if (dp.n_open) dp.n_open[idx] = dno;
+            if (dp.n_gate) dp.n_gate[idx] = dng;
+            if (dp.b_light)
+                for (int l = 0; l < sh.n_light; ++l) dp.b_light[l * npx + idx] = db[l];
+        }
+    }
+}
+
+template <bool DEBUG>
+__global__ __launch_bounds__(64) void glint_fwd_kernel(ViewDesc vw, Shared sh, DebugPlanes dp, int tile_w,
+                                                       int tiles_x)
+{
+    __shared__ TileSmem<DEBUG> sm;
+    const int tile_h = kWave / tile_w;
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    shade_tile<DEBUG>(vw, sh, dp, tx * tile_w, ty * tile_h, tile_w, sm);
+}
+
+// Persistent batched kernel: workgroups pop chunks of tiles from a global
+// counter until every tile of every view is done (the loop always ends: the
+// counter only grows and each pop covers at least one tile).
+__global__ __launch_bounds__(64) void glint_batched_kernel(const ViewDesc *views, const int64_t *tile_start,
+                                                           int n_views, int64_t n_tiles, int tile_w, int chunk,
+                                                           unsigned long long *counter, Shared sh)
+{
+    __shared__ TileSmem<false> sm;
+    __shared__ long long s_t0;
+    const int tile_h = kWave / tile_w;
+    DebugPlanes dp = {};
+    for (;;) {
+        if (threadIdx.x == 0) s_t0 = (long long)atomicAdd(counter, (unsigned long long)chunk);
+        __syncthreads();
+        const int64_t t0 = s_t0;
+        __syncthreads();
+        if (t0 >= n_tiles) break;
+        const int64_t t1 = t0 + chunk < n_tiles ? t0 + chunk : n_tiles;
+        for (int64_t t = t0; t < t1; ++t) {
+            int lo = 0, hi = n_views;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (tile_start[mid] <= t) lo = mid; else hi = mid;
+            }
+            const ViewDesc vw = views[lo];
+            const int64_t local = t - tile_start[lo];
+            const int tiles_x = (vw.width + tile_w - 1) / tile_w;
+            const int tx = (int)(local % tiles_x), ty = (int)(local / tiles_x);
+            shade_tile<false>(vw, sh, dp, tx * tile_w, ty * tile_h, tile_w, sm);
+        }
+    }
+}
+
+__global__ void glint_reset_counter(unsigned long long *counter) { *counter = 0ull; }
+
+// bit-exactness utilities ----------------------------------------------------
+__global__ void glint_texel_hash_kernel(const int32_t *keys, int64_t n, uint32_t *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t *k = keys + 9 * i;
+    const uint32_t root = hstep(kRootSalt, (uint32_t)k[0]);
+    const uint32_t base = hstep(root, node_word(k[1], k[2], k[3]));
+    const uint32_t pre = hstep(hstep(base, (uint32_t)k[4]), (uint32_t)k[5]);
+    const uint32_t ak = hstep(kAngularSalt, angular_word(k[6], k[7], k[8]));
+    out[i] = hstep(pre, ak);
+}
+
+__global__ void glint_hash_step_kernel(const uint32_t *h, const uint32_t *w, int64_t n, uint32_t *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = hstep(h[i], w[i]);
+}
+
+__global__ void glint_ndtri_kernel(const uint32_t *bits, int64_t n, float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = ndtri_bits(bits[i]);
+}
+
+static bool valid_tile_w(int w) { return w == 8 || w == 16 || w == 32 || w == 64; }
+
+}  // namespace glint
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace glint;
+
+struct glint_plan {
+    ViewDesc *d_views = nullptr;
+    int64_t *d_tile_start = nullptr;
+    unsigned long long *d_counter = nullptr;
+    int n_views = 0;
+    int64_t n_tiles = 0;
+    int tile_w = 8;
+    int chunk = 4;
+    int n_blocks = 0;
+    Shared sh;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+extern "C" {
+
+int glint_version(void) { return 10000; }
+
+int glint_last_hip_error(void) { return g_last_hip_error; }
+
+const char *glint_status_string(int s)
+{
+    switch (s) {
+    case GLINT_OK: return "ok";
+    case GLINT_EINVAL: return "invalid argument value";
+    case GLINT_ENULL: return "required pointer is NULL";
+    case GLINT_ESHAPE: return "inconsistent shape or stride";
+    case GLINT_EHIP: return "HIP runtime error (see glint_last_hip_error)";
+    case GLINT_EUNSUPPORTED: return "unsupported request";
+    case GLINT_ENOMEM: return "device allocation failed";
+    default: return "unknown status";
+    }
+}
+
+int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat, const glint_light *lights,
+                int32_t n_light, const glint_params *params, float *out_rgb, const glint_debug *dbg, void *stream)
+{
+    Shared sh;
+    int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
+    if (rc) return rc;
+    ViewDesc vw;
+    rc = make_view(gbuf, out_rgb, vw);
+    if (rc) return rc;
+    if ((int64_t)vw.width * vw.height == 0) return GLINT_OK;
+    const int tile_w = 8;
+    const int tiles_x = (vw.width + tile_w - 1) / tile_w;
+    const int tiles_y = (vw.height + (kWave / tile_w) - 1) / (kWave / tile_w);
+    const int64_t nt = (int64_t)tiles_x * tiles_y;
+    if (nt > 0x7fffffffLL) return GLINT_ESHAPE;
+    hipStream_t st = (hipStream_t)stream;
+    if (dbg) {
+        DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
+                          dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->b_light};
+        hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp, tile_w,
+                           tiles_x);
+    } else {
+        DebugPlanes dp = {};
+        hipLaunchKernelGGL(glint_fwd_kernel<false>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp, tile_w,
+                           tiles_x);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+}
+
+int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t n_views,
+                      const glint_material *mats, int32_t n_mat, const glint_light *lights, int32_t n_light,
+                      const glint_params *params, const glint_tune *tune, glint_plan **plan)
+{
+    if (!plan || !gbufs || !out_rgb) return GLINT_ENULL;
+    *plan = nullptr;
+    if (n_views < 1) return GLINT_ESHAPE;
+    glint_plan *P = new (std::nothrow) glint_plan();
+    if (!P) return GLINT_ENOMEM;
+    int rc = prepare_shared(mats, n_mat, lights, n_light, params, P->sh);
+    if (rc) { delete P; return rc; }
+    P->tile_w = 8;
+    int bpc = 8;
+    if (tune) {
+        if (!valid_tile_w(tune->tile_w) || tune->tile_w * tune->tile_h != kWave || tune->blocks_per_cu < 1 ||
+            tune->blocks_per_cu > 64) {
+            delete P;
+            return GLINT_EINVAL;
+        }
+        P->tile_w = tune->tile_w;
+        bpc = tune->blocks_per_cu;
+    }
+    std::vector<ViewDesc> views((size_t)n_views);
+    std::vector<int64_t> start((size_t)n_views + 1);
+    int64_t total = 0;
+    const int tile_h = kWave / P->tile_w;
+    for (int i = 0; i < n_views; ++i) {
+        rc = make_view(&gbufs[i], out_rgb[i], views[i]);
+        if (rc) { delete P; return rc; }
+        start[i] = total;
+        total += (int64_t)((views[i].width + P->tile_w - 1) / P->tile_w) * ((views[i].height + tile_h - 1) / tile_h);
+    }
+    start[n_views] = total;
+    P->n_views = n_views;
+    P->n_tiles = total;
+    int dev = 0, n_cu = 256;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) { delete P; return set_hip_error(e); }
+    int64_t want = (int64_t)n_cu * bpc;
+    P->n_blocks = (int)(want < 1 ? 1 : want);
+    // chunks of tiles per pop: about 16 pops per workgroup, at most 16 tiles
+    int64_t per = total / ((int64_t)P->n_blocks * 16);
+    P->chunk = (int)(per < 1 ? 1 : (per > 16 ? 16 : per));
+    e = hipMalloc((void **)&P->d_views, sizeof(ViewDesc) * n_views);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_tile_start, sizeof(int64_t) * (n_views + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_counter, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemcpy(P->d_views, views.data(), sizeof(ViewDesc) * n_views, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(P->d_tile_start, start.data(), sizeof(int64_t) * (n_views + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        glint_plan_destroy(P);
+        return e == hipErrorOutOfMemory ? GLINT_ENOMEM : set_hip_error(e);
+    }
+    *plan = P;
+    return GLINT_OK;
+}
+
+static int enqueue_batched(glint_plan *P, hipStream_t st)
+{
+    hipLaunchKernelGGL(glint_reset_counter, dim3(1), dim3(1), 0, st, P->d_counter);
+    hipLaunchKernelGGL(glint_batched_kernel, dim3((unsigned)P->n_blocks), dim3(kWave), 0, st, P->d_views,
+                       P->d_tile_start, P->n_views, P->n_tiles, P->tile_w, P->chunk, P->d_counter, P->sh);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+}
+
+int glint_shade_batched(glint_plan *P, int32_t use_graph, void *stream)
+{
+    if (!P) return GLINT_ENULL;
+    if (P->n_tiles == 0) return GLINT_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (!use_graph) return enqueue_batched(P, st);
+    if (!P->exec) {
+        // capture on a private stream so that the caller's stream is never in capture mode
+        hipStream_t cs;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) return set_hip_error(e);
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) { (void)hipStreamDestroy(cs); return set_hip_error(e); }
+        int rc = enqueue_batched(P, cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return set_hip_error(e);
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); return set_hip_error(e); }
+        P->graph = g;
+        P->exec = ex;
+    }
+    hipError_t e = hipGraphLaunch(P->exec, st);
+    return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+}
+
+int glint_plan_info(const glint_plan *P, int64_t *n_tiles, int32_t *n_blocks)
+{
+    if (!P) return GLINT_ENULL;
+    if (n_tiles) *n_tiles = P->n_tiles;
+    if (n_blocks) *n_blocks = P->n_blocks;
+    return GLINT_OK;
+}
+
+int glint_plan_destroy(glint_plan *P)
+{
+    if (!P) return GLINT_OK;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->d_views) (void)hipFree(P->d_views);
+    if (P->d_tile_start) (void)hipFree(P->d_tile_start);
+    if (P->d_counter) (void)hipFree(P->d_counter);
+    delete P;
+    return GLINT_OK;
+}
+
+int glint_texel_hash(const int32_t *keys, int64_t n, uint32_t *out, void *stream)
+{
+    if (n < 0) return GLINT_ESHAPE;
+    if (n == 0) return GLINT_OK;
+    if (!keys || !out) return GLINT_ENULL;
+    hipLaunchKernelGGL(glint_texel_hash_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, keys, n, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+}
+
+int glint_hash_step(const uint32_t *h, const uint32_t *w, int64_t n, uint32_t *out, void *stream)
+{
+    if (n < 0) return GLINT_ESHAPE;
+    if (n == 0) return GLINT_OK;
+    if (!h || !w || !out) return GLINT_ENULL;
+    hipLaunchKernelGGL(glint_hash_step_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, h, w, n, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+}
+
+int glint_ndtri(const uint32_t *bits, int64_t n, float *out, void *stream)
+{
+    if (n < 0) return GLINT_ESHAPE;
+    if (n == 0) return GLINT_OK;
+    if (!bits || !out) return GLINT_ENULL;
+    hipLaunchKernelGGL(glint_ndtri_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, bits, n, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// glint_host.hpp -- host-side helpers shared by the library's translation
+// units: argument validation, kernel-argument preparation, error state.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/glint.h"
+#include "glint_device.hpp"
+
+namespace glint {
+
+int set_hip_error(hipError_t e);   // records e for glint_last_hip_error, returns GLINT_EHIP
+
+inline bool finite_host(float x) { return std::isfinite(x); }
+
+// Validates materials / lights / params and fills the kernel-argument block.
+inline int prepare_shared(const glint_material *mats, int32_t n_mat, const glint_light *lights,
+                          int32_t n_light, const glint_params *prm, Shared &sh)
+{
+    if (!mats || !prm || (n_light > 0 && !lights)) return GLINT_ENULL;
+    if (n_mat < 1 || n_mat > kMaxMat || n_light < 0 || n_light > kMaxLight) return GLINT_EINVAL;
+    if (prm->k_max < 0 || prm->k_max > GLINT_MAX_K || prm->n_probe_max < 1 ||
+        prm->n_probe_max > GLINT_MAX_PROBES || (prm->rounding != 0 && prm->rounding != 1) || prm->flags != 0)
+        return GLINT_EINVAL;
+    std::memset(&sh, 0, sizeof(sh));
+    for (int i = 0; i < n_mat; ++i) {
+        const glint_material &m = mats[i];
+        if ((m.ndf != 0 && m.ndf != 1) || !finite_host(m.alpha) || !(m.alpha > 0.0f) ||
+            !finite_host(m.R) || !(m.R > 0.0f) || !(m.R <= 1.0f) || !(m.log10_density >= -20.0f) ||
+            !(m.log10_density <= 20.0f) ||
+            !(m.micro_roughness >= 1e-4f) || !(m.micro_roughness <= 1.0f) || !(m.F0 >= 0.0f) ||
+            !(m.F0 <= 1.0f))
+            return GLINT_EINVAL;
+        DevMaterial &d = sh.mats[i];
+        d.ndf = m.ndf;
+        d.alpha = m.alpha;
+        d.R = m.R;
+        d.log10N = m.log10_density;
+        d.F0 = m.F0;
+        d.root = fmix32_hd((kRootSalt ^ m.seed) + 0x9E3779B9u);
+        d.inv_micro = 1.0 / (double)m.micro_roughness;
+    }
+    for (int i = 0; i < n_light; ++i) {
+        const glint_light &l = lights[i];
+        double w[3] = {l.dir[0], l.dir[1], l.dir[2]};
+        double len = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        DevLight &d = sh.lights[i];
+        d.ok = (len > 0.0 && std::isfinite(len)) ? 1 : 0;
+        for (int c = 0; c < 3; ++c) {
+            d.wo[c] = d.ok ? w[c] / len : 0.0;
+            if (!finite_host(l.radiance[c])) return GLINT_EINVAL;
+            d.rad[c] = l.radiance[c];
+        }
+    }
+    for (int m = 0; m < 32; ++m) {
+        const double a = (double)m * 3.14159265358979323846 / 32.0;
+        sh.cs[m][0] = std::cos(a);
+        sh.cs[m][1] = std::sin(a);
+    }
+    sh.n_mat = n_mat;
+    sh.n_light = n_light;
+    sh.k_max = prm->k_max;
+    sh.n_probe_max = prm->n_probe_max;
+    sh.rounding = prm->rounding;
+    return GLINT_OK;
+}
+
+inline int make_view(const glint_gbuffer *g, float *out, ViewDesc &v)
+{
+    if (!g) return GLINT_ENULL;
+    if (g->width < 0 || g->height < 0 || g->stride < g->width) return GLINT_ESHAPE;
+    if ((int64_t)g->width * g->height > 0) {
+        if (!g->u || !g->v || !g->dudx || !g->dvdx || !g->dudy || !g->dvdy || !g->nx || !g->ny || !g->nz ||
+            !g->wx || !g->wy || !g->wz || !out)
+            return GLINT_ENULL;
+    }
+    v.width = g->width;
+    v.height = g->height;
+    v.stride = g->stride;
+    v.u = g->u; v.v = g->v; v.dudx = g->dudx; v.dvdx = g->dvdx; v.dudy = g->dudy; v.dvdy = g->dvdy;
+    v.nx = g->nx; v.ny = g->ny; v.nz = g->nz; v.wx = g->wx; v.wy = g->wy; v.wz = g->wz;
+    v.mat = g->material_id;
+    v.alpha_px = g->alpha_px;
+    v.log10N_px = g->log10_density_px;
+    v.out = out;
+    return GLINT_OK;
+}
+
+}  // namespace glint

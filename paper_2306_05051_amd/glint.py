@@ -1,0 +1,292 @@
+"""Thin Python binding of libglint.so (the C ABI declared in include/glint.h).
+
+Argument marshalling only: every step of glint shading runs in the HIP
+kernels.  PyTorch provides device memory and the current HIP stream.  The
+binding refuses to run when the library is missing; there is no CPU path.
+
+A G-buffer is a dict of CUDA tensors of shape (H, W), dtype float32
+(u, v, dudx, dvdx, dudy, dvdy, nx, ny, nz, wx, wy, wz), an optional int32
+``material_id`` and optional float32 ``alpha_px`` / ``log10_density_px``.
+Materials are dicts (ndf, alpha, R, log10_density, micro_roughness, F0,
+seed) and lights are dicts (dir, radiance), as in ``include/glint.h``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libglint.so")
+PLANES = ("u", "v", "dudx", "dvdx", "dudy", "dvdy", "nx", "ny", "nz", "wx", "wy", "wz")
+
+GLINT_OK, GLINT_EINVAL, GLINT_ENULL, GLINT_ESHAPE = 0, -1, -2, -3
+GLINT_EHIP, GLINT_EUNSUPPORTED, GLINT_ENOMEM = -4, -5, -6
+MAX_MATERIALS, MAX_LIGHTS = 32, 16
+
+
+class GlintError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib().glint_status_string(status).decode()
+        if status == GLINT_EHIP:
+            msg += f" (hipError {lib().glint_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]")
+        self.status = status
+
+
+class _GBuf(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("stride", C.c_int64)] + \
+               [(n, C.c_void_p) for n in PLANES] + \
+               [("material_id", C.c_void_p), ("alpha_px", C.c_void_p), ("log10_density_px", C.c_void_p)]
+
+
+class _Mat(C.Structure):
+    _fields_ = [("ndf", C.c_int32), ("alpha", C.c_float), ("R", C.c_float), ("log10_density", C.c_float),
+                ("micro_roughness", C.c_float), ("F0", C.c_float), ("seed", C.c_uint32)]
+
+
+class _Light(C.Structure):
+    _fields_ = [("dir", C.c_float * 3), ("radiance", C.c_float * 3)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("k_max", C.c_int32), ("n_probe_max", C.c_int32), ("rounding", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+DEBUG_FIELDS = (("flags", torch.int32), ("n_probe", torch.int32), ("level", torch.int32),
+                ("cell", torch.int32), ("key_sum", torch.int32), ("akey_sum", torch.int32),
+                ("theta_sum", torch.int32), ("count_sum", torch.int32), ("n_open", torch.int32),
+                ("n_gate", torch.int32))
+
+
+class _Debug(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n, _ in DEBUG_FIELDS] + [("b_light", C.c_void_p)]
+
+
+class _Tune(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libglint.so (built by paper_2306_05051_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2306_05051_amd.build` "
+                               "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.glint_shade.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
+                                  C.POINTER(_Params), vp, C.POINTER(_Debug), vp]
+        L.glint_backward_workspace_bytes.argtypes = [i32, i32, i32, i32]
+        L.glint_backward_workspace_bytes.restype = C.c_size_t
+        L.glint_shade_backward.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
+                                           C.POINTER(_Params), vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.glint_plan_create.argtypes = [C.POINTER(_GBuf), C.POINTER(vp), i32, C.POINTER(_Mat), i32,
+                                        C.POINTER(_Light), i32, C.POINTER(_Params), C.POINTER(_Tune),
+                                        C.POINTER(vp)]
+        L.glint_shade_batched.argtypes = [vp, i32, vp]
+        L.glint_plan_destroy.argtypes = [vp]
+        L.glint_plan_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32)]
+        L.glint_texel_hash.argtypes = [vp, i64, vp, vp]
+        L.glint_hash_step.argtypes = [vp, vp, i64, vp, vp]
+        L.glint_ndtri.argtypes = [vp, i64, vp, vp]
+        L.glint_status_string.argtypes = [C.c_int]
+        L.glint_status_string.restype = C.c_char_p
+        L.glint_last_hip_error.restype = C.c_int
+        L.glint_version.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, where):
+    if status != GLINT_OK:
+        raise GlintError(status, where)
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor")
+    return t.data_ptr()
+
+
+def make_gbuffer(gb):
+    """ctypes G-buffer descriptor for a dict of CUDA tensors of shape (H, W)."""
+    H, W = gb["u"].shape
+    g = _GBuf()
+    g.width, g.height, g.stride = W, H, W
+    for n in PLANES:
+        if gb[n].shape != (H, W):
+            raise ValueError(f"plane {n} has shape {tuple(gb[n].shape)}, expected {(H, W)}")
+        setattr(g, n, _dev_ptr(gb[n], torch.float32, n))
+    g.material_id = _dev_ptr(gb["material_id"], torch.int32, "material_id") \
+        if gb.get("material_id") is not None else None
+    for n in ("alpha_px", "log10_density_px"):
+        setattr(g, n, _dev_ptr(gb[n], torch.float32, n) if gb.get(n) is not None else None)
+    return g
+
+
+def make_materials(materials):
+    arr = (_Mat * max(1, len(materials)))()
+    for i, m in enumerate(materials):
+        arr[i] = _Mat(int(m.get("ndf", 0)), float(m["alpha"]), float(m.get("R", 0.034)),
+                      float(m["log10_density"]), float(m.get("micro_roughness", 0.02)),
+                      float(m.get("F0", 1.0)), int(m.get("seed", 0)) & 0xFFFFFFFF)
+    return arr
+
+
+def make_lights(lights):
+    arr = (_Light * max(1, len(lights)))()
+    for i, l in enumerate(lights):
+        arr[i].dir[:] = [float(x) for x in l["dir"]]
+        arr[i].radiance[:] = [float(x) for x in l.get("radiance", (1.0, 1.0, 1.0))]
+    return arr
+
+
+def make_params(k_max=4, n_probe_max=21, rounding=0):
+    return _Params(int(k_max), int(n_probe_max), int(rounding), 0)
+
+
+def to_device(gb_np, device="cuda"):
+    """numpy G-buffer dict -> dict of contiguous CUDA tensors."""
+    out = {}
+    for k, v in gb_np.items():
+        if v is None:
+            continue
+        out[k] = torch.from_numpy(v).to(device).contiguous()
+    return out
+
+
+def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, out=None, debug=False,
+                stream=None):
+    """Radiance [3, H, W] float32 (and a dict of debug planes when debug=True)."""
+    L = lib()
+    g = make_gbuffer(gbuf)
+    H, W = gbuf["u"].shape
+    dev = gbuf["u"].device
+    if out is None:
+        out = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    dbg = None
+    planes = {}
+    if debug:
+        dbg = _Debug()
+        for n, dt in DEBUG_FIELDS:
+            planes[n] = torch.zeros((H, W), dtype=dt, device=dev)
+            setattr(dbg, n, planes[n].data_ptr())
+        planes["b_light"] = torch.zeros((max(1, len(lights)), H, W), dtype=torch.float32, device=dev)
+        dbg.b_light = planes["b_light"].data_ptr()
+    prm = make_params(k_max, n_probe_max, rounding)
+    st = glint_shade_raw(g, make_materials(materials), len(materials), make_lights(lights), len(lights),
+                         prm, _dev_ptr(out, torch.float32, "out"), dbg, _stream(stream))
+    _check(st, "glint_shade")
+    return (out, planes) if debug else out
+
+
+def glint_shade_raw(g, mats, n_mat, lts, n_light, prm, out_ptr, dbg, stream_ptr):
+    return lib().glint_shade(C.byref(g), mats, n_mat, lts, n_light, C.byref(prm), out_ptr,
+                             C.byref(dbg) if dbg is not None else None, stream_ptr)
+
+
+def glint_backward_workspace_bytes(width, height, n_mat, n_light):
+    return lib().glint_backward_workspace_bytes(width, height, n_mat, n_light)
+
+
+def glint_shade_backward(gbuf, materials, lights, grad_out, k_max=4, n_probe_max=21, workspace=None,
+                         stream=None):
+    """(grad_alpha[n_mat], grad_ln_density[n_mat], grad_light_dir[n_light, 3]) of
+    sum(grad_out * L) for the relaxed forward."""
+    L = lib()
+    g = make_gbuffer(gbuf)
+    H, W = gbuf["u"].shape
+    dev = gbuf["u"].device
+    nm, nl = len(materials), len(lights)
+    ga = torch.empty(nm, dtype=torch.float32, device=dev)
+    gn = torch.empty(nm, dtype=torch.float32, device=dev)
+    gd = torch.empty((nl, 3), dtype=torch.float32, device=dev)
+    nbytes = L.glint_backward_workspace_bytes(W, H, nm, nl)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(1, nbytes), dtype=torch.uint8, device=dev)
+    st = L.glint_shade_backward(C.byref(g), make_materials(materials), nm, make_lights(lights), nl,
+                                C.byref(make_params(k_max, n_probe_max, 1)),
+                                _dev_ptr(grad_out.contiguous(), torch.float32, "grad_out"),
+                                ga.data_ptr(), gn.data_ptr(), gd.data_ptr(), workspace.data_ptr(),
+                                nbytes, _stream(stream))
+    _check(st, "glint_shade_backward")
+    return ga, gn, gd
+
+
+class GlintPlan:
+    """Batched persistent shading of many views (glint_plan_create /
+    glint_shade_batched / glint_plan_destroy)."""
+
+    def __init__(self, gbufs, outs, materials, lights, k_max=4, n_probe_max=21, rounding=0, tune=None):
+        L = lib()
+        n = len(gbufs)
+        self._gb = (_GBuf * n)(*[make_gbuffer(g) for g in gbufs])
+        self._outs = (C.c_void_p * n)(*[_dev_ptr(o, torch.float32, "out") for o in outs])
+        self._keep = (gbufs, outs)
+        t = None
+        if tune is not None:
+            t = _Tune(int(tune[0]), int(tune[1]), int(tune[2]), 0)
+        h = C.c_void_p()
+        st = L.glint_plan_create(self._gb, self._outs, n, make_materials(materials), len(materials),
+                                 make_lights(lights), len(lights),
+                                 C.byref(make_params(k_max, n_probe_max, rounding)),
+                                 C.byref(t) if t is not None else None, C.byref(h))
+        _check(st, "glint_plan_create")
+        self._h = h
+
+    def run(self, use_graph=True, stream=None):
+        _check(lib().glint_shade_batched(self._h, int(bool(use_graph)), _stream(stream)), "glint_shade_batched")
+
+    def info(self):
+        nt, nb = C.c_int64(), C.c_int32()
+        _check(lib().glint_plan_info(self._h, C.byref(nt), C.byref(nb)), "glint_plan_info")
+        return nt.value, nb.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().glint_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def glint_texel_hash(keys, stream=None):
+    """keys: int32 CUDA tensor [n, 9] (seed, l, k, m, i, j, ai, aj, slot) -> uint32 as int32 [n]."""
+    n = keys.shape[0]
+    out = torch.empty(n, dtype=torch.int32, device=keys.device)
+    _check(lib().glint_texel_hash(_dev_ptr(keys, torch.int32, "keys"), n, out.data_ptr(), _stream(stream)),
+           "glint_texel_hash")
+    return out
+
+
+def glint_hash_step(h, w, stream=None):
+    n = h.numel()
+    out = torch.empty(n, dtype=torch.int32, device=h.device)
+    _check(lib().glint_hash_step(_dev_ptr(h, torch.int32, "h"), _dev_ptr(w, torch.int32, "w"), n,
+                                 out.data_ptr(), _stream(stream)), "glint_hash_step")
+    return out
+
+
+def glint_ndtri(bits, stream=None):
+    n = bits.numel()
+    out = torch.empty(n, dtype=torch.float32, device=bits.device)
+    _check(lib().glint_ndtri(_dev_ptr(bits, torch.int32, "bits"), n, out.data_ptr(), _stream(stream)),
+           "glint_ndtri")
+    return out

@@ -260,15 +260,10 @@ def four_k(W=3840, H=2160, seed=3, n_mat=8, n_light=4, tile=16, grazing_frac=0.3
     g = redraw_ratio(g, np.where(left, r_tile, r_pix))
     sites = rng.uniform(0, 1, (64, 2)) * np.array([W, H])
     labels = rng.integers(0, n_mat, 64)
+    from scipy.spatial import cKDTree
     yy, xx = np.mgrid[0:H, 0:W]
-    best = np.full((H, W), np.inf)
-    site = np.zeros((H, W), np.int64)
-    for s in range(64):
-        d2 = (xx + 0.5 - sites[s, 0]) ** 2 + (yy + 0.5 - sites[s, 1]) ** 2
-        closer = d2 < best
-        best = np.where(closer, d2, best)
-        site = np.where(closer, s, site)
-    mat_map = labels[site].astype(np.int32)
+    _, site = cKDTree(sites).query(np.stack([xx.ravel() + 0.5, yy.ravel() + 0.5], -1))
+    mat_map = labels[site.reshape(H, W)].astype(np.int32)
     g["material_id"] = np.where(g["material_id"] >= 0, mat_map, -1).astype(np.int32)
     mats = [dict(ndf=0, alpha=float(rng.uniform(0.02, 0.6)), R=DEFAULT_R,
                  log10_density=float(rng.uniform(3.0, 8.0)), micro_roughness=DEFAULT_MICRO,

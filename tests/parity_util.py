@@ -1,0 +1,50 @@
+"""Comparison of the HIP path with the FP64 oracle (shared by the GPU tests).
+
+Bar (from the method's exactness claims): texel keys, hash outputs and flake
+counts bit-exact, radiance within 1e-4 relative, on every pixel whose
+discrete decisions all sit at least 1e-5 from their boundary (the oracle's
+margin, in each decision's own units); pixels nearer a boundary are counted
+and reported, not compared.  A decision value lying exactly on its boundary
+(margin 0: exact arithmetic on both sides, e.g. an axis-aligned isotropic
+footprint) is compared like any other.
+"""
+import numpy as np
+
+MARGIN = 1e-5
+RTOL = 1e-4
+
+EXACT = ("n_probe", "level", "cell", "key_sum", "akey_sum", "theta_sum", "count_sum", "n_open", "n_gate")
+
+
+def compare(gpu_rgb, gpu_dbg, ref_rgb, ref_dbg, exact_fields=EXACT, rtol=RTOL, label=""):
+    """Returns a dict of statistics; raises AssertionError on a parity failure."""
+    gflags = gpu_dbg["flags"].astype(np.uint32)
+    rflags = ref_dbg["flags"].astype(np.uint32)
+    assert np.array_equal(gflags & ~np.uint32(4), rflags & ~np.uint32(4)), \
+        f"{label}: flags differ on {np.count_nonzero(gflags != rflags)} pixels"
+    shaded = (rflags & 1) > 0
+    m = ref_dbg["margin"]
+    ok = shaded & ((m >= MARGIN) | (m == 0.0))
+    for k in exact_fields:
+        a = gpu_dbg[k].astype(np.int64) & 0xFFFFFFFF
+        b = ref_dbg[k].astype(np.int64) & 0xFFFFFFFF
+        bad = ok & (a != b)
+        assert not bad.any(), (f"{label}: {k} differs on {bad.sum()} of {ok.sum()} pixels, "
+                               f"first at {np.argwhere(bad)[:3].tolist()}")
+    g = gpu_rgb.astype(np.float64)
+    err = np.abs(g - ref_rgb)
+    lim = rtol * np.abs(ref_rgb)
+    bad = (err > lim)[:, ok]
+    worst = float(np.max(err[:, ok] / np.maximum(np.abs(ref_rgb[:, ok]), 1e-300))) if ok.any() else 0.0
+    assert not bad.any(), f"{label}: radiance off on {bad.sum()} channel-pixels, worst rel {worst:.3e}"
+    # pixels that are not shaded are exactly zero on both sides
+    assert np.all(g[:, ~shaded] == 0.0)
+    stats = dict(shaded=int(shaded.sum()), checked=int(ok.sum()), near_boundary=int((shaded & ~ok).sum()),
+                 worst_rel=worst, nonzero=int((ref_rgb[0] > 0).sum()))
+    kinds = ref_dbg["margin_kind"][shaded & ~ok]
+    stats["near_boundary_kinds"] = {int(k): int(c) for k, c in zip(*np.unique(kinds, return_counts=True))}
+    return stats
+
+
+def dbg_to_numpy(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}

@@ -1,0 +1,225 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Run on an MI355X:  python -u -m pytest tests -m gpu -x -v --timeout 120 --timeout-method thread
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_05051_amd import scenes
+from parity_util import compare, dbg_to_numpy
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hash_vectors.txt")
+
+
+@pytest.fixture(scope="module")
+def glint():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_05051_amd import glint as g
+    g.lib()
+    return g
+
+
+def _run(glint, gb, mats, lights, **kw):
+    print(f"  gpu: {gb['u'].shape} mats={len(mats)} lights={len(lights)} {kw}", flush=True)
+    dgb = glint.to_device(gb)
+    rgb, dbg = glint.glint_shade(dgb, mats, lights, debug=True, **kw)
+    rgb2 = glint.glint_shade(dgb, mats, lights, **kw)
+    torch.cuda.synchronize()
+    # the production kernel (which skips gates that cannot open) gives the same bits
+    assert torch.equal(rgb, rgb2)
+    return rgb.cpu().numpy(), dbg_to_numpy(dbg)
+
+
+def _check(glint, gb, mats, lights, label, **kw):
+    grgb, gdbg = _run(glint, gb, mats, lights, **kw)
+    rrgb, rdbg = oracle.shade(gb, mats, lights, debug=True, **kw)
+    st = compare(grgb, gdbg, rrgb, rdbg, label=label)
+    print(f"  {label}: {st}", flush=True)
+    assert st["checked"] > 0.9 * st["shaded"]
+    return st
+
+
+def test_hash_vectors_bit_exact(glint):
+    steps, texels = [], []
+    for line in open(GOLDEN):
+        if line.startswith("#"):
+            continue
+        f = line.split()
+        if f[0] == "step":
+            steps.append([int(f[1], 16), int(f[2], 16), int(f[3], 16)])
+        else:
+            texels.append([int(f[1], 16)] + [int(x) for x in f[2:10]] + [int(f[10], 16)])
+    s = np.array(steps, dtype=np.uint64)
+    h = torch.from_numpy(s[:, 0].astype(np.uint32).view(np.int32)).cuda()
+    w = torch.from_numpy(s[:, 1].astype(np.uint32).view(np.int32)).cuda()
+    out = glint.glint_hash_step(h, w).cpu().numpy().view(np.uint32)
+    assert np.array_equal(out, s[:, 2].astype(np.uint32))
+    t = np.array(texels, dtype=np.int64)
+    keys = t[:, :9].copy()
+    keys[:, 0] = keys[:, 0].astype(np.uint32).view(np.int32) if False else keys[:, 0]
+    k32 = np.empty((len(t), 9), np.int32)
+    k32[:, 0] = t[:, 0].astype(np.uint32).view(np.int32)
+    k32[:, 1:] = t[:, 1:9].astype(np.int32)
+    out = glint.glint_texel_hash(torch.from_numpy(k32).cuda()).cpu().numpy().view(np.uint32)
+    assert np.array_equal(out, t[:, 9].astype(np.uint32))
+
+
+def test_inverse_cdf_accuracy_all_uniforms(glint):
+    from scipy.special import ndtri
+    k = np.arange(2**23, dtype=np.int64)
+    bits = torch.from_numpy(((k << 9) | 0x155).astype(np.uint32).view(np.int32)).cuda()
+    z = glint.glint_ndtri(bits).cpu().numpy().astype(np.float64)
+    q = (2.0 * k + 1.0) * 2.0**-24
+    ref = ndtri(q)
+    err = np.abs(z - ref) / np.maximum(np.abs(ref), 1.0)
+    print("  max err", err.max(), "at q", q[err.argmax()])
+    assert err.max() < 1e-6
+
+
+@pytest.mark.parametrize("tilt", [0.0, 45.0, 80.0])
+def test_plane_256(glint, tilt):
+    gb, mats, lights = scenes.plain_forward(256, 256, tilt_deg=tilt, seed=int(tilt))
+    _check(glint, gb, mats, lights, f"plane tilt {tilt}")
+
+
+def test_plane_256_brighter(glint):
+    # light placed near the mirror direction so that many gates open
+    gb, mats, lights = scenes.plain_forward(256, 256, tilt_deg=30.0, seed=1)
+    lights = [dict(dir=(0.0, 0.45, 0.89), radiance=(1.0, 0.8, 0.6))]
+    mats = [dict(mats[0], log10_density=7.0)]
+    st = _check(glint, gb, mats, lights, "plane bright")
+    assert st["nonzero"] > 1000
+
+
+def test_sphere_scattered_anisotropy(glint):
+    gb, mats, lights = scenes.sphere_forward(320, 180, seed=1)
+    _check(glint, gb, mats, lights, "sphere 320x180")
+
+
+def test_sphere_geometric_footprints(glint):
+    gb, mats, lights = scenes.sphere_forward(256, 160, seed=2, redraw=False)
+    _check(glint, gb, mats, lights, "sphere geometric")
+
+
+def test_four_k_like_small(glint):
+    gb, mats, lights = scenes.four_k(256, 144, seed=3)
+    st = _check(glint, gb, mats, lights, "4k-like 256x144")
+
+
+@pytest.mark.parametrize("k_max,n_probe_max", [(0, 21), (1, 21), (2, 8), (4, 1), (3, 64)])
+def test_grid_family_variants(glint, k_max, n_probe_max):
+    gb, mats, lights = scenes.four_k(96, 80, seed=5, n_light=2)
+    _check(glint, gb, mats, lights, f"K={k_max} nmax={n_probe_max}", k_max=k_max, n_probe_max=n_probe_max)
+
+
+def test_relaxed_counts(glint):
+    gb, mats, lights = scenes.four_k(128, 72, seed=6, n_light=3)
+    fields = ("n_probe", "level", "cell", "key_sum", "akey_sum", "theta_sum", "n_open", "n_gate")
+    grgb, gdbg = _run(glint, gb, mats, lights, rounding=1)
+    rrgb, rdbg = oracle.shade(gb, mats, lights, debug=True, rounding=1)
+    st = compare(grgb, gdbg, rrgb, rdbg, exact_fields=fields, label="relaxed")
+    print(" ", st)
+
+
+def test_ragged_and_invalid_pixels(glint):
+    gb, mats, lights = scenes.ragged_plane(37, 29, seed=1)
+    gb = {k: v.copy() for k, v in gb.items()}
+    inside = np.argwhere(gb["material_id"] >= 0)
+    (a, b, c, d, e) = [tuple(inside[i]) for i in np.linspace(0, len(inside) - 1, 5).astype(int)]
+    gb["u"][a] = np.nan                          # non-finite input
+    for k in ("dudx", "dudy", "dvdx", "dvdy"):   # det J = 0
+        gb[k][b] = 0.0
+    gb["wz"][c] = -1.0; gb["wx"][c] = 0.0; gb["wy"][c] = 0.0   # view below surface
+    gb["material_id"][d] = 7                     # >= n_mat
+    gb["material_id"][e] = -3                    # skipped
+    grgb, gdbg = _run(glint, gb, mats, lights)
+    rrgb, rdbg = oracle.shade(gb, mats, lights, debug=True)
+    compare(grgb, gdbg, rrgb, rdbg, label="ragged")
+    for (y, x), bit in ((a, 8), (b, 8), (c, 16), (d, 64), (e, 32)):
+        assert gdbg["flags"][y, x] == bit
+        assert np.all(grgb[:, y, x] == 0.0)
+
+
+def test_no_lights_and_empty(glint):
+    gb, mats, lights = scenes.ragged_plane(19, 11, seed=2)
+    dgb = glint.to_device(gb)
+    out = glint.glint_shade(dgb, mats, [])
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(out).item() == 0
+    empty = {k: v[:0] for k, v in dgb.items()}
+    out = glint.glint_shade(empty, mats, lights)
+    assert out.numel() == 0
+
+
+def test_bad_arguments_rejected(glint):
+    gb, mats, lights = scenes.ragged_plane(8, 8, seed=3)
+    dgb = glint.to_device(gb)
+    with pytest.raises(glint.GlintError) as e:
+        glint.glint_shade(dgb, [dict(mats[0], alpha=-1.0)], lights)
+    assert e.value.status == glint.GLINT_EINVAL
+    with pytest.raises(glint.GlintError) as e:
+        glint.glint_shade(dgb, mats, lights, k_max=5)
+    assert e.value.status == glint.GLINT_EINVAL
+    with pytest.raises(glint.GlintError) as e:
+        glint.glint_shade(dgb, mats, lights * 9)
+    assert e.value.status == glint.GLINT_EINVAL
+
+
+def test_deterministic(glint):
+    gb, mats, lights = scenes.four_k(128, 128, seed=7)
+    dgb = glint.to_device(gb)
+    a = glint.glint_shade(dgb, mats, lights)
+    b = glint.glint_shade(dgb, mats, lights)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_full_4k_sampled_rows(glint):
+    """Full-size 3840x2160 frame in the benchmark's launch configuration;
+    the oracle recomputes sampled rows."""
+    gb, mats, lights = scenes.four_k(3840, 2160, seed=3)
+    dgb = glint.to_device(gb)
+    print("  full 4K frame", flush=True)
+    rgb = glint.glint_shade(dgb, mats, lights)
+    torch.cuda.synchronize()
+    rgb = rgb.cpu().numpy()
+    rows = [0, 7, 8, 500, 1079, 1080, 1501, 2159]
+    for r in rows:
+        sub = {k: v[r:r + 1] for k, v in gb.items()}
+        rrgb, rdbg = oracle.shade(sub, mats, lights, debug=True)
+        ok = ((rdbg["flags"] & 1) > 0) & (rdbg["margin"] >= 1e-5)
+        g = rgb[:, r:r + 1].astype(np.float64)
+        err = np.abs(g - rrgb)[:, ok]
+        assert np.all(err <= 1e-4 * np.abs(rrgb[:, ok])), f"row {r}"
+        assert np.all(g[:, ~((rdbg["flags"] & 1) > 0)] == 0)
+
+
+def test_batched_bit_identical_to_per_view(glint):
+    views, mats, lights = scenes.batched_views(n_views=9, seed=1, side_min=40, side_max=300)
+    dviews = [glint.to_device(v) for v in views]
+    ref = [glint.glint_shade(v, mats, lights) for v in dviews]
+    outs = [torch.full((3,) + v["u"].shape, -1.0, device="cuda") for v in dviews]
+    plan = glint.GlintPlan(dviews, outs, mats, lights)
+    for use_graph in (False, True, True):
+        for o in outs:
+            o.fill_(-1.0)
+        plan.run(use_graph=use_graph)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, outs):
+            assert torch.equal(a, b)
+    for tune in ((16, 4, 2), (64, 1, 4), (32, 2, 1)):
+        p2 = glint.GlintPlan(dviews, outs, mats, lights, tune=tune)
+        p2.run(use_graph=False)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, outs):
+            assert torch.equal(a, b)
+        p2.close()
+    plan.close()
