@@ -112,13 +112,15 @@ typedef struct {
  *  akey_sum   sum (mod 2^32) of the angular key hashes (slot 0) of every light
  *  theta_sum  sum (mod 2^32) of every gate hash (all 48 per probe and light)
  *  count_sum  sum of all integer counts (rounding 0)
- *  n_open     number of open gates; n_gate: number of gated binomials
+ *  n_open     number of open gates; n_gate: number of gated binomials;
+ *             n_live: gated binomials whose gate probability reaches the
+ *             smallest uniform 2^-24 (the others cannot open)
  *  b_light    [n_light][height*stride] distributed count sum b per light
  * Asking for debug planes runs an instrumented kernel (slower, same image). */
 typedef struct {
     uint32_t *flags;
     int32_t *n_probe, *level;
-    uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate;
+    uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
 } glint_debug;
 

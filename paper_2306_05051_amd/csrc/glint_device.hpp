@@ -58,7 +58,7 @@ struct ViewDesc {
 struct DebugPlanes {
     uint32_t *flags;
     int32_t *n_probe, *level;
-    uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate;
+    uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
 };
 

@@ -36,7 +36,7 @@ int set_hip_error(hipError_t e)
 
 struct ItemOut {
     float rgb[3];
-    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate;
+    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate, n_live;
     float b[kMaxLight];
 };
 
@@ -49,7 +49,7 @@ __device__ __forceinline__ void shade_item(const Pixel &px, int kp, const Shared
 {
     o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
     if (DEBUG) {
-        o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = 0;
+        o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
     }
     const DevMaterial &M = sh.mats[px.mat];
@@ -126,7 +126,7 @@ __device__ __forceinline__ void shade_item(const Pixel &px, int kp, const Shared
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     const uint32_t h0 = hstep(pre[g][e], ak0[a]);
-                    if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; }
+                    if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_live += K ? 1u : 0u; }
                     if ((h0 >> 9) < K) {                       // theta0 < P>=1 (Eq. 18 gate)
                         const uint32_t h1 = hstep(pre[g][e], ak1[a]);
                         const float x = fmaf(sg, ndtri_bits(h1), mu1);
@@ -208,7 +208,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     sm.off[lane] = off;
     __syncthreads();
     float acc[3] = {0.0f, 0.0f, 0.0f};
-    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0;
+    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0;
     float db[kMaxLight];
     if (DEBUG)
         for (int l = 0; l < kMaxLight; ++l) db[l] = 0.0f;
@@ -234,6 +234,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                 sm.slot[lane].count_sum = o.count_sum;
                 sm.slot[lane].n_open = o.n_open;
                 sm.slot[lane].n_gate = o.n_gate;
+                sm.slot[lane].n_live = o.n_live;
                 for (int l = 0; l < kMaxLight; ++l) sm.slot[lane].b[l] = o.b[l];
             }
         }
@@ -247,6 +248,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                 acc[2] += s.rgb[2];
                 if (DEBUG) {
                     dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
+                    dnl += s.n_live;
                     for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
                 }
             }
@@ -269,6 +271,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             if (dp.count_sum) dp.count_sum[idx] = dcs;
             if (dp.n_open) dp.n_open[idx] = dno;
             if (dp.n_gate) dp.n_gate[idx] = dng;
+            if (dp.n_live) dp.n_live[idx] = dnl;
             if (dp.b_light)
                 for (int l = 0; l < sh.n_light; ++l) dp.b_light[l * npx + idx] = db[l];
         }
@@ -407,7 +410,7 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     hipStream_t st = (hipStream_t)stream;
     if (dbg) {
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
-                          dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->b_light};
+                          dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light};
         hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp, tile_w,
                            tiles_x);
     } else {

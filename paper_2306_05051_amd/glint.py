@@ -58,7 +58,7 @@ class _Params(C.Structure):
 DEBUG_FIELDS = (("flags", torch.int32), ("n_probe", torch.int32), ("level", torch.int32),
                 ("cell", torch.int32), ("key_sum", torch.int32), ("akey_sum", torch.int32),
                 ("theta_sum", torch.int32), ("count_sum", torch.int32), ("n_open", torch.int32),
-                ("n_gate", torch.int32))
+                ("n_gate", torch.int32), ("n_live", torch.int32))
 
 
 class _Debug(C.Structure):
