@@ -1,15 +1,326 @@
-// glint_bwd.hip -- adjoint of the relaxed forward (placeholder until the
-// adjoint kernel lands; reports EUNSUPPORTED).
+// glint_bwd.hip -- adjoint of the relaxed glint forward for gfx950 and the C
+// ABI entry points glint_backward_workspace_bytes / glint_shade_backward.
+//
+// The adjoint recomputes the forward at the current parameters, so every
+// discrete decision (probe split, area level, ratio/orientation cell,
+// triangle, tetrahedron, lattice triangle, angular cell, gate, the max(1,x)
+// clamp and the p <= 1 clamp) is exactly the forward's; only the continuous
+// part of the relaxed count c = max(1, 1 + mu + sigma z) is differentiated
+// (straight-through floor).  Parameters: each material's roughness alpha
+// and log flake density ln N, each light's raw direction.
+//
+// Reduction (deterministic): per light, a butterfly wave sum (every lane ends
+// with the same bits); per material, fixed-order LDS sums; per tile, one
+// partial row in the workspace; a second kernel sums the rows in FP64 in a
+// fixed order.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
+#include "glint_device.hpp"
 #include "glint_host.hpp"
+
+namespace glint {
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// d Lambda / d c and d Lambda / d alpha for direction cosine c (Smith, Eq. 2)
+__device__ __forceinline__ void smith_lambda_grad(int ndf, float alpha, float c, float s2, float &dl_dc,
+                                                  float &dl_da)
+{
+    if (s2 <= 0.0f) { dl_dc = 0.0f; dl_da = 0.0f; return; }
+    const float a2 = alpha * alpha;
+    const float T = s2 / (c * c);
+    if (ndf == 0) {
+        const float S = sqrtf(1.0f + a2 * T);
+        dl_dc = -a2 / (2.0f * c * c * c * S);
+        dl_da = alpha * T / (2.0f * S);
+    } else {
+        const float a = 1.0f / (alpha * sqrtf(T));
+        const float dl_dacoef = -expf(-a * a) / (2.0f * a * a * 1.7724538509055160f);
+        dl_dc = dl_dacoef / (alpha * s2 * sqrtf(s2));
+        dl_da = dl_dacoef * (-a / alpha);
+    }
+}
+
+struct MatSlot {
+    int mat;
+    float da, dn;
+};
+
+struct BwdSmem {
+    int off[kWave];
+    MatSlot ms[kWave];
+    float dd[kMaxLight][3];
+};
+
+// one (pixel, probe) item: accumulates d/d alpha and d/d ln N of the pixel's
+// material into da, dn, and d/d dir of each light into sm.dd (wave-reduced).
+// Called by every lane of the wave (live = false contributes zeros).
+__device__ void grad_item(bool live, const Pixel &px, int kp, const Shared &sh, const float gout[3],
+                          float &da, float &dn, BwdSmem &sm)
+{
+    da = 0.0f;
+    dn = 0.0f;
+    const int lane = threadIdx.x;
+    const DevMaterial &M = sh.mats[live ? px.mat : 0];
+    uint32_t pre[4][3];
+    float beta[4][3];
+    const int nn = live ? px.n_nodes : 0;
+    if (live) {
+        const double off = ((double)kp + 0.5) / (double)px.npr - 0.5;
+        const double cx = px.u + off * px.ex, cy = px.v + off * px.ey;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            if (g < nn) {
+                int vi[3], vj[3];
+                simplex_locate(cx, cy, px.nl[g], px.nk[g], px.nm[g], sh, vi, vj, beta[g]);
+                const uint32_t base = hstep(M.root, node_word(px.nl[g], px.nk[g], px.nm[g]));
+#pragma unroll
+                for (int e = 0; e < 3; ++e) pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
+            }
+        }
+    }
+    double tt[3] = {0, 0, 0}, bb[3] = {0, 0, 0};
+    float kpx = 0.0f, lam_i = 0.0f, dli_dc = 0.0f, dli_da = 0.0f;
+    const float alpha = live ? px.alpha : 1.0f;
+    if (live) {
+        onb(px.n, tt, bb);
+        kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha * (double)px.alpha * 4.0 *
+                             px.cos_i));
+        const float ci = (float)px.cos_i, si2 = (float)(1.0 - px.cos_i * px.cos_i);
+        lam_i = smith_lambda(M.ndf, alpha, ci, si2);
+        smith_lambda_grad(M.ndf, alpha, ci, si2, dli_dc, dli_da);
+    }
+    const float inv_micro = (float)M.inv_micro;
+    for (int li = 0; li < sh.n_light; ++li) {
+        const DevLight &L = sh.lights[li];
+        float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
+        LightEval le;
+        if (live && eval_light(px, L, M, tt, bb, le)) {
+            const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
+            const float dvx[4] = {-le.gy, le.gy, -le.fy, le.fy};
+            const float dvy[4] = {-le.gx, -le.fx, le.gx, le.fx};
+            const float v[4] = {le.gx * le.gy, le.fx * le.gy, le.gx * le.fy, le.fx * le.fy};
+            uint32_t ak0[4], ak1[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
+                ak1[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
+            }
+            const float p = le.p;
+            const float lp = log1pf(-p);
+            float B = 0.0f, Bp = 0.0f, Bm = 0.0f, Bfx = 0.0f, Bfy = 0.0f;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (g >= nn) continue;
+                NodeEval ne;
+                eval_node(px.nw[g], px.nl[g], px.N, p, lp, ne);
+                if (ne.K == 0u) continue;
+                const float dmdl = ne.n > 1.0f ? ne.n : 0.0f;          // d m / d ln N
+                const float isg = ne.sg > 0.0f ? 0.5f / ne.sg : 0.0f;
+                const float dsdp = ne.m * (1.0f - 2.0f * p) * isg;       // d sigma / d p
+                const float dsdm = p * (1.0f - p) * isg;                 // d sigma / d m
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const uint32_t h0 = hstep(pre[g][e], ak0[a]);
+                        if ((h0 >> 9) < ne.K) {
+                            const uint32_t h1 = hstep(pre[g][e], ak1[a]);
+                            const float z = ndtri_bits(h1);
+                            const float x = fmaf(ne.sg, z, ne.mu1);
+                            const float be = beta[g][e];
+                            if (x >= 1.0f) {                 // relaxed count c = x
+                                const float bv = be * v[a];
+                                B = fmaf(bv, x, B);
+                                Bp = fmaf(bv, ne.m + z * dsdp, Bp);
+                                Bm = fmaf(bv, (p + z * dsdm) * dmdl, Bm);
+                                Bfx = fmaf(be * dvx[a], x, Bfx);
+                                Bfy = fmaf(be * dvy[a], x, Bfy);
+                            } else {                          // clamped: c = 1
+                                B = fmaf(be, v[a], B);
+                                Bfx += be * dvx[a];
+                                Bfy += be * dvy[a];
+                            }
+                        }
+                    }
+                }
+            }
+            // derivatives of p (Eq. 4) with respect to alpha and c2 = <n,h>^2
+            const float c2 = (float)(le.ch * le.ch), s2 = (float)(1.0 - le.ch * le.ch);
+            const float a2 = alpha * alpha;
+            float dp_da = 0.0f, dp_dc2 = 0.0f;
+            if (!le.pclamp && p > 0.0f) {
+                if (M.ndf == 0) {
+                    const float d = s2 + c2 * a2;
+                    dp_da = 4.0f * p / alpha * (1.0f - a2 * c2 / d);
+                    dp_dc2 = 2.0f * p * (1.0f - a2) / d;
+                } else {
+                    dp_da = 2.0f * p * s2 / (c2 * a2 * alpha);
+                    dp_dc2 = p * (1.0f / (c2 * c2 * a2) - 2.0f / c2);
+                }
+            }
+            const float co = (float)le.cos_o, so2 = (float)(1.0 - le.cos_o * le.cos_o);
+            float dlo_dc, dlo_da;
+            smith_lambda_grad(M.ndf, alpha, co, so2, dlo_dc, dlo_da);
+            const float G = 1.0f / ((1.0f + lam_i) * (1.0f + le.lam_o));
+            const float dG_da = -G * (dli_da / (1.0f + lam_i) + dlo_da / (1.0f + le.lam_o));
+            const float sk = s * kpx;
+            da += sk * (le.F * dG_da * B + le.F * G * Bp * dp_da) - 2.0f * sk * le.F * G * B / alpha;
+            dn += sk * le.F * G * (Bm - B);
+            // gradient with respect to the unit half vector h
+            const float om = (float)(1.0 - (px.wi[0] * le.h[0] + px.wi[1] * le.h[1] + px.wi[2] * le.h[2]));
+            const float dF = -5.0f * (1.0f - M.F0) * om * om * om * om * G * B;   // times wi
+            const float cn = sk * le.F * G * Bp * dp_dc2 * 2.0f * (float)le.ch;   // times n
+            const float ct = sk * le.F * G * Bfx * inv_micro;                      // times t
+            const float cb = sk * le.F * G * Bfy * inv_micro;                      // times b
+            float gh[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                gh[c] = sk * dF * (float)px.wi[c] + cn * (float)px.n[c] + ct * (float)tt[c] + cb * (float)bb[c];
+            // direct dependence on wo through Lambda(<n,wo>)
+            const float gon = sk * le.F * B * (-G / (1.0f + le.lam_o)) * dlo_dc;
+            // h = (wi + wo)/|wi + wo|, wo = d/|d|: chain through both normalisations
+            const float hx = (float)le.h[0], hy = (float)le.h[1], hz = (float)le.h[2];
+            const float hd = gh[0] * hx + gh[1] * hy + gh[2] * hz;
+            const float ihl = (float)(1.0 / le.hl);
+            const float gw[3] = {(gh[0] - hd * hx) * ihl + gon * (float)px.n[0],
+                           (gh[1] - hd * hy) * ihl + gon * (float)px.n[1],
+                           (gh[2] - hd * hz) * ihl + gon * (float)px.n[2]};
+            const float wx = (float)L.wo[0], wy = (float)L.wo[1], wz = (float)L.wo[2];
+            const float wd = gw[0] * wx + gw[1] * wy + gw[2] * wz;
+            const float idl = L.inv_len;
+            gdx = (gw[0] - wd * wx) * idl;
+            gdy = (gw[1] - wd * wy) * idl;
+            gdz = (gw[2] - wd * wz) * idl;
+        }
+        gdx = wave_sum(gdx);
+        gdy = wave_sum(gdy);
+        gdz = wave_sum(gdz);
+        if (lane == 0) {
+            sm.dd[li][0] += gdx;
+            sm.dd[li][1] += gdy;
+            sm.dd[li][2] += gdz;
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, const float *gout, int tiles_x,
+                                                       float *partials, int n_par)
+{
+    __shared__ BwdSmem sm;
+    const int lane = threadIdx.x;
+    const int tile_w = 8, tile_h = 8;
+    const int x0 = (blockIdx.x % tiles_x) * tile_w, y0 = (blockIdx.x / tiles_x) * tile_h;
+    const int x = x0 + (lane % tile_w), y = y0 + (lane / tile_w);
+    const bool inb = (x < vw.width) && (y < vw.height);
+    const int64_t idx = (int64_t)y * vw.stride + x;
+    const int64_t npx = (int64_t)vw.height * vw.stride;
+    Pixel px;
+    px.flags = 0;
+    px.npr = 0;
+    if (inb) setup_pixel<false>(vw, idx, sh, px);
+    const int npr = (px.flags & F_SHADED) ? px.npr : 0;
+    int incl = npr;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+    }
+    const int S = __shfl(incl, kWave - 1);
+    sm.off[lane] = incl - npr;
+    if (lane < kMaxLight * 3) (&sm.dd[0][0])[lane] = 0.0f;
+    __syncthreads();
+    float acc_a = 0.0f, acc_n = 0.0f;          // lane m < n_mat: material m
+    for (int base = 0; base < S; base += kWave) {
+        const int q = base + lane;
+        const bool live = q < S;
+        Pixel ip;
+        int kp = 0;
+        float g3[3] = {0.0f, 0.0f, 0.0f};
+        ip.flags = 0;
+        if (live) {
+            int p = 0;
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1)
+                if (sm.off[p + st] <= q) p += st;
+            kp = q - sm.off[p];
+            const int px_x = x0 + (p % tile_w), px_y = y0 + (p / tile_w);
+            const int64_t pidx = (int64_t)px_y * vw.stride + px_x;
+            setup_pixel<false>(vw, pidx, sh, ip);
+            g3[0] = gout[pidx];
+            g3[1] = gout[npx + pidx];
+            g3[2] = gout[2 * npx + pidx];
+        }
+        float da, dn;
+        grad_item(live, ip, kp, sh, g3, da, dn, sm);
+        sm.ms[lane].mat = live ? ip.mat : -1;
+        sm.ms[lane].da = da;
+        sm.ms[lane].dn = dn;
+        __syncthreads();
+        if (lane < sh.n_mat) {
+            for (int j = 0; j < kWave; ++j) {
+                if (sm.ms[j].mat == lane) {
+                    acc_a += sm.ms[j].da;
+                    acc_n += sm.ms[j].dn;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *row = partials + (int64_t)blockIdx.x * n_par;
+    if (lane < sh.n_mat) {
+        row[2 * lane] = acc_a;
+        row[2 * lane + 1] = acc_n;
+    }
+    if (lane < 3 * sh.n_light) row[2 * sh.n_mat + lane] = (&sm.dd[0][0])[lane];
+}
+
+// sum column c of partials[n_rows][n_par] in FP64, fixed order, one block per column
+__global__ __launch_bounds__(256) void glint_bwd_reduce(const float *partials, int64_t n_rows, int n_par,
+                                                        int n_mat, float *g_alpha, float *g_lnN, float *g_dir)
+{
+    __shared__ double s[256];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t r = threadIdx.x; r < n_rows; r += 256) acc += (double)partials[r * n_par + c];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float v = (float)s[0];
+        if (c < 2 * n_mat) {
+            if (c & 1) g_lnN[c >> 1] = v; else g_alpha[c >> 1] = v;
+        } else {
+            g_dir[c - 2 * n_mat] = v;
+        }
+    }
+}
+
+static int64_t bwd_tiles(int32_t width, int32_t height)
+{
+    return (int64_t)((width + 7) / 8) * ((height + 7) / 8);
+}
+
+}  // namespace glint
+
+using namespace glint;
 
 extern "C" {
 
 size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_mat, int32_t n_light)
 {
-    (void)width; (void)height; (void)n_mat; (void)n_light;
-    return 0;
+    if (width <= 0 || height <= 0 || n_mat < 1 || n_light < 0) return 0;
+    return (size_t)bwd_tiles(width, height) * (size_t)(2 * n_mat + 3 * n_light) * sizeof(float);
 }
 
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
@@ -17,10 +328,39 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
                          const float *grad_out_rgb, float *grad_alpha, float *grad_ln_density,
                          float *grad_light_dir, void *workspace, size_t workspace_bytes, void *stream)
 {
-    (void)gbuf; (void)mats; (void)n_mat; (void)lights; (void)n_light; (void)params; (void)grad_out_rgb;
-    (void)grad_alpha; (void)grad_ln_density; (void)grad_light_dir; (void)workspace; (void)workspace_bytes;
-    (void)stream;
-    return GLINT_EUNSUPPORTED;
+    if (!params) return GLINT_ENULL;
+    glint_params prm = *params;
+    prm.rounding = 1;                            // the adjoint differentiates the relaxed counts
+    Shared sh;
+    int rc = prepare_shared(mats, n_mat, lights, n_light, &prm, sh);
+    if (rc) return rc;
+    if (!grad_alpha || !grad_ln_density || (n_light > 0 && !grad_light_dir)) return GLINT_ENULL;
+    ViewDesc vw;
+    rc = make_view(gbuf, reinterpret_cast<float *>(const_cast<float *>(grad_out_rgb)), vw);
+    if (rc) return rc;
+    if (vw.alpha_px || vw.log10N_px) return GLINT_EUNSUPPORTED;
+    const int n_par = 2 * n_mat + 3 * n_light;
+    const int64_t tiles = (int64_t)vw.width * vw.height > 0 ? bwd_tiles(vw.width, vw.height) : 0;
+    hipStream_t st = (hipStream_t)stream;
+    if (tiles == 0) {
+        // empty image: gradients are zero
+        hipError_t e = hipMemsetAsync(grad_alpha, 0, sizeof(float) * n_mat, st);
+        if (e == hipSuccess) e = hipMemsetAsync(grad_ln_density, 0, sizeof(float) * n_mat, st);
+        if (e == hipSuccess && n_light > 0) e = hipMemsetAsync(grad_light_dir, 0, sizeof(float) * 3 * n_light, st);
+        return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+    }
+    if (tiles > 0x7fffffffLL) return GLINT_ESHAPE;
+    const size_t need = (size_t)tiles * n_par * sizeof(float);
+    if (!workspace) return GLINT_ENULL;
+    if (workspace_bytes < need) return GLINT_ESHAPE;
+    const int tiles_x = (vw.width + 7) / 8;
+    float *partials = (float *)workspace;
+    hipLaunchKernelGGL(glint_bwd_kernel, dim3((unsigned)tiles), dim3(kWave), 0, st, vw, sh, grad_out_rgb, tiles_x,
+                       partials, n_par);
+    hipLaunchKernelGGL(glint_bwd_reduce, dim3((unsigned)n_par), dim3(256), 0, st, partials, tiles, n_par, n_mat,
+                       grad_alpha, grad_ln_density, grad_light_dir);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GLINT_OK : set_hip_error(e);
 }
 
 }  // extern "C"

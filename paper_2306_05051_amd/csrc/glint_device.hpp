@@ -36,6 +36,7 @@ struct DevMaterial {
 struct DevLight {
     double wo[3];             // unit direction toward the light (FP64 normalised)
     float rad[3];
+    float inv_len;            // 1 / |raw direction| (for gradients w.r.t. the raw vector)
     int32_t ok;               // 0 when the raw direction has zero length
 };
 
@@ -411,6 +412,55 @@ __device__ __forceinline__ float success_prob(int ndf, float alpha, float R, flo
     return clamped ? 1.0f : p;
 }
 
+// Everything one light needs at one pixel (shared by the forward and the
+// adjoint so that both take identical decisions).
+struct LightEval {
+    double h[3];               // half vector (FP64, unit)
+    double hl;                 // |wi + wo| before normalisation
+    double cos_o, ch;          // <n, wo>, <n, h>
+    float p;                   // success probability (Eq. 4)
+    bool pclamp;
+    int ai, aj;                // angular cell (lower-left texel)
+    float fx, fy, gx, gy;      // bilinear fractions and their complements
+    float F, lam_o;            // Schlick Fresnel, Smith Lambda of wo
+};
+
+__device__ __forceinline__ bool eval_light(const Pixel &px, const DevLight &L, const DevMaterial &M,
+                                           const double tt[3], const double bb[3], LightEval &e)
+{
+    if (!L.ok) return false;
+    e.cos_o = px.n[0] * L.wo[0] + px.n[1] * L.wo[1] + px.n[2] * L.wo[2];
+    if (!(e.cos_o > 0.0)) return false;
+    double h0 = px.wi[0] + L.wo[0], h1 = px.wi[1] + L.wo[1], h2 = px.wi[2] + L.wo[2];
+    e.hl = sqrt(h0 * h0 + h1 * h1 + h2 * h2);
+    if (!(e.hl > 0.0)) return false;
+    e.h[0] = h0 / e.hl; e.h[1] = h1 / e.hl; e.h[2] = h2 / e.hl;
+    e.ch = px.n[0] * e.h[0] + px.n[1] * e.h[1] + px.n[2] * e.h[2];
+    e.p = success_prob(M.ndf, px.alpha, M.R, (float)(e.ch * e.ch), (float)(1.0 - e.ch * e.ch), e.pclamp);
+    // angular grid over the projected half vector (Eq. 14)
+    const double ax = (e.h[0] * tt[0] + e.h[1] * tt[1] + e.h[2] * tt[2]) * M.inv_micro - 0.5;
+    const double ay = (e.h[0] * bb[0] + e.h[1] * bb[1] + e.h[2] * bb[2]) * M.inv_micro - 0.5;
+    const double fax = floor(ax), fay = floor(ay);
+    e.ai = (int)fax; e.aj = (int)fay;
+    // bilinear fractions; both complements from FP64 so small weights stay accurate
+    e.fx = (float)(ax - fax); e.fy = (float)(ay - fay);
+    e.gx = (float)(fax + 1.0 - ax); e.gy = (float)(fay + 1.0 - ay);
+    // Schlick Fresnel, Smith Lambda of the light direction (Eq. 2)
+    const float om = (float)(1.0 - (px.wi[0] * e.h[0] + px.wi[1] * e.h[1] + px.wi[2] * e.h[2]));
+    const float om2 = om * om;
+    e.F = M.F0 + (1.0f - M.F0) * om2 * om2 * om;
+    e.lam_o = smith_lambda(M.ndf, px.alpha, (float)e.cos_o, (float)(1.0 - e.cos_o * e.cos_o));
+    return true;
+}
+
+// Gate and Gaussian of one grid node (Eqs. 10, 16, 17): trials n = w N 2^l
+struct NodeEval {
+    float n, m, mu1, sg;
+    uint32_t K;                // gate threshold on the top 23 hash bits
+};
+
+__device__ __forceinline__ void eval_node(float w, int l, float N, float p, float lp, NodeEval &ne);
+
 // gate threshold: the uniform (2k+1) 2^-24 is below pg  <=>  k < K
 __device__ __forceinline__ uint32_t gate_threshold(float pg)
 {
@@ -418,4 +468,17 @@ __device__ __forceinline__ uint32_t gate_threshold(float pg)
     return kf <= 0.0f ? 0u : (kf >= 8388608.0f ? 8388608u : (uint32_t)kf);
 }
 
+}  // namespace glint
+
+namespace glint {
+__device__ __forceinline__ void eval_node(float w, int l, float N, float p, float lp, NodeEval &ne)
+{
+    ne.n = w * ldexpf(N, l);
+    float pg = 0.0f;
+    if (ne.n > 0.0f && p > 0.0f) pg = (p >= 1.0f) ? 1.0f : -expm1f(ne.n * lp);
+    ne.K = gate_threshold(pg);
+    ne.m = fmaxf(ne.n - 1.0f, 0.0f);
+    ne.mu1 = 1.0f + ne.m * p;
+    ne.sg = sqrtf(ne.m * p * (1.0f - p));
+}
 }  // namespace glint

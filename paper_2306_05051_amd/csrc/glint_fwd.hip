@@ -78,49 +78,28 @@ __device__ __forceinline__ void shade_item(const Pixel &px, int kp, const Shared
     // D_P = D(n) b / (R N P) with D(n) = 1/(pi alpha^2); L = E F G D_P / (4 <wi,n>)
     const float kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha *
                                      (double)px.alpha * 4.0 * cos_i));
-    const float ci = (float)cos_i, si2 = (float)(1.0 - cos_i * cos_i);
-    const float lam_i = smith_lambda(M.ndf, px.alpha, ci, si2);
+    const float lam_i = smith_lambda(M.ndf, px.alpha, (float)cos_i, (float)(1.0 - cos_i * cos_i));
     for (int li = 0; li < sh.n_light; ++li) {
         const DevLight &L = sh.lights[li];
-        if (!L.ok) continue;
-        const double cos_o = px.n[0] * L.wo[0] + px.n[1] * L.wo[1] + px.n[2] * L.wo[2];
-        if (!(cos_o > 0.0)) continue;
-        double h[3] = {px.wi[0] + L.wo[0], px.wi[1] + L.wo[1], px.wi[2] + L.wo[2]};
-        const double hl = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
-        if (!(hl > 0.0)) continue;
-        h[0] /= hl; h[1] /= hl; h[2] /= hl;
-        const double ch = px.n[0] * h[0] + px.n[1] * h[1] + px.n[2] * h[2];
-        bool pclamp;
-        const float p = success_prob(M.ndf, px.alpha, M.R, (float)(ch * ch), (float)(1.0 - ch * ch), pclamp);
-        // angular grid over the projected half vector (Eq. 14)
-        const double ax = (h[0] * tt[0] + h[1] * tt[1] + h[2] * tt[2]) * M.inv_micro - 0.5;
-        const double ay = (h[0] * bb[0] + h[1] * bb[1] + h[2] * bb[2]) * M.inv_micro - 0.5;
-        const double fax = floor(ax), fay = floor(ay);
-        const int ai = (int)fax, aj = (int)fay;
-        // bilinear weights; both complements from FP64 so small weights stay accurate
-        const float fx = (float)(ax - fax), fy = (float)(ay - fay);
-        const float gx = (float)(fax + 1.0 - ax), gy = (float)(fay + 1.0 - ay);
-        const float v[4] = {gx * gy, fx * gy, gx * fy, fx * fy};
+        LightEval le;
+        if (!eval_light(px, L, M, tt, bb, le)) continue;
+        const float v[4] = {le.gx * le.gy, le.fx * le.gy, le.gx * le.fy, le.fx * le.fy};
         uint32_t ak0[4], ak1[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            ak0[a] = hstep(kAngularSalt, angular_word(ai + (a & 1), aj + (a >> 1), 0));
-            ak1[a] = hstep(kAngularSalt, angular_word(ai + (a & 1), aj + (a >> 1), 1));
+            ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
+            ak1[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
         }
+        const float p = le.p;
         const float lp = log1pf(-p);
         float bsum = 0.0f;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             if (g >= nn) continue;
-            // Eq. 10: node g receives w_g N 2^l_g trials; Eqs. 16-17
-            const float ng = px.nw[g] * ldexpf(px.N, px.nl[g]);
-            float pg = 0.0f;
-            if (ng > 0.0f && p > 0.0f) pg = (p >= 1.0f) ? 1.0f : -expm1f(ng * lp);
-            const uint32_t K = gate_threshold(pg);
+            NodeEval ne;
+            eval_node(px.nw[g], px.nl[g], px.N, p, lp, ne);
+            const uint32_t K = ne.K;
             if (!DEBUG && K == 0u) continue;
-            const float mm = fmaxf(ng - 1.0f, 0.0f);
-            const float mu1 = 1.0f + mm * p;
-            const float sg = sqrtf(mm * p * (1.0f - p));
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
 #pragma unroll
@@ -129,7 +108,7 @@ __device__ __forceinline__ void shade_item(const Pixel &px, int kp, const Shared
                     if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_live += K ? 1u : 0u; }
                     if ((h0 >> 9) < K) {                       // theta0 < P>=1 (Eq. 18 gate)
                         const uint32_t h1 = hstep(pre[g][e], ak1[a]);
-                        const float x = fmaf(sg, ndtri_bits(h1), mu1);
+                        const float x = fmaf(ne.sg, ndtri_bits(h1), ne.mu1);
                         const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
                         bsum = fmaf(beta[g][e] * v[a], c, bsum);
                         if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
@@ -137,13 +116,8 @@ __device__ __forceinline__ void shade_item(const Pixel &px, int kp, const Shared
                 }
             }
         }
-        // Schlick Fresnel, separable Smith masking (Eq. 2)
-        const float om = (float)(1.0 - (px.wi[0] * h[0] + px.wi[1] * h[1] + px.wi[2] * h[2]));
-        const float om2 = om * om;
-        const float F = M.F0 + (1.0f - M.F0) * om2 * om2 * om;
-        const float lam_o = smith_lambda(M.ndf, px.alpha, (float)cos_o, (float)(1.0 - cos_o * cos_o));
-        const float G = 1.0f / ((1.0f + lam_i) * (1.0f + lam_o));
-        const float f = F * G * kpx * bsum;
+        const float G = 1.0f / ((1.0f + lam_i) * (1.0f + le.lam_o));
+        const float f = le.F * G * kpx * bsum;
         o.rgb[0] = fmaf(L.rad[0], f, o.rgb[0]);
         o.rgb[1] = fmaf(L.rad[1], f, o.rgb[1]);
         o.rgb[2] = fmaf(L.rad[2], f, o.rgb[2]);
@@ -159,18 +133,9 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
     onb(px.n, tt, bb);
     uint32_t s = 0;
     for (int li = 0; li < sh.n_light; ++li) {
-        const DevLight &L = sh.lights[li];
-        if (!L.ok) continue;
-        const double cos_o = px.n[0] * L.wo[0] + px.n[1] * L.wo[1] + px.n[2] * L.wo[2];
-        if (!(cos_o > 0.0)) continue;
-        double h[3] = {px.wi[0] + L.wo[0], px.wi[1] + L.wo[1], px.wi[2] + L.wo[2]};
-        const double hl = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
-        if (!(hl > 0.0)) continue;
-        h[0] /= hl; h[1] /= hl; h[2] /= hl;
-        const double ax = (h[0] * tt[0] + h[1] * tt[1] + h[2] * tt[2]) * M.inv_micro - 0.5;
-        const double ay = (h[0] * bb[0] + h[1] * bb[1] + h[2] * bb[2]) * M.inv_micro - 0.5;
-        const int ai = (int)floor(ax), aj = (int)floor(ay);
-        for (int a = 0; a < 4; ++a) s += hstep(kAngularSalt, angular_word(ai + (a & 1), aj + (a >> 1), 0));
+        LightEval le;
+        if (!eval_light(px, sh.lights[li], M, tt, bb, le)) continue;
+        for (int a = 0; a < 4; ++a) s += hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
     }
     return s;
 }

@@ -49,6 +49,7 @@ inline int prepare_shared(const glint_material *mats, int32_t n_mat, const glint
         double len = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
         DevLight &d = sh.lights[i];
         d.ok = (len > 0.0 && std::isfinite(len)) ? 1 : 0;
+        d.inv_len = d.ok ? (float)(1.0 / len) : 0.0f;
         for (int c = 0; c < 3; ++c) {
             d.wo[c] = d.ok ? w[c] / len : 0.0;
             if (!finite_host(l.radiance[c])) return GLINT_EINVAL;
