@@ -159,7 +159,10 @@ def main():
         views, bm, bl = scenes.batched_views(n_views=64, seed=4)
         dviews = [glint.to_device(v) for v in views]
         outs = [torch.empty((3,) + v["u"].shape, device="cuda") for v in dviews]
-        plan = glint.GlintPlan(dviews, outs, bm, bl)
+        from paper_2306_05051_amd.autotune import autotune
+        best, tt = autotune(dviews, outs, bm, bl, reps=1)
+        log("autotuned batched shape", best, {k: round(v, 3) for k, v in tt.items()})
+        plan = glint.GlintPlan(dviews, outs, bm, bl, tune=best)
         plan.run(use_graph=True)
         torch.cuda.synchronize()
         npx = sum(v["u"].numel() for v in dviews)
@@ -180,6 +183,7 @@ def main():
         extra["batched_mpix_s"] = round(npx / 1e6 / (bt / 1e3), 2)
         extra["per_view_mpix_s"] = round(npx / 1e6 / (st / 1e3), 2)
         extra["batched_pixels"] = int(npx)
+        extra["batched_tune"] = list(best)
         plan.close()
 
     cpu = None
