@@ -73,6 +73,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-count", action="store_true", help="skip the instrumented unit-count run")
     ap.add_argument("--batched", action="store_true", help="also time the batched multi-view path")
+    ap.add_argument("--no-backward", action="store_true", help="skip the forward+backward timing")
+    ap.add_argument("--scene-cache", default=None, help="npz file to load the 4K scene from / save it to")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy (HBM byte-counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the path shards by pixels/views "
@@ -83,8 +87,24 @@ def main():
     from paper_2306_05051_amd import costmodel, glint, scenes
 
     W, H = 3840, 2160
-    log("generating the 4K scene ...")
-    gb, mats, lights = scenes.four_k(W, H, seed=3)
+    if args.scene_cache and os.path.exists(args.scene_cache):
+        z = np.load(args.scene_cache, allow_pickle=False)
+        gb = {k: z[k] for k in z.files}
+        _, mats, lights = scenes.four_k(16, 16, seed=3)      # same seeded materials and lights
+        log("loaded the 4K scene from", args.scene_cache)
+    else:
+        log("generating the 4K scene ...")
+        gb, mats, lights = scenes.four_k(W, H, seed=3)
+        if args.scene_cache:
+            np.savez(args.scene_cache, **gb)
+    if args.copy_calibration:
+        import torch as _t
+        a = _t.empty(1 << 28, dtype=_t.float32, device="cuda")     # 1 GiB
+        b = _t.empty_like(a)
+        b.copy_(a)
+        _t.cuda.synchronize()
+        log("copy calibration: 1073741824 bytes read, 1073741824 bytes written")
+        del a, b
     dgb = glint.to_device(gb)
     out = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -133,6 +153,8 @@ def main():
     extra = {}
     # forward + backward on the same frame (relaxed counts): one material set, same lights
     try:
+        if args.no_backward:
+            raise glint.GlintError(glint.GLINT_EUNSUPPORTED, "skipped (--no-backward)")
         go = torch.randn((3, H, W), device="cuda", dtype=torch.float32)
         ws = torch.empty(max(1, glint.glint_backward_workspace_bytes(W, H, len(mats), len(lights))),
                          dtype=torch.uint8, device="cuda")

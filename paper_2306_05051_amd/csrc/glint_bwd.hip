@@ -102,7 +102,7 @@ __device__ void grad_item(bool live, const Pixel &px, int kp, const Shared &sh, 
         const DevLight &L = sh.lights[li];
         float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
         LightEval le;
-        if (live && eval_light(px, L, M, tt, bb, le)) {
+        if (live && eval_light(px.n, px.wi, alpha, L, M, tt, bb, le)) {
             const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
             const float dvx[4] = {-le.gy, le.gy, -le.fy, le.fy};
             const float dvy[4] = {-le.gx, -le.fx, le.gx, le.fx};

@@ -122,7 +122,10 @@ __device__ __forceinline__ float ndtri_bits(uint32_t h)
     const float x = (float)(2 * k + 1 - 8388608) * 0x1p-23f;
     const float omx = (float)(16777215 - 2 * k) * 0x1p-23f;   // 1 - x
     const float opx = (float)(2 * k + 1) * 0x1p-23f;          // 1 + x
-    float w = -logf(omx * opx);
+    // v_log_f32 (log2, <= 1 ulp): the polynomial depends weakly on w in the
+    // centre and like sqrt(w) in the tails, so ulp-level errors in w stay far
+    // below the count margins
+    float w = -0.69314718055994531f * __builtin_amdgcn_logf(omx * opx);
     float p;
     if (w < 5.0f) {
         const float s = w - 2.5f;
@@ -136,7 +139,7 @@ __device__ __forceinline__ float ndtri_bits(uint32_t h)
         p = fmaf(p, s, 2.466407418e-01f);
         p = fmaf(p, s, 1.501409411e+00f);
     } else {
-        const float s = sqrtf(w) - 3.0f;
+        const float s = __builtin_amdgcn_sqrtf(w) - 3.0f;
         p = -2.158486895e-04f;
         p = fmaf(p, s, 1.057877307e-04f);
         p = fmaf(p, s, 1.370809623e-03f);
@@ -173,6 +176,16 @@ struct Pixel {
 
 __device__ __forceinline__ bool finitef(float x) { return (__float_as_uint(x) & 0x7f800000u) != 0x7f800000u; }
 
+// FP64 normalisation of an FP32 input vector (identical wherever it is used)
+__device__ __forceinline__ bool normalize_in(float x, float y, float z, double out[3])
+{
+    double l2 = (double)x * x + (double)y * y + (double)z * z;
+    if (!(l2 > 0.0)) return false;
+    const double l = sqrt(l2);
+    out[0] = x / l; out[1] = y / l; out[2] = z / l;
+    return true;
+}
+
 template <bool DEBUG>
 __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, const Shared &sh, Pixel &px)
 {
@@ -192,20 +205,18 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
     const float fwx = vw.wx[idx], fwy = vw.wy[idx], fwz = vw.wz[idx];
     const float alpha = vw.alpha_px ? vw.alpha_px[idx] : M.alpha;
     const float l10 = vw.log10N_px ? vw.log10N_px[idx] : M.log10N;
-    bool fin = finitef(fu) & finitef(fv) & finitef(dux) & finitef(dvx) & finitef(duy) & finitef(dvy) &
-               finitef(fnx) & finitef(fny) & finitef(fnz) & finitef(fwx) & finitef(fwy) & finitef(fwz) &
-               finitef(alpha) & finitef(l10);
+    const int fin = (int)finitef(fu) & (int)finitef(fv) & (int)finitef(dux) & (int)finitef(dvx) &
+                    (int)finitef(duy) & (int)finitef(dvy) & (int)finitef(fnx) & (int)finitef(fny) &
+                    (int)finitef(fnz) & (int)finitef(fwx) & (int)finitef(fwy) & (int)finitef(fwz) &
+                    (int)finitef(alpha) & (int)finitef(l10);
     if (!fin || !(alpha > 0.0f)) { px.flags = F_BAD_INPUT; return; }
     px.alpha = alpha;
     px.N = exp10f(l10);
     // normal and view, FP64 normalised
-    double nn = (double)fnx * fnx + (double)fny * fny + (double)fnz * fnz;
-    double ww = (double)fwx * fwx + (double)fwy * fwy + (double)fwz * fwz;
-    if (!(nn > 0.0) || !(ww > 0.0)) { px.flags = F_BAD_INPUT; return; }
-    nn = sqrt(nn);
-    ww = sqrt(ww);
-    px.n[0] = fnx / nn; px.n[1] = fny / nn; px.n[2] = fnz / nn;
-    px.wi[0] = fwx / ww; px.wi[1] = fwy / ww; px.wi[2] = fwz / ww;
+    if (!normalize_in(fnx, fny, fnz, px.n) || !normalize_in(fwx, fwy, fwz, px.wi)) {
+        px.flags = F_BAD_INPUT;
+        return;
+    }
     // footprint: J J^T moments and |det J| in FP64 (products of FP32 are exact)
     const double a = (double)dux * dux + (double)duy * duy;
     const double b = (double)dux * dvx + (double)duy * dvy;
@@ -343,6 +354,16 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
     px.flags |= F_SHADED;
 }
 
+// Per-pixel record staged in LDS for the (pixel, probe) items: everything an
+// item needs that does not depend on the probe.
+struct PixelRec {
+    double ex, ey;             // sigma0 * major axis direction
+    uint32_t pk;               // npr | n_nodes << 8 | mat << 16
+    float alpha, kpx, lam_i;   // roughness, D(n)/(R N P 4 <wi,n>), Smith Lambda of the view
+    uint32_t nwd[4];           // node key words: (l + 1024) | k << 11 | m << 14
+    float ng[4];               // trials per node, w N 2^l (Eq. 10)
+};
+
 // ---------------------------------------------------------------------------
 // Simplex lattice of grid node (l, k, m) around point c (Eq. 12 read as
 // rotate-then-scale, Sec. 6.2 simplex grid): three vertices and barycentrics.
@@ -425,9 +446,11 @@ struct LightEval {
     float F, lam_o;            // Schlick Fresnel, Smith Lambda of wo
 };
 
-__device__ __forceinline__ bool eval_light(const Pixel &px, const DevLight &L, const DevMaterial &M,
-                                           const double tt[3], const double bb[3], LightEval &e)
+__device__ __forceinline__ bool eval_light(const double pn[3], const double pwi[3], float alpha, const DevLight &L,
+                                           const DevMaterial &M, const double tt[3], const double bb[3],
+                                           LightEval &e)
 {
+    struct { const double *n, *wi; float alpha; } px = {pn, pwi, alpha};
     if (!L.ok) return false;
     e.cos_o = px.n[0] * L.wo[0] + px.n[1] * L.wo[1] + px.n[2] * L.wo[2];
     if (!(e.cos_o > 0.0)) return false;
@@ -479,6 +502,6 @@ __device__ __forceinline__ void eval_node(float w, int l, float N, float p, floa
     ne.K = gate_threshold(pg);
     ne.m = fmaxf(ne.n - 1.0f, 0.0f);
     ne.mu1 = 1.0f + ne.m * p;
-    ne.sg = sqrtf(ne.m * p * (1.0f - p));
+    ne.sg = __builtin_amdgcn_sqrtf(ne.m * p * (1.0f - p));
 }
 }  // namespace glint

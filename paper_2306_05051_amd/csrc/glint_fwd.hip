@@ -17,8 +17,8 @@
 
 #include <cmath>
 #include <cstring>
-#include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "glint_device.hpp"
@@ -40,84 +40,142 @@ struct ItemOut {
     float b[kMaxLight];
 };
 
+struct RgbOut {
+    float rgb[3];
+};
+
+// Per-wave LDS.  Values the open-gate loop reads with a per-lane index live
+// here ([slot][lane], conflict-free) rather than in registers, which cannot
+// be indexed per lane.
+template <bool DEBUG>
+struct TileSmem {
+    int off[kWave];
+    PixelRec rec[kWave];
+    uint32_t pre[12][kWave];   // texel key hashes of each lane's item, [node*3 + vertex][lane]
+    float beta[12][kWave];     // their barycentric weights
+    uint32_t ak1[4][kWave];    // slot-1 angular keys of the current light
+    float mu1[4][kWave];       // 1 + mu of each node for the current light
+    float sg[4][kWave];        // sigma of each node for the current light
+    typename std::conditional<DEBUG, ItemOut, RgbOut>::type slot[kWave];
+};
+
+__device__ __forceinline__ PixelRec make_rec(const Pixel &px, const Shared &sh)
+{
+    PixelRec r;
+    const DevMaterial &M = sh.mats[px.mat];
+    r.ex = px.ex;
+    r.ey = px.ey;
+    r.pk = (uint32_t)px.npr | ((uint32_t)px.n_nodes << 8) | ((uint32_t)px.mat << 16);
+    r.alpha = px.alpha;
+    // D_P = D(n) b / (R N P) with D(n) = 1/(pi alpha^2); L = E F G D_P / (4 <wi,n>)
+    r.kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha * (double)px.alpha * 4.0 *
+                           px.cos_i));
+    r.lam_i = smith_lambda(M.ndf, px.alpha, (float)px.cos_i, (float)(1.0 - px.cos_i * px.cos_i));
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        r.nwd[g] = node_word(px.nl[g], px.nk[g], px.nm[g]);
+        r.ng[g] = px.nw[g] * ldexpf(px.N, px.nl[g]);          // Eq. 10: w_g N 2^l_g trials
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // One (pixel, probe) item: simplex texels of every grid node, then per light
 // the distributed gated binomial sum b and its radiance contribution.
+// Gates are tested for all 48 (node, texel, angular texel) triples without
+// branching and collected in a per-lane bit mask; the open ones (a few per
+// cent) are then counted in a loop over set bits, so a wave runs the
+// expensive branch about max-popcount times instead of once per triple.
+// Bits are taken in increasing (node, texel, angular) order: the sum order is
+// that of the plain triple loop.
 // ---------------------------------------------------------------------------
 template <bool DEBUG>
-__device__ __forceinline__ void shade_item(const Pixel &px, int kp, const Shared &sh, ItemOut &o)
+__device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v, const double n[3],
+                                           const double wi[3], int kp, const Shared &sh, TileSmem<DEBUG> &sm,
+                                           ItemOut &o)
 {
+    const int lane = threadIdx.x;
     o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
     if (DEBUG) {
         o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
     }
-    const DevMaterial &M = sh.mats[px.mat];
+    const int npr = R.pk & 0xff, nn = (R.pk >> 8) & 0xff, mat = R.pk >> 16;
+    const DevMaterial &M = sh.mats[mat];
     // probe centre, uniform along the major axis over length sigma0
-    const double off = ((double)kp + 0.5) / (double)px.npr - 0.5;
-    const double cx = px.u + off * px.ex, cy = px.v + off * px.ey;
+    const double off = ((double)kp + 0.5) / (double)npr - 0.5;
+    const double cx = u + off * R.ex, cy = v + off * R.ey;
     uint32_t pre[4][3];
-    float beta[4][3];
-    const int nn = px.n_nodes;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         if (g < nn) {
+            const uint32_t w = R.nwd[g];
+            const int l = (int)(w & 0x7ffu) - 1024, k = (w >> 11) & 7, m = w >> 14;
             int vi[3], vj[3];
-            simplex_locate(cx, cy, px.nl[g], px.nk[g], px.nm[g], sh, vi, vj, beta[g]);
-            const uint32_t base = hstep(M.root, node_word(px.nl[g], px.nk[g], px.nm[g]));
+            float beta[3];
+            simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta);
+            const uint32_t base = hstep(M.root, w);
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
                 pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
+                sm.pre[g * 3 + e][lane] = pre[g][e];
+                sm.beta[g * 3 + e][lane] = beta[e];
                 if (DEBUG) o.key_sum += pre[g][e];
             }
         }
     }
     double tt[3], bb[3];
-    onb(px.n, tt, bb);
-    const double cos_i = px.cos_i;
-    // D_P = D(n) b / (R N P) with D(n) = 1/(pi alpha^2); L = E F G D_P / (4 <wi,n>)
-    const float kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha *
-                                     (double)px.alpha * 4.0 * cos_i));
-    const float lam_i = smith_lambda(M.ndf, px.alpha, (float)cos_i, (float)(1.0 - cos_i * cos_i));
+    onb(n, tt, bb);
     for (int li = 0; li < sh.n_light; ++li) {
         const DevLight &L = sh.lights[li];
         LightEval le;
-        if (!eval_light(px, L, M, tt, bb, le)) continue;
-        const float v[4] = {le.gx * le.gy, le.fx * le.gy, le.gx * le.fy, le.fx * le.fy};
-        uint32_t ak0[4], ak1[4];
+        if (!eval_light(n, wi, R.alpha, L, M, tt, bb, le)) continue;
+        uint32_t ak0[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
-            ak1[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
+            sm.ak1[a][lane] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
         }
         const float p = le.p;
         const float lp = log1pf(-p);
-        float bsum = 0.0f;
+        uint32_t mlo = 0u, mhi = 0u;           // open gates: bit g*16 + e*4 + a (g < 2 in mlo)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            if (g >= nn) continue;
             NodeEval ne;
-            eval_node(px.nw[g], px.nl[g], px.N, p, lp, ne);
+            eval_node(R.ng[g], 0, 1.0f, p, lp, ne);
+            sm.mu1[g][lane] = ne.mu1;
+            sm.sg[g][lane] = ne.sg;
             const uint32_t K = ne.K;
-            if (!DEBUG && K == 0u) continue;
+            if (g >= nn) continue;
+            if (!DEBUG && K == 0u) continue;   // no uniform can open these gates
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     const uint32_t h0 = hstep(pre[g][e], ak0[a]);
                     if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_live += K ? 1u : 0u; }
-                    if ((h0 >> 9) < K) {                       // theta0 < P>=1 (Eq. 18 gate)
-                        const uint32_t h1 = hstep(pre[g][e], ak1[a]);
-                        const float x = fmaf(ne.sg, ndtri_bits(h1), ne.mu1);
-                        const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
-                        bsum = fmaf(beta[g][e] * v[a], c, bsum);
-                        if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
-                    }
+                    const uint32_t bit = ((h0 >> 9) < K) ? 1u : 0u;   // theta0 < P>=1 (Eq. 18 gate)
+                    if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                    else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
                 }
             }
         }
-        const float G = 1.0f / ((1.0f + lam_i) * (1.0f + le.lam_o));
-        const float f = le.F * G * kpx * bsum;
+        float bsum = 0.0f;
+        while (mlo | mhi) {
+            int idx;
+            if (mlo) { idx = __builtin_ctz(mlo); mlo &= mlo - 1u; }
+            else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
+            const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
+            const int ge = g * 3 + e;
+            const uint32_t h1 = hstep(sm.pre[ge][lane], sm.ak1[a][lane]);
+            const float x = fmaf(sm.sg[g][lane], ndtri_bits(h1), sm.mu1[g][lane]);
+            const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
+            const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);   // bilinear weight (Eq. 14)
+            bsum = fmaf(sm.beta[ge][lane] * va, c, bsum);
+            if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
+        }
+        const float G = 1.0f / ((1.0f + R.lam_i) * (1.0f + le.lam_o));
+        const float f = le.F * G * R.kpx * bsum;
         o.rgb[0] = fmaf(L.rad[0], f, o.rgb[0]);
         o.rgb[1] = fmaf(L.rad[1], f, o.rgb[1]);
         o.rgb[2] = fmaf(L.rad[2], f, o.rgb[2]);
@@ -134,17 +192,11 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
     uint32_t s = 0;
     for (int li = 0; li < sh.n_light; ++li) {
         LightEval le;
-        if (!eval_light(px, sh.lights[li], M, tt, bb, le)) continue;
+        if (!eval_light(px.n, px.wi, px.alpha, sh.lights[li], M, tt, bb, le)) continue;
         for (int a = 0; a < 4; ++a) s += hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
     }
     return s;
 }
-
-template <bool DEBUG>
-struct TileSmem {
-    int off[kWave];
-    ItemOut slot[kWave];
-};
 
 // ---------------------------------------------------------------------------
 // One tile of 64 pixels (tile_w x 64/tile_w) at (x0, y0) of a view.
@@ -157,11 +209,25 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     const int x = x0 + (lane % tile_w), y = y0 + (lane / tile_w);
     const bool inb = (x < vw.width) && (y < vw.height);
     const int64_t idx = (int64_t)y * vw.stride + x;
-    Pixel px;
-    px.flags = 0;
-    px.npr = 0;
-    if (inb) setup_pixel<DEBUG>(vw, idx, sh, px);
-    const int npr = (px.flags & F_SHADED) ? px.npr : 0;
+    int npr = 0;
+    uint32_t dflags = 0, dcell = 0, dakey = 0;
+    int dlevel = 0;
+    {
+        Pixel px;
+        px.flags = 0;
+        px.npr = 0;
+        if (inb) setup_pixel<DEBUG>(vw, idx, sh, px);
+        if (px.flags & F_SHADED) {
+            npr = px.npr;
+            sm.rec[lane] = make_rec(px, sh);
+        }
+        if (DEBUG) {
+            dflags = px.flags;
+            dcell = npr ? px.cell : 0u;
+            dlevel = npr ? px.level : 0;
+            dakey = npr ? akey_fingerprint(px, sh) : 0u;
+        }
+    }
     int incl = npr;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -185,15 +251,16 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             for (int st = 32; st > 0; st >>= 1)
                 if (sm.off[p + st] <= q) p += st;
             const int kp = q - sm.off[p];
-            const int px_x = x0 + (p % tile_w), px_y = y0 + (p / tile_w);
-            Pixel ip;
-            setup_pixel<false>(vw, (int64_t)px_y * vw.stride + px_x, sh, ip);
+            const int64_t pidx = (int64_t)(y0 + p / tile_w) * vw.stride + (x0 + p % tile_w);
+            double n[3], wi[3];
+            normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
+            normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             ItemOut o;
-            shade_item<DEBUG>(ip, kp, sh, o);
+            shade_item<DEBUG>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm, o);
             sm.slot[lane].rgb[0] = o.rgb[0];
             sm.slot[lane].rgb[1] = o.rgb[1];
             sm.slot[lane].rgb[2] = o.rgb[2];
-            if (DEBUG) {
+            if constexpr (DEBUG) {
                 sm.slot[lane].key_sum = o.key_sum;
                 sm.slot[lane].theta_sum = o.theta_sum;
                 sm.slot[lane].count_sum = o.count_sum;
@@ -207,11 +274,11 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
         if (npr > 0) {
             const int i0 = max(off, base), i1 = min(off + npr, base + kWave);
             for (int i = i0; i < i1; ++i) {
-                const ItemOut &s = sm.slot[i - base];
+                const auto &s = sm.slot[i - base];
                 acc[0] += s.rgb[0];
                 acc[1] += s.rgb[1];
                 acc[2] += s.rgb[2];
-                if (DEBUG) {
+                if constexpr (DEBUG) {
                     dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
                     dnl += s.n_live;
                     for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
@@ -226,12 +293,12 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
         vw.out[npx + idx] = acc[1];
         vw.out[2 * npx + idx] = acc[2];
         if (DEBUG) {
-            if (dp.flags) dp.flags[idx] = px.flags;
+            if (dp.flags) dp.flags[idx] = dflags;
             if (dp.n_probe) dp.n_probe[idx] = npr;
-            if (dp.level) dp.level[idx] = npr ? px.level : 0;
-            if (dp.cell) dp.cell[idx] = npr ? px.cell : 0;
+            if (dp.level) dp.level[idx] = dlevel;
+            if (dp.cell) dp.cell[idx] = dcell;
             if (dp.key_sum) dp.key_sum[idx] = dks;
-            if (dp.akey_sum) dp.akey_sum[idx] = npr ? akey_fingerprint(px, sh) : 0u;
+            if (dp.akey_sum) dp.akey_sum[idx] = dakey;
             if (dp.theta_sum) dp.theta_sum[idx] = dts;
             if (dp.count_sum) dp.count_sum[idx] = dcs;
             if (dp.n_open) dp.n_open[idx] = dno;

@@ -242,6 +242,19 @@ def four_k(W=3840, H=2160, seed=3, n_mat=8, n_light=4, tile=16, grazing_frac=0.3
     r = 16 n_pr U(0.9,1]).  Tiles in the left half are clustered (one draw per
     tile); pixels in the right half draw independently (scattered)."""
     rng = np.random.Generator(np.random.PCG64(3000 + seed))
+    # materials, lights and the material map come from their own stream so that
+    # they do not depend on the frame size
+    rng_m = np.random.Generator(np.random.PCG64(3100 + seed))
+    mats = [dict(ndf=0, alpha=float(rng_m.uniform(0.02, 0.6)), R=DEFAULT_R,
+                 log10_density=float(rng_m.uniform(3.0, 8.0)), micro_roughness=DEFAULT_MICRO,
+                 F0=DEFAULT_F0, seed=m) for m in range(n_mat)]
+    lights = []
+    for _ in range(n_light):
+        el = math.radians(rng_m.uniform(20, 80)); az = rng_m.uniform(0, 2 * math.pi)
+        col = tuple(float(c) for c in rng_m.uniform(0.3, 1.0, 3))
+        lights.append(dict(dir=_light_dir(el, az, "y"), radiance=col))
+    sites = rng_m.uniform(0, 1, (64, 2)) * np.array([W, H])
+    labels = rng_m.integers(0, n_mat, 64)
     g = sphere_gbuffer(W, H, rng)
     rmax = float(2 ** k_max)
     ty, tx = (H + tile - 1) // tile, (W + tile - 1) // tile
@@ -258,21 +271,11 @@ def four_k(W=3840, H=2160, seed=3, n_mat=8, n_light=4, tile=16, grazing_frac=0.3
     r_pix = draw((H, W))
     left = (np.arange(W) < W // 2)[None, :]
     g = redraw_ratio(g, np.where(left, r_tile, r_pix))
-    sites = rng.uniform(0, 1, (64, 2)) * np.array([W, H])
-    labels = rng.integers(0, n_mat, 64)
     from scipy.spatial import cKDTree
     yy, xx = np.mgrid[0:H, 0:W]
     _, site = cKDTree(sites).query(np.stack([xx.ravel() + 0.5, yy.ravel() + 0.5], -1))
     mat_map = labels[site.reshape(H, W)].astype(np.int32)
     g["material_id"] = np.where(g["material_id"] >= 0, mat_map, -1).astype(np.int32)
-    mats = [dict(ndf=0, alpha=float(rng.uniform(0.02, 0.6)), R=DEFAULT_R,
-                 log10_density=float(rng.uniform(3.0, 8.0)), micro_roughness=DEFAULT_MICRO,
-                 F0=DEFAULT_F0, seed=m) for m in range(n_mat)]
-    lights = []
-    for _ in range(n_light):
-        el = math.radians(rng.uniform(20, 80)); az = rng.uniform(0, 2 * math.pi)
-        col = tuple(float(c) for c in rng.uniform(0.3, 1.0, 3))
-        lights.append(dict(dir=_light_dir(el, az, "y"), radiance=col))
     return _finish(g), mats, lights
 
 
