@@ -29,25 +29,6 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-// d Lambda / d c and d Lambda / d alpha for direction cosine c (Smith, Eq. 2)
-__device__ __forceinline__ void smith_lambda_grad(int ndf, float alpha, float c, float s2, float &dl_dc,
-                                                  float &dl_da)
-{
-    if (s2 <= 0.0f) { dl_dc = 0.0f; dl_da = 0.0f; return; }
-    const float a2 = alpha * alpha;
-    const float T = s2 / (c * c);
-    if (ndf == 0) {
-        const float S = sqrtf(1.0f + a2 * T);
-        dl_dc = -a2 / (2.0f * c * c * c * S);
-        dl_da = alpha * T / (2.0f * S);
-    } else {
-        const float a = 1.0f / (alpha * sqrtf(T));
-        const float dl_dacoef = -expf(-a * a) / (2.0f * a * a * 1.7724538509055160f);
-        dl_dc = dl_dacoef / (alpha * s2 * sqrtf(s2));
-        dl_da = dl_dacoef * (-a / alpha);
-    }
-}
-
 struct MatSlot {
     int mat;
     float da, dn;
@@ -55,101 +36,101 @@ struct MatSlot {
 
 struct BwdSmem {
     int off[kWave];
+    PixelRec rec[kWave];
+    uint32_t pre[12][kWave];
+    float beta[12][kWave];
+    uint32_t ak1[4][kWave];
+    float mu1[4][kWave];
+    float sg[4][kWave];
     MatSlot ms[kWave];
     float dd[kMaxLight][3];
 };
 
 // one (pixel, probe) item: accumulates d/d alpha and d/d ln N of the pixel's
 // material into da, dn, and d/d dir of each light into sm.dd (wave-reduced).
-// Called by every lane of the wave (live = false contributes zeros).
-__device__ void grad_item(bool live, const Pixel &px, int kp, const Shared &sh, const float gout[3],
-                          float &da, float &dn, BwdSmem &sm)
+// Called by every lane of the wave (live = false contributes zeros).  Gates
+// are collected in bit masks and the open ones processed in a compacted loop,
+// as in the forward.
+__device__ void grad_item(bool live, const PixelRec &R, double u, double v, const double n[3], const double wi[3],
+                          int kp, const Shared &sh, const float gout[3], float &da, float &dn, BwdSmem &sm)
 {
     da = 0.0f;
     dn = 0.0f;
     const int lane = threadIdx.x;
-    const DevMaterial &M = sh.mats[live ? px.mat : 0];
+    const int nn = live ? (int)((R.pk >> 8) & 0xff) : 0;
+    const DevMaterial &M = sh.mats[live ? (int)(R.pk >> 16) : 0];
     uint32_t pre[4][3];
-    float beta[4][3];
-    const int nn = live ? px.n_nodes : 0;
-    if (live) {
-        const double off = ((double)kp + 0.5) / (double)px.npr - 0.5;
-        const double cx = px.u + off * px.ex, cy = px.v + off * px.ey;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            if (g < nn) {
-                int vi[3], vj[3];
-                simplex_locate(cx, cy, px.nl[g], px.nk[g], px.nm[g], sh, vi, vj, beta[g]);
-                const uint32_t base = hstep(M.root, node_word(px.nl[g], px.nk[g], px.nm[g]));
-#pragma unroll
-                for (int e = 0; e < 3; ++e) pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
-            }
-        }
-    }
+    if (live) probe_texels(R, u, v, kp, M, sh, pre, sm, (uint32_t *)nullptr);
     double tt[3] = {0, 0, 0}, bb[3] = {0, 0, 0};
-    float kpx = 0.0f, lam_i = 0.0f, dli_dc = 0.0f, dli_da = 0.0f;
-    const float alpha = live ? px.alpha : 1.0f;
-    if (live) {
-        onb(px.n, tt, bb);
-        kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha * (double)px.alpha * 4.0 *
-                             px.cos_i));
-        const float ci = (float)px.cos_i, si2 = (float)(1.0 - px.cos_i * px.cos_i);
-        lam_i = smith_lambda(M.ndf, alpha, ci, si2);
-        smith_lambda_grad(M.ndf, alpha, ci, si2, dli_dc, dli_da);
-    }
+    if (live) onb(n, tt, bb);
+    const float alpha = live ? R.alpha : 1.0f;
+    const float kpx = live ? R.kpx : 0.0f, lam_i = live ? R.lam_i : 0.0f, dli_da = live ? R.dlam_i : 0.0f;
     const float inv_micro = (float)M.inv_micro;
     for (int li = 0; li < sh.n_light; ++li) {
         const DevLight &L = sh.lights[li];
         float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
         LightEval le;
-        if (live && eval_light(px.n, px.wi, alpha, L, M, tt, bb, le)) {
+        if (live && eval_light(n, wi, alpha, L, M, tt, bb, le)) {
             const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
-            const float dvx[4] = {-le.gy, le.gy, -le.fy, le.fy};
-            const float dvy[4] = {-le.gx, -le.fx, le.gx, le.fx};
-            const float v[4] = {le.gx * le.gy, le.fx * le.gy, le.gx * le.fy, le.fx * le.fy};
-            uint32_t ak0[4], ak1[4];
+            uint32_t ak0[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
-                ak1[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
+                sm.ak1[a][lane] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
             }
             const float p = le.p;
             const float lp = log1pf(-p);
-            float B = 0.0f, Bp = 0.0f, Bm = 0.0f, Bfx = 0.0f, Bfy = 0.0f;
+            uint32_t mlo = 0u, mhi = 0u;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                if (g >= nn) continue;
                 NodeEval ne;
-                eval_node(px.nw[g], px.nl[g], px.N, p, lp, ne);
-                if (ne.K == 0u) continue;
-                const float dmdl = ne.n > 1.0f ? ne.n : 0.0f;          // d m / d ln N
-                const float isg = ne.sg > 0.0f ? 0.5f / ne.sg : 0.0f;
-                const float dsdp = ne.m * (1.0f - 2.0f * p) * isg;       // d sigma / d p
-                const float dsdm = p * (1.0f - p) * isg;                 // d sigma / d m
+                eval_node(R.ng[g], 0, 1.0f, p, lp, ne);
+                sm.mu1[g][lane] = ne.mu1;
+                sm.sg[g][lane] = ne.sg;
+                if (g >= nn || ne.K == 0u) continue;
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
                         const uint32_t h0 = hstep(pre[g][e], ak0[a]);
-                        if ((h0 >> 9) < ne.K) {
-                            const uint32_t h1 = hstep(pre[g][e], ak1[a]);
-                            const float z = ndtri_bits(h1);
-                            const float x = fmaf(ne.sg, z, ne.mu1);
-                            const float be = beta[g][e];
-                            if (x >= 1.0f) {                 // relaxed count c = x
-                                const float bv = be * v[a];
-                                B = fmaf(bv, x, B);
-                                Bp = fmaf(bv, ne.m + z * dsdp, Bp);
-                                Bm = fmaf(bv, (p + z * dsdm) * dmdl, Bm);
-                                Bfx = fmaf(be * dvx[a], x, Bfx);
-                                Bfy = fmaf(be * dvy[a], x, Bfy);
-                            } else {                          // clamped: c = 1
-                                B = fmaf(be, v[a], B);
-                                Bfx += be * dvx[a];
-                                Bfy += be * dvy[a];
-                            }
-                        }
+                        const uint32_t bit = ((h0 >> 9) < ne.K) ? 1u : 0u;
+                        if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                        else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
                     }
+                }
+            }
+            float B = 0.0f, Bp = 0.0f, Bm = 0.0f, Bfx = 0.0f, Bfy = 0.0f;
+            while (mlo | mhi) {
+                int idx;
+                if (mlo) { idx = __builtin_ctz(mlo); mlo &= mlo - 1u; }
+                else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
+                const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
+                const int ge = g * 3 + e;
+                const uint32_t h1 = hstep(sm.pre[ge][lane], sm.ak1[a][lane]);
+                const float z = ndtri_bits(h1);
+                const float sgg = sm.sg[g][lane];
+                const float x = fmaf(sgg, z, sm.mu1[g][lane]);
+                const float be = sm.beta[ge][lane];
+                const float wx = (a & 1) ? le.fx : le.gx, wy = (a & 2) ? le.fy : le.gy;
+                const float va = wx * wy;                             // bilinear weight (Eq. 14)
+                const float dvx = (a & 1) ? wy : -wy, dvy = (a & 2) ? wx : -wx;
+                if (x >= 1.0f) {                                      // relaxed count c = x
+                    const float ng = R.ng[g];
+                    const float m = fmaxf(ng - 1.0f, 0.0f);
+                    const float isg = sgg > 0.0f ? 0.5f / sgg : 0.0f;
+                    const float dsdp = m * (1.0f - 2.0f * p) * isg;   // d sigma / d p
+                    const float dsdm = p * (1.0f - p) * isg;          // d sigma / d m
+                    const float dmdl = ng > 1.0f ? ng : 0.0f;         // d m / d ln N
+                    const float bv = be * va;
+                    B = fmaf(bv, x, B);
+                    Bp = fmaf(bv, m + z * dsdp, Bp);
+                    Bm = fmaf(bv, (p + z * dsdm) * dmdl, Bm);
+                    Bfx = fmaf(be * dvx, x, Bfx);
+                    Bfy = fmaf(be * dvy, x, Bfy);
+                } else {                                              // clamped: c = 1
+                    B = fmaf(be, va, B);
+                    Bfx += be * dvx;
+                    Bfy += be * dvy;
                 }
             }
             // derivatives of p (Eq. 4) with respect to alpha and c2 = <n,h>^2
@@ -175,7 +156,7 @@ __device__ void grad_item(bool live, const Pixel &px, int kp, const Shared &sh, 
             da += sk * (le.F * dG_da * B + le.F * G * Bp * dp_da) - 2.0f * sk * le.F * G * B / alpha;
             dn += sk * le.F * G * (Bm - B);
             // gradient with respect to the unit half vector h
-            const float om = (float)(1.0 - (px.wi[0] * le.h[0] + px.wi[1] * le.h[1] + px.wi[2] * le.h[2]));
+            const float om = (float)(1.0 - (wi[0] * le.h[0] + wi[1] * le.h[1] + wi[2] * le.h[2]));
             const float dF = -5.0f * (1.0f - M.F0) * om * om * om * om * G * B;   // times wi
             const float cn = sk * le.F * G * Bp * dp_dc2 * 2.0f * (float)le.ch;   // times n
             const float ct = sk * le.F * G * Bfx * inv_micro;                      // times t
@@ -183,22 +164,22 @@ __device__ void grad_item(bool live, const Pixel &px, int kp, const Shared &sh, 
             float gh[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                gh[c] = sk * dF * (float)px.wi[c] + cn * (float)px.n[c] + ct * (float)tt[c] + cb * (float)bb[c];
+                gh[c] = sk * dF * (float)wi[c] + cn * (float)n[c] + ct * (float)tt[c] + cb * (float)bb[c];
             // direct dependence on wo through Lambda(<n,wo>)
             const float gon = sk * le.F * B * (-G / (1.0f + le.lam_o)) * dlo_dc;
             // h = (wi + wo)/|wi + wo|, wo = d/|d|: chain through both normalisations
             const float hx = (float)le.h[0], hy = (float)le.h[1], hz = (float)le.h[2];
             const float hd = gh[0] * hx + gh[1] * hy + gh[2] * hz;
             const float ihl = (float)(1.0 / le.hl);
-            const float gw[3] = {(gh[0] - hd * hx) * ihl + gon * (float)px.n[0],
-                           (gh[1] - hd * hy) * ihl + gon * (float)px.n[1],
-                           (gh[2] - hd * hz) * ihl + gon * (float)px.n[2]};
-            const float wx = (float)L.wo[0], wy = (float)L.wo[1], wz = (float)L.wo[2];
-            const float wd = gw[0] * wx + gw[1] * wy + gw[2] * wz;
+            const float gw[3] = {(gh[0] - hd * hx) * ihl + gon * (float)n[0],
+                                 (gh[1] - hd * hy) * ihl + gon * (float)n[1],
+                                 (gh[2] - hd * hz) * ihl + gon * (float)n[2]};
+            const float wxl = (float)L.wo[0], wyl = (float)L.wo[1], wzl = (float)L.wo[2];
+            const float wd = gw[0] * wxl + gw[1] * wyl + gw[2] * wzl;
             const float idl = L.inv_len;
-            gdx = (gw[0] - wd * wx) * idl;
-            gdy = (gw[1] - wd * wy) * idl;
-            gdz = (gw[2] - wd * wz) * idl;
+            gdx = (gw[0] - wd * wxl) * idl;
+            gdy = (gw[1] - wd * wyl) * idl;
+            gdz = (gw[2] - wd * wzl) * idl;
         }
         gdx = wave_sum(gdx);
         gdy = wave_sum(gdy);
@@ -222,11 +203,17 @@ __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, c
     const bool inb = (x < vw.width) && (y < vw.height);
     const int64_t idx = (int64_t)y * vw.stride + x;
     const int64_t npx = (int64_t)vw.height * vw.stride;
-    Pixel px;
-    px.flags = 0;
-    px.npr = 0;
-    if (inb) setup_pixel<false>(vw, idx, sh, px);
-    const int npr = (px.flags & F_SHADED) ? px.npr : 0;
+    int npr = 0;
+    {
+        Pixel px;
+        px.flags = 0;
+        px.npr = 0;
+        if (inb) setup_pixel<false>(vw, idx, sh, px);
+        if (px.flags & F_SHADED) {
+            npr = px.npr;
+            sm.rec[lane] = make_rec(px, sh);
+        }
+    }
     int incl = npr;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -241,26 +228,26 @@ __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, c
     for (int base = 0; base < S; base += kWave) {
         const int q = base + lane;
         const bool live = q < S;
-        Pixel ip;
-        int kp = 0;
+        int p = 0, kp = 0;
         float g3[3] = {0.0f, 0.0f, 0.0f};
-        ip.flags = 0;
+        double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, u = 0.0, v = 0.0;
         if (live) {
-            int p = 0;
 #pragma unroll
             for (int st = 32; st > 0; st >>= 1)
                 if (sm.off[p + st] <= q) p += st;
             kp = q - sm.off[p];
-            const int px_x = x0 + (p % tile_w), px_y = y0 + (p / tile_w);
-            const int64_t pidx = (int64_t)px_y * vw.stride + px_x;
-            setup_pixel<false>(vw, pidx, sh, ip);
+            const int64_t pidx = (int64_t)(y0 + p / tile_w) * vw.stride + (x0 + p % tile_w);
+            normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
+            normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
+            u = vw.u[pidx];
+            v = vw.v[pidx];
             g3[0] = gout[pidx];
             g3[1] = gout[npx + pidx];
             g3[2] = gout[2 * npx + pidx];
         }
         float da, dn;
-        grad_item(live, ip, kp, sh, g3, da, dn, sm);
-        sm.ms[lane].mat = live ? ip.mat : -1;
+        grad_item(live, sm.rec[p], u, v, n, wi, kp, sh, g3, da, dn, sm);
+        sm.ms[lane].mat = live ? (int)(sm.rec[p].pk >> 16) : -1;
         sm.ms[lane].da = da;
         sm.ms[lane].dn = dn;
         __syncthreads();

@@ -360,6 +360,7 @@ struct PixelRec {
     double ex, ey;             // sigma0 * major axis direction
     uint32_t pk;               // npr | n_nodes << 8 | mat << 16
     float alpha, kpx, lam_i;   // roughness, D(n)/(R N P 4 <wi,n>), Smith Lambda of the view
+    float dlam_i;              // d Lambda(view) / d alpha (adjoint only)
     uint32_t nwd[4];           // node key words: (l + 1024) | k << 11 | m << 14
     float ng[4];               // trials per node, w N 2^l (Eq. 10)
 };
@@ -503,5 +504,80 @@ __device__ __forceinline__ void eval_node(float w, int l, float N, float p, floa
     ne.m = fmaxf(ne.n - 1.0f, 0.0f);
     ne.mu1 = 1.0f + ne.m * p;
     ne.sg = __builtin_amdgcn_sqrtf(ne.m * p * (1.0f - p));
+}
+}  // namespace glint
+
+namespace glint {
+// d Lambda / d c and d Lambda / d alpha for direction cosine c (Smith, Eq. 2)
+__device__ __forceinline__ void smith_lambda_grad(int ndf, float alpha, float c, float s2, float &dl_dc,
+                                                  float &dl_da)
+{
+    if (s2 <= 0.0f) { dl_dc = 0.0f; dl_da = 0.0f; return; }
+    const float a2 = alpha * alpha;
+    const float T = s2 / (c * c);
+    if (ndf == 0) {
+        const float S = __builtin_amdgcn_sqrtf(1.0f + a2 * T);
+        dl_dc = -a2 / (2.0f * c * c * c * S);
+        dl_da = alpha * T / (2.0f * S);
+    } else {
+        const float a = 1.0f / (alpha * __builtin_amdgcn_sqrtf(T));
+        const float dl_dacoef = -expf(-a * a) / (2.0f * a * a * 1.7724538509055160f);
+        dl_dc = dl_dacoef / (alpha * s2 * __builtin_amdgcn_sqrtf(s2));
+        dl_da = dl_dacoef * (-a / alpha);
+    }
+}
+
+// the LDS record of a shaded pixel
+__device__ __forceinline__ PixelRec make_rec(const Pixel &px, const Shared &sh)
+{
+    PixelRec r;
+    const DevMaterial &M = sh.mats[px.mat];
+    r.ex = px.ex;
+    r.ey = px.ey;
+    r.pk = (uint32_t)px.npr | ((uint32_t)px.n_nodes << 8) | ((uint32_t)px.mat << 16);
+    r.alpha = px.alpha;
+    // D_P = D(n) b / (R N P) with D(n) = 1/(pi alpha^2); L = E F G D_P / (4 <wi,n>)
+    r.kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha * (double)px.alpha * 4.0 *
+                           px.cos_i));
+    const float ci = (float)px.cos_i, si2 = (float)(1.0 - px.cos_i * px.cos_i);
+    r.lam_i = smith_lambda(M.ndf, px.alpha, ci, si2);
+    float dl_dc;
+    smith_lambda_grad(M.ndf, px.alpha, ci, si2, dl_dc, r.dlam_i);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        r.nwd[g] = node_word(px.nl[g], px.nk[g], px.nm[g]);
+        r.ng[g] = px.nw[g] * ldexpf(px.N, px.nl[g]);          // Eq. 10: w_g N 2^l_g trials
+    }
+    return r;
+}
+
+// texel keys and barycentric weights of one probe's simplex texels (Sec. 6.2)
+template <typename SM>
+__device__ __forceinline__ void probe_texels(const PixelRec &R, double u, double v, int kp, const DevMaterial &M,
+                                             const Shared &sh, uint32_t pre[4][3], SM &sm, uint32_t *key_sum)
+{
+    const int lane = threadIdx.x;
+    const int npr = R.pk & 0xff, nn = (R.pk >> 8) & 0xff;
+    // probe centre, uniform along the major axis over length sigma0
+    const double off = ((double)kp + 0.5) / (double)npr - 0.5;
+    const double cx = u + off * R.ex, cy = v + off * R.ey;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if (g < nn) {
+            const uint32_t w = R.nwd[g];
+            const int l = (int)(w & 0x7ffu) - 1024, k = (w >> 11) & 7, m = w >> 14;
+            int vi[3], vj[3];
+            float beta[3];
+            simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta);
+            const uint32_t base = hstep(M.root, w);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
+                sm.pre[g * 3 + e][lane] = pre[g][e];
+                sm.beta[g * 3 + e][lane] = beta[e];
+                if (key_sum) *key_sum += pre[g][e];
+            }
+        }
+    }
 }
 }  // namespace glint

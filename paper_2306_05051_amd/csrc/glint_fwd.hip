@@ -59,26 +59,6 @@ struct TileSmem {
     typename std::conditional<DEBUG, ItemOut, RgbOut>::type slot[kWave];
 };
 
-__device__ __forceinline__ PixelRec make_rec(const Pixel &px, const Shared &sh)
-{
-    PixelRec r;
-    const DevMaterial &M = sh.mats[px.mat];
-    r.ex = px.ex;
-    r.ey = px.ey;
-    r.pk = (uint32_t)px.npr | ((uint32_t)px.n_nodes << 8) | ((uint32_t)px.mat << 16);
-    r.alpha = px.alpha;
-    // D_P = D(n) b / (R N P) with D(n) = 1/(pi alpha^2); L = E F G D_P / (4 <wi,n>)
-    r.kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha * (double)px.alpha * 4.0 *
-                           px.cos_i));
-    r.lam_i = smith_lambda(M.ndf, px.alpha, (float)px.cos_i, (float)(1.0 - px.cos_i * px.cos_i));
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        r.nwd[g] = node_word(px.nl[g], px.nk[g], px.nm[g]);
-        r.ng[g] = px.nw[g] * ldexpf(px.N, px.nl[g]);          // Eq. 10: w_g N 2^l_g trials
-    }
-    return r;
-}
-
 // ---------------------------------------------------------------------------
 // One (pixel, probe) item: simplex texels of every grid node, then per light
 // the distributed gated binomial sum b and its radiance contribution.
@@ -100,30 +80,10 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
         o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
     }
-    const int npr = R.pk & 0xff, nn = (R.pk >> 8) & 0xff, mat = R.pk >> 16;
+    const int nn = (R.pk >> 8) & 0xff, mat = R.pk >> 16;
     const DevMaterial &M = sh.mats[mat];
-    // probe centre, uniform along the major axis over length sigma0
-    const double off = ((double)kp + 0.5) / (double)npr - 0.5;
-    const double cx = u + off * R.ex, cy = v + off * R.ey;
     uint32_t pre[4][3];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        if (g < nn) {
-            const uint32_t w = R.nwd[g];
-            const int l = (int)(w & 0x7ffu) - 1024, k = (w >> 11) & 7, m = w >> 14;
-            int vi[3], vj[3];
-            float beta[3];
-            simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta);
-            const uint32_t base = hstep(M.root, w);
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
-                sm.pre[g * 3 + e][lane] = pre[g][e];
-                sm.beta[g * 3 + e][lane] = beta[e];
-                if (DEBUG) o.key_sum += pre[g][e];
-            }
-        }
-    }
+    probe_texels(R, u, v, kp, M, sh, pre, sm, DEBUG ? &o.key_sum : (uint32_t *)nullptr);
     double tt[3], bb[3];
     onb(n, tt, bb);
     for (int li = 0; li < sh.n_light; ++li) {
@@ -203,10 +163,11 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 // ---------------------------------------------------------------------------
 template <bool DEBUG>
 __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
-                           int tile_w, TileSmem<DEBUG> &sm)
+                           int lw, TileSmem<DEBUG> &sm)
 {
     const int lane = threadIdx.x;
-    const int x = x0 + (lane % tile_w), y = y0 + (lane / tile_w);
+    const int tmask = (1 << lw) - 1;
+    const int x = x0 + (lane & tmask), y = y0 + (lane >> lw);
     const bool inb = (x < vw.width) && (y < vw.height);
     const int64_t idx = (int64_t)y * vw.stride + x;
     int npr = 0;
@@ -251,7 +212,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             for (int st = 32; st > 0; st >>= 1)
                 if (sm.off[p + st] <= q) p += st;
             const int kp = q - sm.off[p];
-            const int64_t pidx = (int64_t)(y0 + p / tile_w) * vw.stride + (x0 + p % tile_w);
+            const int64_t pidx = (int64_t)(y0 + (p >> lw)) * vw.stride + (x0 + (p & tmask));
             double n[3], wi[3];
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
@@ -311,49 +272,88 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
 }
 
 template <bool DEBUG>
-__global__ __launch_bounds__(64) void glint_fwd_kernel(ViewDesc vw, Shared sh, DebugPlanes dp, int tile_w,
-                                                       int tiles_x)
+__global__ __launch_bounds__(64) void glint_fwd_kernel(ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x)
 {
     __shared__ TileSmem<DEBUG> sm;
-    const int tile_h = kWave / tile_w;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    shade_tile<DEBUG>(vw, sh, dp, tx * tile_w, ty * tile_h, tile_w, sm);
+    shade_tile<DEBUG>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm);
+}
+
+// wave-uniform copies (scalar registers) of a descriptor's fields
+__device__ __forceinline__ int32_t uni32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ int64_t uni64(int64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T *uniptr(T *p)
+{
+    return reinterpret_cast<T *>(uni64(reinterpret_cast<int64_t>(p)));
+}
+
+__device__ __forceinline__ ViewDesc uniform_view(const ViewDesc &v)
+{
+    ViewDesc u;
+    u.width = uni32(v.width);
+    u.height = uni32(v.height);
+    u.stride = uni64(v.stride);
+    u.u = uniptr(v.u); u.v = uniptr(v.v);
+    u.dudx = uniptr(v.dudx); u.dvdx = uniptr(v.dvdx); u.dudy = uniptr(v.dudy); u.dvdy = uniptr(v.dvdy);
+    u.nx = uniptr(v.nx); u.ny = uniptr(v.ny); u.nz = uniptr(v.nz);
+    u.wx = uniptr(v.wx); u.wy = uniptr(v.wy); u.wz = uniptr(v.wz);
+    u.mat = uniptr(v.mat);
+    u.alpha_px = uniptr(v.alpha_px);
+    u.log10N_px = uniptr(v.log10N_px);
+    u.out = uniptr(v.out);
+    return u;
 }
 
 // Persistent batched kernel: workgroups pop chunks of tiles from a global
 // counter until every tile of every view is done (the loop always ends: the
-// counter only grows and each pop covers at least one tile).
-__global__ __launch_bounds__(64) void glint_batched_kernel(const ViewDesc *views, const int64_t *tile_start,
-                                                           int n_views, int64_t n_tiles, int tile_w, int chunk,
-                                                           unsigned long long *counter, Shared sh)
+// counter only grows and each pop covers at least one tile).  Tile indices
+// and view descriptors are wave-uniform (scalar registers).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void glint_batched_kernel(
+    const ViewDesc *__restrict__ views,
+                                                           const int32_t *__restrict__ tile_start,
+                                                           int n_views, int32_t n_tiles, int lw, int chunk,
+                                                           unsigned int *counter, const Shared *__restrict__ shp)
 {
     __shared__ TileSmem<false> sm;
-    __shared__ long long s_t0;
-    const int tile_h = kWave / tile_w;
+    __shared__ int s_t0;
     DebugPlanes dp = {};
     for (;;) {
-        if (threadIdx.x == 0) s_t0 = (long long)atomicAdd(counter, (unsigned long long)chunk);
+        if (threadIdx.x == 0) s_t0 = (int)atomicAdd(counter, (unsigned int)chunk);
         __syncthreads();
-        const int64_t t0 = s_t0;
+        const int t0 = __builtin_amdgcn_readfirstlane(s_t0);
         __syncthreads();
         if (t0 >= n_tiles) break;
-        const int64_t t1 = t0 + chunk < n_tiles ? t0 + chunk : n_tiles;
-        for (int64_t t = t0; t < t1; ++t) {
+        const int t1 = min(t0 + chunk, n_tiles);
+        for (int t = t0; t < t1; ++t) {
             int lo = 0, hi = n_views;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 if (tile_start[mid] <= t) lo = mid; else hi = mid;
             }
-            const ViewDesc vw = views[lo];
-            const int64_t local = t - tile_start[lo];
-            const int tiles_x = (vw.width + tile_w - 1) / tile_w;
-            const int tx = (int)(local % tiles_x), ty = (int)(local / tiles_x);
-            shade_tile<false>(vw, sh, dp, tx * tile_w, ty * tile_h, tile_w, sm);
+            lo = __builtin_amdgcn_readfirstlane(lo);
+            const ViewDesc vw = uniform_view(views[lo]);
+            const int local = uni32(t - tile_start[lo]);
+            const int tiles_x = (vw.width + (1 << lw) - 1) >> lw;
+            const int tx = local % tiles_x, ty = local / tiles_x;
+            // an opaque copy of the parameter pointer per tile keeps the compiler
+            // from hoisting parameter loads out of the loop (which would hold them
+            // in registers across every tile and halve the occupancy)
+            const Shared *sp = shp;
+            asm volatile("" : "+s"(sp));
+            shade_tile<false>(vw, *sp, dp, tx << lw, ty << (6 - lw), lw, sm);
         }
     }
 }
 
-__global__ void glint_reset_counter(unsigned long long *counter) { *counter = 0ull; }
+__global__ void glint_reset_counter(unsigned int *counter) { *counter = 0u; }
 
 // bit-exactness utilities ----------------------------------------------------
 __global__ void glint_texel_hash_kernel(const int32_t *keys, int64_t n, uint32_t *out)
@@ -382,6 +382,8 @@ __global__ void glint_ndtri_kernel(const uint32_t *bits, int64_t n, float *out)
 
 static bool valid_tile_w(int w) { return w == 8 || w == 16 || w == 32 || w == 64; }
 
+static int log2_tile(int w) { return w == 8 ? 3 : (w == 16 ? 4 : (w == 32 ? 5 : 6)); }
+
 }  // namespace glint
 
 // ===========================================================================
@@ -391,8 +393,9 @@ using namespace glint;
 
 struct glint_plan {
     ViewDesc *d_views = nullptr;
-    int64_t *d_tile_start = nullptr;
-    unsigned long long *d_counter = nullptr;
+    Shared *d_sh = nullptr;
+    int32_t *d_tile_start = nullptr;
+    unsigned int *d_counter = nullptr;
     int n_views = 0;
     int64_t n_tiles = 0;
     int tile_w = 8;
@@ -443,12 +446,12 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     if (dbg) {
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light};
-        hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp, tile_w,
-                           tiles_x);
+        hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
+                           log2_tile(tile_w), tiles_x);
     } else {
         DebugPlanes dp = {};
-        hipLaunchKernelGGL(glint_fwd_kernel<false>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp, tile_w,
-                           tiles_x);
+        hipLaunchKernelGGL(glint_fwd_kernel<false>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
+                           log2_tile(tile_w), tiles_x);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);
@@ -477,16 +480,17 @@ int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t
         bpc = tune->blocks_per_cu;
     }
     std::vector<ViewDesc> views((size_t)n_views);
-    std::vector<int64_t> start((size_t)n_views + 1);
+    std::vector<int32_t> start((size_t)n_views + 1);
     int64_t total = 0;
     const int tile_h = kWave / P->tile_w;
     for (int i = 0; i < n_views; ++i) {
         rc = make_view(&gbufs[i], out_rgb[i], views[i]);
         if (rc) { delete P; return rc; }
-        start[i] = total;
+        start[i] = (int32_t)total;
         total += (int64_t)((views[i].width + P->tile_w - 1) / P->tile_w) * ((views[i].height + tile_h - 1) / tile_h);
+        if (total > 0x7fff0000LL) { delete P; return GLINT_ESHAPE; }
     }
-    start[n_views] = total;
+    start[n_views] = (int32_t)total;
     P->n_views = n_views;
     P->n_tiles = total;
     int dev = 0, n_cu = 256;
@@ -499,11 +503,13 @@ int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t
     int64_t per = total / ((int64_t)P->n_blocks * 16);
     P->chunk = (int)(per < 1 ? 1 : (per > 16 ? 16 : per));
     e = hipMalloc((void **)&P->d_views, sizeof(ViewDesc) * n_views);
-    if (e == hipSuccess) e = hipMalloc((void **)&P->d_tile_start, sizeof(int64_t) * (n_views + 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&P->d_counter, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_sh, sizeof(Shared));
+    if (e == hipSuccess) e = hipMemcpy(P->d_sh, &P->sh, sizeof(Shared), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_tile_start, sizeof(int32_t) * (n_views + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_counter, sizeof(unsigned int));
     if (e == hipSuccess) e = hipMemcpy(P->d_views, views.data(), sizeof(ViewDesc) * n_views, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(P->d_tile_start, start.data(), sizeof(int64_t) * (n_views + 1), hipMemcpyHostToDevice);
+        e = hipMemcpy(P->d_tile_start, start.data(), sizeof(int32_t) * (n_views + 1), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         glint_plan_destroy(P);
         return e == hipErrorOutOfMemory ? GLINT_ENOMEM : set_hip_error(e);
@@ -516,7 +522,8 @@ static int enqueue_batched(glint_plan *P, hipStream_t st)
 {
     hipLaunchKernelGGL(glint_reset_counter, dim3(1), dim3(1), 0, st, P->d_counter);
     hipLaunchKernelGGL(glint_batched_kernel, dim3((unsigned)P->n_blocks), dim3(kWave), 0, st, P->d_views,
-                       P->d_tile_start, P->n_views, P->n_tiles, P->tile_w, P->chunk, P->d_counter, P->sh);
+                       P->d_tile_start, P->n_views, (int32_t)P->n_tiles, log2_tile(P->tile_w), P->chunk,
+                       P->d_counter, P->d_sh);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);
 }
@@ -564,6 +571,7 @@ int glint_plan_destroy(glint_plan *P)
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->d_views) (void)hipFree(P->d_views);
+    if (P->d_sh) (void)hipFree(P->d_sh);
     if (P->d_tile_start) (void)hipFree(P->d_tile_start);
     if (P->d_counter) (void)hipFree(P->d_counter);
     delete P;
