@@ -39,9 +39,6 @@ struct BwdSmem {
     PixelRec rec[kWave];
     uint32_t pre[12][kWave];
     float beta[12][kWave];
-    uint32_t ak1[4][kWave];
-    float mu1[4][kWave];
-    float sg[4][kWave];
     MatSlot ms[kWave];
     float dd[kMaxLight][3];
 };
@@ -72,30 +69,32 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
         LightEval le;
         if (live && eval_light(n, wi, alpha, L, M, tt, bb, le)) {
             const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
-            uint32_t ak0[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
-                sm.ak1[a][lane] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
-            }
             const float p = le.p;
-            const float lp = log1pf(-p);
-            uint32_t mlo = 0u, mhi = 0u;
+            const float lp = log1m(p);
+            uint32_t K[4], anyK = 0u;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                NodeEval ne;
-                eval_node(R.ng[g], 0, 1.0f, p, lp, ne);
-                sm.mu1[g][lane] = ne.mu1;
-                sm.sg[g][lane] = ne.sg;
-                if (g >= nn || ne.K == 0u) continue;
+                K[g] = gate_threshold(gate_prob(R.ng[g], p, lp));
+                if (g < nn) anyK |= K[g];
+            }
+            uint32_t mlo = 0u, mhi = 0u;
+            if (anyK) {
+                uint32_t ak0[4];
 #pragma unroll
-                for (int e = 0; e < 3; ++e) {
+                for (int a = 0; a < 4; ++a)
+                    ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const uint32_t h0 = hstep(pre[g][e], ak0[a]);
-                        const uint32_t bit = ((h0 >> 9) < ne.K) ? 1u : 0u;
-                        if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
-                        else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                for (int g = 0; g < 4; ++g) {
+                    if (g >= nn || K[g] == 0u) continue;
+                    const uint32_t thr = (K[g] << 9) - 1u;   // (h >> 9) < K  <=>  h <= K 2^9 - 1
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            const uint32_t bit = (hstep(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
+                            if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                            else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                        }
                     }
                 }
             }
@@ -106,17 +105,19 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
                 else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
                 const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
                 const int ge = g * 3 + e;
-                const uint32_t h1 = hstep(sm.pre[ge][lane], sm.ak1[a][lane]);
+                const uint32_t ak1 = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
+                const uint32_t h1 = hstep(sm.pre[ge][lane], ak1);
                 const float z = ndtri_bits(h1);
-                const float sgg = sm.sg[g][lane];
-                const float x = fmaf(sgg, z, sm.mu1[g][lane]);
+                // Eq. 17 for node g (same arithmetic as the forward)
+                const float ng = R.ng[g];
+                const float m = fmaxf(ng - 1.0f, 0.0f);
+                const float sgg = __builtin_amdgcn_sqrtf(m * p * (1.0f - p));
+                const float x = fmaf(sgg, z, 1.0f + m * p);
                 const float be = sm.beta[ge][lane];
                 const float wx = (a & 1) ? le.fx : le.gx, wy = (a & 2) ? le.fy : le.gy;
                 const float va = wx * wy;                             // bilinear weight (Eq. 14)
                 const float dvx = (a & 1) ? wy : -wy, dvy = (a & 2) ? wx : -wx;
                 if (x >= 1.0f) {                                      // relaxed count c = x
-                    const float ng = R.ng[g];
-                    const float m = fmaxf(ng - 1.0f, 0.0f);
                     const float isg = sgg > 0.0f ? 0.5f / sgg : 0.0f;
                     const float dsdp = m * (1.0f - 2.0f * p) * isg;   // d sigma / d p
                     const float dsdm = p * (1.0f - p) * isg;          // d sigma / d m

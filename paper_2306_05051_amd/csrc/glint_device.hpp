@@ -181,8 +181,8 @@ __device__ __forceinline__ bool normalize_in(float x, float y, float z, double o
 {
     double l2 = (double)x * x + (double)y * y + (double)z * z;
     if (!(l2 > 0.0)) return false;
-    const double l = sqrt(l2);
-    out[0] = x / l; out[1] = y / l; out[2] = z / l;
+    const double il = 1.0 / sqrt(l2);
+    out[0] = x * il; out[1] = y * il; out[2] = z * il;
     return true;
 }
 
@@ -369,11 +369,11 @@ struct PixelRec {
 // Simplex lattice of grid node (l, k, m) around point c (Eq. 12 read as
 // rotate-then-scale, Sec. 6.2 simplex grid): three vertices and barycentrics.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double pow2_half(int e)   // 2^(e/2)
+__device__ __forceinline__ double pow2_neg_half(int e)   // 2^(-e/2)
 {
-    const double r2 = 1.41421356237309504880;
-    const int h = e >> 1;                 // floor(e/2)
-    return (e & 1) ? ldexp(r2, h) : ldexp(1.0, h);
+    const double ir2 = 0.70710678118654752440;
+    const int h = e >> 1;                 // floor(e/2): 2^(-e/2) = 2^-h (e even), 2^-h / sqrt 2 (e odd)
+    return (e & 1) ? ldexp(ir2, -h) : ldexp(1.0, -h);
 }
 
 __device__ __forceinline__ void simplex_locate(double cx, double cy, int l, int k, int m, const Shared &sh,
@@ -383,8 +383,8 @@ __device__ __forceinline__ void simplex_locate(double cx, double cy, int l, int 
     const double cph = sh.cs[mi][0], sph = sh.cs[mi][1];
     const double qx = cph * cx + sph * cy;
     const double qy = -sph * cx + cph * cy;
-    const double x = qx / pow2_half(l + k);
-    const double y = qy / pow2_half(l - k);
+    const double x = qx * pow2_neg_half(l + k);
+    const double y = qy * pow2_neg_half(l - k);
     const double Lx = x + 0.5 * y, Ly = y;
     const double fi = floor(Lx), fj = floor(Ly);
     const double f = Lx - fi, g = Ly - fj;
@@ -408,13 +408,47 @@ __device__ __forceinline__ void onb(const double n[3], double t[3], double b[3])
     b[0] = bb; b[1] = sgn + n[1] * n[1] * a; b[2] = -n[1];
 }
 
+// v_rcp_f32 (1 ulp): the relative error of every quotient below stays ~1e-7
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// log(1 - p) for p in [0, 1): atanh series 2s(1 + s^2/3 + ... + s^8/9) with
+// s = -p/(2 - p) for p <= 1/4 (truncation < 4e-10 relative), hardware log2 of
+// 1 - p above (|log(1-p)| > 0.28 there).  Relative error ~3e-7.
+__device__ __forceinline__ float log1m(float p)
+{
+    const float s = -p * rcpf(2.0f - p);
+    const float s2 = s * s;
+    float t = fmaf(s2, 1.0f / 9.0f, 1.0f / 7.0f);
+    t = fmaf(t, s2, 1.0f / 5.0f);
+    t = fmaf(t, s2, 1.0f / 3.0f);
+    t = fmaf(t, s2, 1.0f);
+    const float small = 2.0f * s * t;
+    const float large = 0.69314718055994531f * __builtin_amdgcn_logf(1.0f - p);
+    return p <= 0.25f ? small : large;
+}
+
+// 1 - exp(y) for y <= 0: Taylor series to y^7 for |y| <= 1/4 (truncation
+// < 4e-10 relative), 1 - 2^(y log2 e) below (result > 0.22).  ~2e-7 relative.
+__device__ __forceinline__ float one_minus_exp(float y)
+{
+    float t = fmaf(y, 1.0f / 5040.0f, 1.0f / 720.0f);
+    t = fmaf(t, y, 1.0f / 120.0f);
+    t = fmaf(t, y, 1.0f / 24.0f);
+    t = fmaf(t, y, 1.0f / 6.0f);
+    t = fmaf(t, y, 0.5f);
+    t = fmaf(t, y, 1.0f);
+    const float small = -y * t;
+    const float large = 1.0f - __builtin_amdgcn_exp2f(y * 1.4426950408889634f);
+    return y >= -0.25f ? small : large;
+}
+
 // Smith Lambda of the NDF for a direction with cos theta = c, 1 - c^2 = s2
 __device__ __forceinline__ float smith_lambda(int ndf, float alpha, float c, float s2)
 {
     if (s2 <= 0.0f) return 0.0f;
-    const float tan2 = s2 / (c * c);
-    if (ndf == 0) return 0.5f * (-1.0f + sqrtf(1.0f + alpha * alpha * tan2));
-    const float a = 1.0f / (alpha * sqrtf(tan2));
+    const float tan2 = s2 * rcpf(c * c);
+    if (ndf == 0) return 0.5f * (-1.0f + __builtin_amdgcn_sqrtf(1.0f + alpha * alpha * tan2));
+    const float a = rcpf(alpha * __builtin_amdgcn_sqrtf(tan2));
     return 0.5f * (erff(a) - 1.0f) + expf(-a * a) / (2.0f * a * 1.7724538509055160f);
 }
 
@@ -425,9 +459,9 @@ __device__ __forceinline__ float success_prob(int ndf, float alpha, float R, flo
     float ratio;
     if (ndf == 0) {
         const float d = s2 + c2 * a2;          // (n.h)^2 (a^2 - 1) + 1, cancellation-free
-        ratio = (a2 * a2) / (d * d);
+        ratio = (a2 * a2) * rcpf(d * d);
     } else {
-        ratio = expf(-(s2 / c2) / a2) / (c2 * c2);
+        ratio = expf(-(s2 * rcpf(c2 * a2))) * rcpf(c2 * c2);
     }
     float p = R * ratio;
     clamped = p > 1.0f;
@@ -458,7 +492,8 @@ __device__ __forceinline__ bool eval_light(const double pn[3], const double pwi[
     double h0 = px.wi[0] + L.wo[0], h1 = px.wi[1] + L.wo[1], h2 = px.wi[2] + L.wo[2];
     e.hl = sqrt(h0 * h0 + h1 * h1 + h2 * h2);
     if (!(e.hl > 0.0)) return false;
-    e.h[0] = h0 / e.hl; e.h[1] = h1 / e.hl; e.h[2] = h2 / e.hl;
+    const double ihl = 1.0 / e.hl;
+    e.h[0] = h0 * ihl; e.h[1] = h1 * ihl; e.h[2] = h2 * ihl;
     e.ch = px.n[0] * e.h[0] + px.n[1] * e.h[1] + px.n[2] * e.h[2];
     e.p = success_prob(M.ndf, px.alpha, M.R, (float)(e.ch * e.ch), (float)(1.0 - e.ch * e.ch), e.pclamp);
     // angular grid over the projected half vector (Eq. 14)
@@ -483,6 +518,13 @@ struct NodeEval {
     uint32_t K;                // gate threshold on the top 23 hash bits
 };
 
+// gate probability P>=1 = 1 - (1 - p)^n (Eq. 16) from lp = log(1 - p)
+__device__ __forceinline__ float gate_prob(float n, float p, float lp)
+{
+    if (!(n > 0.0f) || !(p > 0.0f)) return 0.0f;
+    return p >= 1.0f ? 1.0f : one_minus_exp(n * lp);
+}
+
 __device__ __forceinline__ void eval_node(float w, int l, float N, float p, float lp, NodeEval &ne);
 
 // gate threshold: the uniform (2k+1) 2^-24 is below pg  <=>  k < K
@@ -498,9 +540,7 @@ namespace glint {
 __device__ __forceinline__ void eval_node(float w, int l, float N, float p, float lp, NodeEval &ne)
 {
     ne.n = w * ldexpf(N, l);
-    float pg = 0.0f;
-    if (ne.n > 0.0f && p > 0.0f) pg = (p >= 1.0f) ? 1.0f : -expm1f(ne.n * lp);
-    ne.K = gate_threshold(pg);
+    ne.K = gate_threshold(gate_prob(ne.n, p, lp));
     ne.m = fmaxf(ne.n - 1.0f, 0.0f);
     ne.mu1 = 1.0f + ne.m * p;
     ne.sg = __builtin_amdgcn_sqrtf(ne.m * p * (1.0f - p));

@@ -53,9 +53,6 @@ struct TileSmem {
     PixelRec rec[kWave];
     uint32_t pre[12][kWave];   // texel key hashes of each lane's item, [node*3 + vertex][lane]
     float beta[12][kWave];     // their barycentric weights
-    uint32_t ak1[4][kWave];    // slot-1 angular keys of the current light
-    float mu1[4][kWave];       // 1 + mu of each node for the current light
-    float sg[4][kWave];        // sigma of each node for the current light
     typename std::conditional<DEBUG, ItemOut, RgbOut>::type slot[kWave];
 };
 
@@ -90,31 +87,37 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
         const DevLight &L = sh.lights[li];
         LightEval le;
         if (!eval_light(n, wi, R.alpha, L, M, tt, bb, le)) continue;
+        const float p = le.p;
+        const float lp = log1m(p);
+        uint32_t K[4], anyK = 0u;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            K[g] = gate_threshold(gate_prob(R.ng[g], p, lp));
+            if (g < nn) anyK |= K[g];
+        }
+        if (!DEBUG && anyK == 0u) continue;    // no gate of this light can open
         uint32_t ak0[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
-            sm.ak1[a][lane] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
-        }
-        const float p = le.p;
-        const float lp = log1pf(-p);
+        for (int a = 0; a < 4; ++a) ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
         uint32_t mlo = 0u, mhi = 0u;           // open gates: bit g*16 + e*4 + a (g < 2 in mlo)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            NodeEval ne;
-            eval_node(R.ng[g], 0, 1.0f, p, lp, ne);
-            sm.mu1[g][lane] = ne.mu1;
-            sm.sg[g][lane] = ne.sg;
-            const uint32_t K = ne.K;
             if (g >= nn) continue;
-            if (!DEBUG && K == 0u) continue;   // no uniform can open these gates
+            if (!DEBUG && K[g] == 0u) continue;   // no uniform can open these gates
+            // theta0 < P>=1 (Eq. 18 gate)  <=>  (h >> 9) < K  <=>  h <= K 2^9 - 1  (K > 0)
+            const uint32_t thr = (K[g] << 9) - 1u;
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     const uint32_t h0 = hstep(pre[g][e], ak0[a]);
-                    if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_live += K ? 1u : 0u; }
-                    const uint32_t bit = ((h0 >> 9) < K) ? 1u : 0u;   // theta0 < P>=1 (Eq. 18 gate)
+                    uint32_t bit;
+                    if (DEBUG) {
+                        o.theta_sum += h0; o.n_gate += 1; o.n_live += K[g] ? 1u : 0u;
+                        bit = ((h0 >> 9) < K[g]) ? 1u : 0u;
+                    } else {
+                        bit = (h0 <= thr) ? 1u : 0u;
+                    }
                     if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
                     else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
                 }
@@ -127,8 +130,12 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
             else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
             const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
             const int ge = g * 3 + e;
-            const uint32_t h1 = hstep(sm.pre[ge][lane], sm.ak1[a][lane]);
-            const float x = fmaf(sm.sg[g][lane], ndtri_bits(h1), sm.mu1[g][lane]);
+            const uint32_t ak1 = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
+            const uint32_t h1 = hstep(sm.pre[ge][lane], ak1);
+            // Eq. 17 for node g: m = max(n - 1, 0), 1 + mu, sigma (same arithmetic as eval_node)
+            const float ng = R.ng[g];
+            const float m = fmaxf(ng - 1.0f, 0.0f);
+            const float x = fmaf(__builtin_amdgcn_sqrtf(m * p * (1.0f - p)), ndtri_bits(h1), 1.0f + m * p);
             const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
             const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);   // bilinear weight (Eq. 14)
             bsum = fmaf(sm.beta[ge][lane] * va, c, bsum);
