@@ -4,7 +4,9 @@
 
 hipcc compiles every HIP translation unit for gfx950 only, with packed FP32
 instructions disabled (-packed-fp32-ops), then links one shared library next
-to this file.  Object files go to _build/ (not committed).
+to this file.  Object files go to _build/ (not committed).  It also builds
+valu_probe, the stand-alone VALU issue-rate probe behind the roofline's
+denominator and slot costs (costmodel.py).
 """
 from __future__ import annotations
 
@@ -17,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libglint.so")
+PROBE = os.path.join(HERE, "valu_probe")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["glint_fwd.hip", "glint_bwd.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -46,8 +49,14 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link of libglint.so failed")
     os.replace(tmp, OUT)
+    r = subprocess.run([HIPCC, *FLAGS, "-o", PROBE + ".tmp", os.path.join(CSRC, "valu_probe.hip")],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on valu_probe.hip")
+    os.replace(PROBE + ".tmp", PROBE)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", PROBE)
     return OUT
 
 

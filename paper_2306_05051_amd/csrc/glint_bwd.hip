@@ -37,6 +37,7 @@ struct MatSlot {
 struct BwdSmem {
     int off[kWave];
     PixelRec rec[kWave];
+    float dlam[kWave];         // d Lambda(view) / d alpha per pixel
     uint32_t pre[12][kWave];
     float beta[12][kWave];
     MatSlot ms[kWave];
@@ -48,20 +49,22 @@ struct BwdSmem {
 // Called by every lane of the wave (live = false contributes zeros).  Gates
 // are collected in bit masks and the open ones processed in a compacted loop,
 // as in the forward.
-__device__ void grad_item(bool live, const PixelRec &R, double u, double v, const double n[3], const double wi[3],
-                          int kp, const Shared &sh, const float gout[3], float &da, float &dn, BwdSmem &sm)
+__device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, double v, const double n[3],
+                          const double wi[3], int kp, const Shared &sh, const float gout[3], float &da, float &dn,
+                          BwdSmem &sm)
 {
     da = 0.0f;
     dn = 0.0f;
     const int lane = threadIdx.x;
-    const int nn = live ? (int)((R.pk >> 8) & 0xff) : 0;
-    const DevMaterial &M = sh.mats[live ? (int)(R.pk >> 16) : 0];
+    const int nn = live ? rec_nodes(R) : 0;
+    const DevMaterial &M = sh.mats[live ? rec_mat(R) : 0];
     uint32_t pre[4][3];
     if (live) probe_texels(R, u, v, kp, M, sh, pre, sm, (uint32_t *)nullptr);
     double tt[3] = {0, 0, 0}, bb[3] = {0, 0, 0};
     if (live) onb(n, tt, bb);
     const float alpha = live ? R.alpha : 1.0f;
-    const float kpx = live ? R.kpx : 0.0f, lam_i = live ? R.lam_i : 0.0f, dli_da = live ? R.dlam_i : 0.0f;
+    const float kpx = live ? R.kpx : 0.0f, lam_i = live ? R.lam_i : 0.0f;
+    if (!live) dli_da = 0.0f;
     const float inv_micro = (float)M.inv_micro;
     for (int li = 0; li < sh.n_light; ++li) {
         const DevLight &L = sh.lights[li];
@@ -213,6 +216,9 @@ __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, c
         if (px.flags & F_SHADED) {
             npr = px.npr;
             sm.rec[lane] = make_rec(px, sh);
+            const float ci = (float)px.cos_i, si2 = (float)(1.0 - px.cos_i * px.cos_i);
+            float dl_dc;
+            smith_lambda_grad(sh.mats[px.mat].ndf, px.alpha, ci, si2, dl_dc, sm.dlam[lane]);
         }
     }
     int incl = npr;
@@ -247,8 +253,8 @@ __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, c
             g3[2] = gout[2 * npx + pidx];
         }
         float da, dn;
-        grad_item(live, sm.rec[p], u, v, n, wi, kp, sh, g3, da, dn, sm);
-        sm.ms[lane].mat = live ? (int)(sm.rec[p].pk >> 16) : -1;
+        grad_item(live, sm.rec[p], sm.dlam[p], u, v, n, wi, kp, sh, g3, da, dn, sm);
+        sm.ms[lane].mat = live ? rec_mat(sm.rec[p]) : -1;
         sm.ms[lane].da = da;
         sm.ms[lane].dn = dn;
         __syncthreads();

@@ -355,15 +355,30 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
 }
 
 // Per-pixel record staged in LDS for the (pixel, probe) items: everything an
-// item needs that does not depend on the probe.
+// item needs that does not depend on the probe (56 bytes).
+//   pk     n_pr (bits 0-6) | node count (7-9) | material (10-14) | l + 1024 (15-25)
+//   nd[2]  per node 9 bits, two nodes per word at bits 0 and 16:
+//          top level (bit 0: level l + 1) | k << 1 | m << 4
+// The bottom area level l lies in [-300, 256] for FP32 derivatives (|det J|
+// is a product of two FP32 values), so l + 1024 takes 11 bits.
 struct PixelRec {
     double ex, ey;             // sigma0 * major axis direction
-    uint32_t pk;               // npr | n_nodes << 8 | mat << 16
+    uint32_t pk;
     float alpha, kpx, lam_i;   // roughness, D(n)/(R N P 4 <wi,n>), Smith Lambda of the view
-    float dlam_i;              // d Lambda(view) / d alpha (adjoint only)
-    uint32_t nwd[4];           // node key words: (l + 1024) | k << 11 | m << 14
+    uint32_t nd[2];
     float ng[4];               // trials per node, w N 2^l (Eq. 10)
 };
+
+__device__ __forceinline__ int rec_npr(const PixelRec &R) { return (int)(R.pk & 0x7fu); }
+__device__ __forceinline__ int rec_nodes(const PixelRec &R) { return (int)((R.pk >> 7) & 7u); }
+__device__ __forceinline__ int rec_mat(const PixelRec &R) { return (int)((R.pk >> 10) & 31u); }
+
+// key word (l + 1024) | k << 11 | m << 14 of node g
+__device__ __forceinline__ uint32_t rec_node_word(const PixelRec &R, int g)
+{
+    const uint32_t d = (R.nd[g >> 1] >> ((g & 1) * 16)) & 0x1ffu;
+    return (((R.pk >> 15) & 0x7ffu) + (d & 1u)) | (((d >> 1) & 7u) << 11) | ((d >> 4) << 14);
+}
 
 // ---------------------------------------------------------------------------
 // Simplex lattice of grid node (l, k, m) around point c (Eq. 12 read as
@@ -574,20 +589,22 @@ __device__ __forceinline__ PixelRec make_rec(const Pixel &px, const Shared &sh)
     const DevMaterial &M = sh.mats[px.mat];
     r.ex = px.ex;
     r.ey = px.ey;
-    r.pk = (uint32_t)px.npr | ((uint32_t)px.n_nodes << 8) | ((uint32_t)px.mat << 16);
+    r.pk = (uint32_t)px.npr | ((uint32_t)px.n_nodes << 7) | ((uint32_t)px.mat << 10) |
+           ((uint32_t)(px.level + 1024) << 15);
     r.alpha = px.alpha;
     // D_P = D(n) b / (R N P) with D(n) = 1/(pi alpha^2); L = E F G D_P / (4 <wi,n>)
     r.kpx = (float)(1.0 / ((double)M.R * (double)px.N * px.P * kPi * (double)px.alpha * (double)px.alpha * 4.0 *
                            px.cos_i));
     const float ci = (float)px.cos_i, si2 = (float)(1.0 - px.cos_i * px.cos_i);
     r.lam_i = smith_lambda(M.ndf, px.alpha, ci, si2);
-    float dl_dc;
-    smith_lambda_grad(M.ndf, px.alpha, ci, si2, dl_dc, r.dlam_i);
+    uint32_t d[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        r.nwd[g] = node_word(px.nl[g], px.nk[g], px.nm[g]);
+        d[g] = (uint32_t)(px.nl[g] - px.level) | ((uint32_t)px.nk[g] << 1) | ((uint32_t)px.nm[g] << 4);
         r.ng[g] = px.nw[g] * ldexpf(px.N, px.nl[g]);          // Eq. 10: w_g N 2^l_g trials
     }
+    r.nd[0] = d[0] | (d[1] << 16);
+    r.nd[1] = d[2] | (d[3] << 16);
     return r;
 }
 
@@ -597,14 +614,14 @@ __device__ __forceinline__ void probe_texels(const PixelRec &R, double u, double
                                              const Shared &sh, uint32_t pre[4][3], SM &sm, uint32_t *key_sum)
 {
     const int lane = threadIdx.x;
-    const int npr = R.pk & 0xff, nn = (R.pk >> 8) & 0xff;
+    const int npr = rec_npr(R), nn = rec_nodes(R);
     // probe centre, uniform along the major axis over length sigma0
     const double off = ((double)kp + 0.5) / (double)npr - 0.5;
     const double cx = u + off * R.ex, cy = v + off * R.ey;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         if (g < nn) {
-            const uint32_t w = R.nwd[g];
+            const uint32_t w = rec_node_word(R, g);
             const int l = (int)(w & 0x7ffu) - 1024, k = (w >> 11) & 7, m = w >> 14;
             int vi[3], vj[3];
             float beta[3];

@@ -40,20 +40,19 @@ struct ItemOut {
     float b[kMaxLight];
 };
 
-struct RgbOut {
-    float rgb[3];
-};
-
-// Per-wave LDS.  Values the open-gate loop reads with a per-lane index live
-// here ([slot][lane], conflict-free) rather than in registers, which cannot
-// be indexed per lane.
+// Per-wave LDS (9984 bytes without the debug slots: 16 workgroups per CU).
+// Values the open-gate loop reads with a per-lane index live here
+// ([slot][lane], conflict-free) rather than in registers, which cannot be
+// indexed per lane.  Column `lane` of pre[][] is private to that lane while
+// its item runs; afterwards rows 0-2 of the column hold the item's RGB for
+// the pixel lanes' sums.
 template <bool DEBUG>
 struct TileSmem {
     int off[kWave];
     PixelRec rec[kWave];
     uint32_t pre[12][kWave];   // texel key hashes of each lane's item, [node*3 + vertex][lane]
     float beta[12][kWave];     // their barycentric weights
-    typename std::conditional<DEBUG, ItemOut, RgbOut>::type slot[kWave];
+    ItemOut dslot[DEBUG ? kWave : 1];
 };
 
 // ---------------------------------------------------------------------------
@@ -77,8 +76,8 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
         o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
     }
-    const int nn = (R.pk >> 8) & 0xff, mat = R.pk >> 16;
-    const DevMaterial &M = sh.mats[mat];
+    const int nn = rec_nodes(R);
+    const DevMaterial &M = sh.mats[rec_mat(R)];
     uint32_t pre[4][3];
     probe_texels(R, u, v, kp, M, sh, pre, sm, DEBUG ? &o.key_sum : (uint32_t *)nullptr);
     double tt[3], bb[3];
@@ -225,31 +224,30 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             ItemOut o;
             shade_item<DEBUG>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm, o);
-            sm.slot[lane].rgb[0] = o.rgb[0];
-            sm.slot[lane].rgb[1] = o.rgb[1];
-            sm.slot[lane].rgb[2] = o.rgb[2];
             if constexpr (DEBUG) {
-                sm.slot[lane].key_sum = o.key_sum;
-                sm.slot[lane].theta_sum = o.theta_sum;
-                sm.slot[lane].count_sum = o.count_sum;
-                sm.slot[lane].n_open = o.n_open;
-                sm.slot[lane].n_gate = o.n_gate;
-                sm.slot[lane].n_live = o.n_live;
-                for (int l = 0; l < kMaxLight; ++l) sm.slot[lane].b[l] = o.b[l];
+                sm.dslot[lane] = o;
+            } else {
+                sm.pre[0][lane] = __float_as_uint(o.rgb[0]);
+                sm.pre[1][lane] = __float_as_uint(o.rgb[1]);
+                sm.pre[2][lane] = __float_as_uint(o.rgb[2]);
             }
         }
         __syncthreads();
         if (npr > 0) {
             const int i0 = max(off, base), i1 = min(off + npr, base + kWave);
             for (int i = i0; i < i1; ++i) {
-                const auto &s = sm.slot[i - base];
-                acc[0] += s.rgb[0];
-                acc[1] += s.rgb[1];
-                acc[2] += s.rgb[2];
                 if constexpr (DEBUG) {
+                    const ItemOut &s = sm.dslot[i - base];
+                    acc[0] += s.rgb[0];
+                    acc[1] += s.rgb[1];
+                    acc[2] += s.rgb[2];
                     dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
                     dnl += s.n_live;
                     for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
+                } else {
+                    acc[0] += __uint_as_float(sm.pre[0][i - base]);
+                    acc[1] += __uint_as_float(sm.pre[1][i - base]);
+                    acc[2] += __uint_as_float(sm.pre[2][i - base]);
                 }
             }
         }
