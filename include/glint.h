@@ -133,15 +133,30 @@ typedef struct {
 
 typedef struct glint_plan glint_plan;
 
+/* Workspace of glint_shade for a width x height view, in bytes (0 when the
+ * view is empty): about 5.5 bytes per 8x8 tile. */
+size_t glint_shade_workspace_bytes(int32_t width, int32_t height);
+
 /* Forward shading of one view: out_rgb[3][height*stride] <- radiance
  * L = sum_l E_l F G D_P / (4 <w,n>) with D_P = D(n) b / (R N P)
  * (Eqs. 1-4, 10, 14, 16-18).  n_mat in [1, 32], n_light in [0, 16].
- * dbg may be NULL.  Errors: ENULL (gbuf, planes, mats, out_rgb, lights when
- * n_light > 0), ESHAPE (width/height < 0, stride < width), EINVAL (params or
- * material values out of range), EHIP (launch failure). */
+ * dbg may be NULL.
+ * workspace: device memory of at least glint_shade_workspace_bytes(width,
+ * height) bytes, 4-byte aligned, owned by the caller and used by this call
+ * only (calls that overlap on the device need their own).  With a workspace
+ * the 8x8 tiles are shaded heaviest first (a cost pre-pass over the
+ * derivatives orders them by their number of probe items; the first
+ * 4*n_tiles bytes then hold that order as int32 tile indices, row-major tile
+ * numbering); with workspace == NULL they are shaded in row-major order.
+ * The image is bit-identical either way.
+ * Errors: ENULL (gbuf, planes, mats, out_rgb, lights when n_light > 0),
+ * ESHAPE (width/height < 0, stride < width, workspace_bytes too small),
+ * EINVAL (params or material values out of range, misaligned workspace),
+ * EHIP (launch failure). */
 int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                 const glint_light *lights, int32_t n_light, const glint_params *params,
-                float *out_rgb, const glint_debug *dbg, void *stream);
+                float *out_rgb, const glint_debug *dbg, void *workspace, size_t workspace_bytes,
+                void *stream);
 
 /* Workspace for glint_shade_backward, in bytes. */
 size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_mat, int32_t n_light);

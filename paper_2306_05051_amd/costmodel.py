@@ -1,47 +1,74 @@
 """Algorithmic work of one glint-shading launch, in VALU issue slots.
 
 The path is ALU-bound (60 bytes of G-buffer and output per pixel against
-thousands of VALU operations), so its roofline is the VALU issue rate:
-256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-slots/s.  A slot is
-one lane-instruction issue; quarter-rate instructions (32-bit integer
-multiply, FP32/FP64 transcendentals and square roots) count 4.
+thousands of VALU operations), so its roofline is the FP32 VALU issue rate.
 
-Per-unit costs are the minimal instruction sequences of each step of the
-method on gfx950 (the compiler already fuses xor+add into v_xad_u32 and
-x ^ (x >> 16) into one SDWA xor):
+Peak.  A gfx950 SIMD issues 64-lane FP32/INT32 VALU instructions at one per
+two clocks when at least two waves are resident (one wave alone issues one
+per four clocks), i.e. 32 lane-operations per clock per SIMD:
+    256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.64e12 lane-slots/s,
+the vendor's FP32 vector peak (157.3 TFLOP/s) counted as FMAs.  valu_probe
+(built with the library) measures 0.42-0.47 wave-instructions per clock per
+SIMD for v_mul_f32 at 16 waves per SIMD and 0.21 with one wave.
 
-  hash step H(h, w) = fmix32((h ^ w) + c): xad, xor-shift, mul_lo, shift, xor,
-      mul_lo, xor-shift = 5 + 2 x 4 = 13 slots
-  live gate (gate probability reaches the smallest uniform 2^-24; the others
-      cannot open and need no work): H + compare + mask insert = 15
-  open gate (extra): slot-1 angular key (pack 3 + H 13), H 13, inverse normal
-      CDF 22, node mean/sigma 9, count 3, bilinear weight and accumulate 5 = 68
-  item-light (one pixel, probe, light): FP64 half vector 27, cosines 11, GGX
-      ratio 10, angular cell 20, log(1-p) 12, 4 gate set-ups 4 x 19 = 76,
-      4 slot-0 angular keys 64, Fresnel 4, Smith masking 16, radiance 3 = 243
-  item (one pixel, probe): probe centre 12, 4 x (simplex locate 28 + node hash
-      13 + 6 texel-key hashes 78 + 6 LDS stores) = 500, frame 10, FP64
-      normalisation of n and w 30 = 552
-  pixel: FP64 footprint moments/eigenvalue 60, atan2 60, sincos 60, probe split
-      and area level 25, log2 40, cell and tetrahedron 70, weights and record 65 = 380
+Slot costs.  One slot is one lane-operation at that rate; the probe's rates
+per instruction class give
+    FP32 add/mul/FMA/compare/select, INT32 add/logic/shift, cvt  1
+    v_mul_lo_u32, FP64 add/mul/FMA/compare/convert                2
+    FP32 exp/log/rcp/rsq/sqrt                                     4
+    FP64 rcp/rsq seeds                                            8
+An FP64 square root or quotient is a seed plus about six FP64 operations:
+20 slots.
+
+Per-unit costs: the minimal instruction sequence of each step of the method
+at the path's precision (FP64 for the footprint, the grid transforms, the
+half vector and the angular projection; FP32 for the rest; exact integers for
+keys and gates):
+
+  hash step H(h, w) = fmix32((h ^ w) + c): xor-add, xor-shift, mul_lo, shift,
+      xor, mul_lo, xor-shift = 5 + 2 x 2 = 9
+  live gate (its node's gate probability reaches the smallest uniform 2^-24;
+      the others provably cannot open and need no work): H + compare + mask
+      insert = 12
+  open gate (extra): slot-1 angular key (pack 3 + H) 12, H 9, inverse normal
+      CDF (bits to x, 1-x, 1+x 7, log 6, select 1, polynomial 9, scale 2) 25,
+      node mean/sigma 11, Gaussian 1, count 2, bilinear weight and
+      accumulate 5 = 65
+  item-light (one pixel, probe, light): <n,wo> 8, h = wi + wo 6, |h| 26, h/|h|
+      26, <n,h> 6, cos^2/sin^2 8, GGX ratio p 12, angular cell and bilinear
+      fractions 44, Fresnel 15, Smith Lambda(wo) 20, log(1-p) 21, 4 gate
+      set-ups (trials x log, 1-exp, guards, threshold, shift) 4 x 28 = 112,
+      4 slot-0 angular keys 4 x 12 = 48, radiance 13 = 365
+  item (one pixel, probe): probe centre 36, FP64 tangent frame 42, 4 x (key
+      unpack 5, trig table index 3, rotation 8, anisotropic scales 14, lattice
+      shear/floor/fractions 18, triangle 2, vertex selects 6, barycentrics 10,
+      node hash 9, 6 texel-key hashes 54) = 4 x 129 = 516, probe sum 3 = 597
+  pixel: density 5, FP64 normalisation of n and w 116, footprint moments 24,
+      <n,wi> 6, eigenvalue and ratio 54, atan2 80, sigma0 and sincos 84, probe
+      split 52, area level 6, ratio/orientation cell, triangle, merge, sort,
+      tetrahedron and node words 180, D(n)/(R N P 4<wi,n>) and Lambda(wi) 56
+      = 663
 
 Units are counted exactly by the library's instrumented kernel (debug
-planes).  Loop control, address arithmetic, LDS traffic, recomputation and
-idle lanes are not credited, so the achieved rate is a lower bound on the
-issue rate the kernel sustains.
+planes).  Loop control, address arithmetic, LDS traffic, recomputation,
+scheduling and idle lanes are not credited, so the achieved rate is a lower
+bound on the issue rate the kernel sustains.
 """
 from __future__ import annotations
 
-VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9          # lane-slots / s
-FP32_PEAK_FLOPS = 157.3e12                       # vendor dense FP32 vector (packed FMA)
+CU, SIMD_PER_CU, LANES_PER_CLK, CLOCK_HZ = 256, 4, 32, 2.4e9
+VALU_PEAK_SLOTS = CU * SIMD_PER_CU * LANES_PER_CLK * CLOCK_HZ    # lane-slots / s (78.64e12)
+FP32_PEAK_FLOPS = 157.3e12                                       # vendor dense FP32 vector (FMA = 2 flops)
 
-HASH = 13
+HASH = 5 + 2 * 2
+FP64_SQRT = FP64_DIV = 8 + 6 * 2
 COST = {
-    "live_gate": HASH + 2,
-    "open_gate": 3 + HASH + HASH + 22 + 9 + 3 + 5,
-    "item_light": 27 + 11 + 10 + 20 + 12 + 4 * 19 + 4 * (3 + HASH) + 4 + 16 + 3,
-    "item": 12 + 4 * (28 + HASH + 6 * HASH + 6) + 10 + 30,
-    "pixel": 380,
+    "live_gate": HASH + 1 + 2,
+    "open_gate": (3 + HASH) + HASH + 25 + 11 + 1 + 2 + 5,
+    "item_light": (8 + 6 + (6 + FP64_SQRT) + (FP64_DIV + 6) + 6 + 8 + 12 + 44 + 15 + 20 + 21 + 4 * 28
+                   + 4 * (3 + HASH) + 13),
+    "item": 36 + 42 + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + HASH + 6 * HASH) + 3,
+    "pixel": 663,
 }
 
 

@@ -276,12 +276,190 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     }
 }
 
+// One workgroup per tile.  With a tile order (cost classes, heaviest first)
+// workgroup b shades tile order[b]; without one, tiles go in row-major order.
 template <bool DEBUG>
-__global__ __launch_bounds__(64) void glint_fwd_kernel(ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x)
+__global__ __launch_bounds__(64) void glint_fwd_kernel(ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x,
+                                                       const int32_t *__restrict__ order, int32_t n_tiles)
 {
     __shared__ TileSmem<DEBUG> sm;
-    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int t = order ? __builtin_amdgcn_readfirstlane(order[blockIdx.x]) : (int)blockIdx.x;
+    if ((unsigned)t >= (unsigned)n_tiles) return;
+    const int tx = t % tiles_x, ty = t / tiles_x;
     shade_tile<DEBUG>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Tile order for glint_shade: a stable counting sort of the 8x8 tiles by cost
+// class, heaviest class first, so that the long tiles (footprints split into
+// many probes) start early instead of trailing at the end of the grid.  The
+// order only schedules work; every tile's arithmetic is unchanged.
+//   count:   tile cost S = sum of the pixels' probe counts (an FP32 estimate
+//            of the forward's n_pr), class of ceil(S / 64) item batches;
+//            per block of kOrderTiles tiles, the count of each class
+//   scan:    one workgroup turns the counts into output offsets
+//   scatter: one workgroup per block ranks its tiles within each class
+// ---------------------------------------------------------------------------
+constexpr int kOrderClasses = 8;
+constexpr int kOrderTiles = 64;       // tiles per count block
+constexpr int kOrderWaves = 16;       // waves per count workgroup (4 tiles each)
+constexpr int kScatterWaves = kOrderTiles / kWave;
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ int cost_class(int S)
+{
+    const int b = (S + kWave - 1) / kWave;
+    return b < 4 ? b : (b < 6 ? 4 : (b < 9 ? 5 : (b < 14 ? 6 : 7)));
+}
+
+// probe count n_pr of a pixel as the forward computes it, in FP32 (an
+// estimate: only the order of the tiles depends on it)
+__device__ __forceinline__ int probe_estimate(const ViewDesc &vw, int64_t idx, int n_mat, float inv_rmax,
+                                              int n_probe_max)
+{
+    const int mat = vw.mat ? vw.mat[idx] : 0;
+    if (mat < 0 || mat >= n_mat) return 0;
+    const float dux = vw.dudx[idx], dvx = vw.dvdx[idx], duy = vw.dudy[idx], dvy = vw.dvdy[idx];
+    const float a = dux * dux + duy * duy, b = dux * dvx + duy * dvy, c = dvx * dvx + dvy * dvy;
+    const float P = fabsf(dux * dvy - duy * dvx);
+    const float hd = 0.5f * (a - c);
+    const float r = (0.5f * (a + c) + __builtin_amdgcn_sqrtf(hd * hd + b * b)) / P;
+    const float n = ceilf(r * inv_rmax);
+    return n >= 1.0f ? (n < (float)n_probe_max ? (int)n : n_probe_max) : 1;
+}
+
+__global__ __launch_bounds__(kWave * kOrderWaves) void glint_order_count(ViewDesc vw, int tiles_x, int32_t n_tiles,
+                                                                         int n_mat, float inv_rmax,
+                                                                         int n_probe_max, uint8_t *cls,
+                                                                         uint32_t *cnt)
+{
+    constexpr int kPerWave = kOrderTiles / kOrderWaves;
+    __shared__ uint32_t s_cnt[kOrderWaves][kOrderClasses];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t t0 = (int64_t)blockIdx.x * kOrderTiles + w * kPerWave;
+    int S[kPerWave];
+#pragma unroll
+    for (int i = 0; i < kPerWave; ++i) {
+        const int64_t t = t0 + i;
+        const int x = (int)(t % tiles_x) * 8 + (lane & 7), y = (int)(t / tiles_x) * 8 + (lane >> 3);
+        S[i] = (t < n_tiles && x < vw.width && y < vw.height)
+                   ? probe_estimate(vw, (int64_t)y * vw.stride + x, n_mat, inv_rmax, n_probe_max)
+                   : 0;
+    }
+    uint32_t mine = 0;                    // lane c < 8: this wave's count of class c
+#pragma unroll
+    for (int i = 0; i < kPerWave; ++i) {
+        int v = S[i];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        const int c = cost_class(v);
+        if (t0 + i < n_tiles) {
+            if (lane == 0) cls[t0 + i] = (uint8_t)c;
+            if (lane == c) ++mine;
+        }
+    }
+    if (lane < kOrderClasses) s_cnt[w][lane] = mine;
+    __syncthreads();
+    if (threadIdx.x < kOrderClasses) {
+        uint32_t n = 0;
+        for (int j = 0; j < kOrderWaves; ++j) n += s_cnt[j][threadIdx.x];
+        cnt[(int64_t)blockIdx.x * kOrderClasses + threadIdx.x] = n;
+    }
+}
+
+// counts cnt[block][class] -> offs[block][class]: class c's tiles of block b
+// start at (tiles of heavier classes) + (class-c tiles of blocks before b)
+__global__ __launch_bounds__(kScanThreads) void glint_order_scan(const uint32_t *__restrict__ cnt,
+                                                                 uint32_t *__restrict__ offs, int64_t n_blk)
+{
+    constexpr int kScanWaves = kScanThreads / kWave;
+    __shared__ uint32_t s_wt[kOrderClasses][kScanWaves];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t per = (n_blk + kScanThreads - 1) / kScanThreads;
+    const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < n_blk ? b0 + per : n_blk;
+    uint32_t loc[kOrderClasses];
+#pragma unroll
+    for (int c = 0; c < kOrderClasses; ++c) loc[c] = 0;
+    for (int64_t b = b0; b < b1; ++b)
+#pragma unroll
+        for (int c = 0; c < kOrderClasses; ++c) loc[c] += cnt[b * kOrderClasses + c];
+    // exclusive prefix of this thread's chunk within its wave, per class
+#pragma unroll
+    for (int c = 0; c < kOrderClasses; ++c) {
+        uint32_t v = loc[c];
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t u = __shfl_up(v, d);
+            if (lane >= d) v += u;
+        }
+        if (lane == kWave - 1) s_wt[c][w] = v;
+        loc[c] = v - loc[c];
+    }
+    __syncthreads();
+    uint32_t base = 0, run[kOrderClasses];
+#pragma unroll
+    for (int c = kOrderClasses - 1; c >= 0; --c) {
+        uint32_t tot = 0, pre = 0;
+        for (int j = 0; j < kScanWaves; ++j) {
+            const uint32_t x = s_wt[c][j];
+            tot += x;
+            if (j < w) pre += x;
+        }
+        run[c] = base + pre + loc[c];
+        base += tot;
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+        uint32_t n[kOrderClasses];
+#pragma unroll
+        for (int c = 0; c < kOrderClasses; ++c) n[c] = cnt[b * kOrderClasses + c];
+#pragma unroll
+        for (int c = 0; c < kOrderClasses; ++c) {
+            offs[b * kOrderClasses + c] = run[c];
+            run[c] += n[c];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kOrderTiles) void glint_order_scatter(const uint8_t *__restrict__ cls,
+                                                                   const uint32_t *__restrict__ offs,
+                                                                   int32_t n_tiles, int32_t *__restrict__ order)
+{
+    __shared__ uint32_t s_wc[kScatterWaves][kOrderClasses];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t t = (int64_t)blockIdx.x * kOrderTiles + threadIdx.x;
+    const int c = t < n_tiles ? (int)cls[t] : -1;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t rank = 0;
+#pragma unroll
+    for (int cc = 0; cc < kOrderClasses; ++cc) {
+        const uint64_t m = __ballot(c == cc);
+        if (c == cc) rank = (uint32_t)__popcll(m & below);
+        if (lane == cc) s_wc[w][cc] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (c >= 0) {
+        uint32_t pos = offs[(int64_t)blockIdx.x * kOrderClasses + c] + rank;
+        for (int j = 0; j < w; ++j) pos += s_wc[j][c];
+        order[pos] = (int32_t)t;
+    }
+}
+
+struct OrderLayout {
+    int64_t n_tiles, n_blk;
+    size_t cls_off, cnt_off, offs_off, bytes;
+};
+
+static OrderLayout order_layout(int32_t width, int32_t height)
+{
+    OrderLayout L;
+    L.n_tiles = (int64_t)((width + 7) / 8) * ((height + 7) / 8);
+    L.n_blk = (L.n_tiles + kOrderTiles - 1) / kOrderTiles;
+    const size_t a = 256, cb = (size_t)L.n_blk * kOrderClasses * 4;
+    L.cls_off = ((size_t)L.n_tiles * 4 + a - 1) / a * a;
+    L.cnt_off = L.cls_off + ((size_t)L.n_blk * kOrderTiles + a - 1) / a * a;
+    L.offs_off = L.cnt_off + (cb + a - 1) / a * a;
+    L.bytes = L.offs_off + cb;
+    return L;
 }
 
 // wave-uniform copies (scalar registers) of a descriptor's fields
@@ -432,8 +610,15 @@ const char *glint_status_string(int s)
     }
 }
 
+size_t glint_shade_workspace_bytes(int32_t width, int32_t height)
+{
+    if (width <= 0 || height <= 0) return 0;
+    return order_layout(width, height).bytes;
+}
+
 int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat, const glint_light *lights,
-                int32_t n_light, const glint_params *params, float *out_rgb, const glint_debug *dbg, void *stream)
+                int32_t n_light, const glint_params *params, float *out_rgb, const glint_debug *dbg,
+                void *workspace, size_t workspace_bytes, void *stream)
 {
     Shared sh;
     int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
@@ -448,15 +633,34 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     const int64_t nt = (int64_t)tiles_x * tiles_y;
     if (nt > 0x7fffffffLL) return GLINT_ESHAPE;
     hipStream_t st = (hipStream_t)stream;
+    const int32_t *order = nullptr;
+    if (workspace) {
+        const OrderLayout L = order_layout(vw.width, vw.height);
+        if (workspace_bytes < L.bytes) return GLINT_ESHAPE;
+        if ((uintptr_t)workspace & 3u) return GLINT_EINVAL;
+        if (L.n_blk > 0x7fffffffLL) return GLINT_ESHAPE;
+        char *ws = (char *)workspace;
+        int32_t *ord = (int32_t *)ws;
+        uint8_t *cls = (uint8_t *)(ws + L.cls_off);
+        uint32_t *cnt = (uint32_t *)(ws + L.cnt_off);
+        uint32_t *offs = (uint32_t *)(ws + L.offs_off);
+        const float inv_rmax = 1.0f / (float)(1 << sh.k_max);
+        hipLaunchKernelGGL(glint_order_count, dim3((unsigned)L.n_blk), dim3(kWave * kOrderWaves), 0, st, vw, tiles_x,
+                           (int32_t)nt, sh.n_mat, inv_rmax, sh.n_probe_max, cls, cnt);
+        hipLaunchKernelGGL(glint_order_scan, dim3(1), dim3(kScanThreads), 0, st, cnt, offs, L.n_blk);
+        hipLaunchKernelGGL(glint_order_scatter, dim3((unsigned)L.n_blk), dim3(kOrderTiles), 0, st, cls, offs,
+                           (int32_t)nt, ord);
+        order = ord;
+    }
     if (dbg) {
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light};
         hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
-                           log2_tile(tile_w), tiles_x);
+                           log2_tile(tile_w), tiles_x, order, (int32_t)nt);
     } else {
         DebugPlanes dp = {};
         hipLaunchKernelGGL(glint_fwd_kernel<false>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
-                           log2_tile(tile_w), tiles_x);
+                           log2_tile(tile_w), tiles_x, order, (int32_t)nt);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);

@@ -83,7 +83,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.glint_shade.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
-                                  C.POINTER(_Params), vp, C.POINTER(_Debug), vp]
+                                  C.POINTER(_Params), vp, C.POINTER(_Debug), vp, C.c_size_t, vp]
+        L.glint_shade_workspace_bytes.argtypes = [i32, i32]
+        L.glint_shade_workspace_bytes.restype = C.c_size_t
         L.glint_backward_workspace_bytes.argtypes = [i32, i32, i32, i32]
         L.glint_backward_workspace_bytes.restype = C.c_size_t
         L.glint_shade_backward.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
@@ -168,15 +170,30 @@ def to_device(gb_np, device="cuda"):
     return out
 
 
+def glint_shade_workspace_bytes(width, height):
+    return lib().glint_shade_workspace_bytes(width, height)
+
+
 def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, out=None, debug=False,
-                stream=None):
-    """Radiance [3, H, W] float32 (and a dict of debug planes when debug=True)."""
+                workspace=None, stream=None):
+    """Radiance [3, H, W] float32 (and a dict of debug planes when debug=True).
+
+    workspace: None allocates the tile-order workspace (heaviest tiles first),
+    False shades the tiles in row-major order without one, a uint8 CUDA tensor
+    of at least glint_shade_workspace_bytes(W, H) bytes is used as given."""
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
     dev = gbuf["u"].device
     if out is None:
         out = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    nbytes = L.glint_shade_workspace_bytes(W, H)
+    if workspace is False or nbytes == 0:
+        ws_ptr, ws_bytes = None, 0
+    else:
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        ws_ptr, ws_bytes = _dev_ptr(workspace, torch.uint8, "workspace"), workspace.numel()
     dbg = None
     planes = {}
     if debug:
@@ -188,14 +205,14 @@ def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, ou
         dbg.b_light = planes["b_light"].data_ptr()
     prm = make_params(k_max, n_probe_max, rounding)
     st = glint_shade_raw(g, make_materials(materials), len(materials), make_lights(lights), len(lights),
-                         prm, _dev_ptr(out, torch.float32, "out"), dbg, _stream(stream))
+                         prm, _dev_ptr(out, torch.float32, "out"), dbg, _stream(stream), ws_ptr, ws_bytes)
     _check(st, "glint_shade")
     return (out, planes) if debug else out
 
 
-def glint_shade_raw(g, mats, n_mat, lts, n_light, prm, out_ptr, dbg, stream_ptr):
+def glint_shade_raw(g, mats, n_mat, lts, n_light, prm, out_ptr, dbg, stream_ptr, ws_ptr=None, ws_bytes=0):
     return lib().glint_shade(C.byref(g), mats, n_mat, lts, n_light, C.byref(prm), out_ptr,
-                             C.byref(dbg) if dbg is not None else None, stream_ptr)
+                             C.byref(dbg) if dbg is not None else None, ws_ptr, ws_bytes, stream_ptr)
 
 
 def glint_backward_workspace_bytes(width, height, n_mat, n_light):

@@ -51,17 +51,31 @@ def test_host_validation_without_device(lib):
     g.width, g.height, g.stride = 4, 4, 4
     out = C.c_void_p(0)
     # NULL G-buffer planes
-    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(prm), out, None, None) == glint.GLINT_ENULL
+    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(prm), out, None, None, 0, None) == glint.GLINT_ENULL
     # stride < width
     g.stride = 2
-    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(prm), out, None, None) == glint.GLINT_ESHAPE
+    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(prm), out, None, None, 0, None) == glint.GLINT_ESHAPE
     g.stride = 4
     bad = glint.make_params(k_max=7)
-    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(bad), out, None, None) == glint.GLINT_EINVAL
-    assert L.glint_shade(C.byref(g), mats, 0, lts, 1, C.byref(prm), out, None, None) == glint.GLINT_EINVAL
-    assert L.glint_shade(C.byref(g), mats, 1, lts, 17, C.byref(prm), out, None, None) == glint.GLINT_EINVAL
+    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(bad), out, None, None, 0, None) == glint.GLINT_EINVAL
+    assert L.glint_shade(C.byref(g), mats, 0, lts, 1, C.byref(prm), out, None, None, 0, None) == glint.GLINT_EINVAL
+    assert L.glint_shade(C.byref(g), mats, 1, lts, 17, C.byref(prm), out, None, None, 0, None) == glint.GLINT_EINVAL
     badm = glint.make_materials([dict(alpha=0.3, log10_density=5.0, micro_roughness=1e-6)])
-    assert L.glint_shade(C.byref(g), badm, 1, lts, 1, C.byref(prm), out, None, None) == glint.GLINT_EINVAL
+    assert L.glint_shade(C.byref(g), badm, 1, lts, 1, C.byref(prm), out, None, None, 0, None) == glint.GLINT_EINVAL
+    # tile-order workspace: size formula, too small, misaligned (rejected before any launch)
+    assert L.glint_shade_workspace_bytes(0, 5) == 0
+    tiles = 480 * 270
+    assert L.glint_shade_workspace_bytes(3840, 2160) >= 5 * tiles
+    assert L.glint_shade_workspace_bytes(3840, 2160) < 6 * tiles + 4096
+    need = L.glint_shade_workspace_bytes(4, 4)
+    assert need > 0
+    for n in ("u", "v", "dudx", "dvdx", "dudy", "dvdy", "nx", "ny", "nz", "wx", "wy", "wz"):
+        setattr(g, n, 4096)
+    fake_out = C.c_void_p(8192)
+    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake_out, None, C.c_void_p(4096), need - 1,
+                         None) == glint.GLINT_ESHAPE
+    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake_out, None, C.c_void_p(4098), need,
+                         None) == glint.GLINT_EINVAL
     # utilities: negative sizes and NULL pointers
     assert L.glint_texel_hash(None, -1, None, None) == glint.GLINT_ESHAPE
     assert L.glint_texel_hash(None, 5, None, None) == glint.GLINT_ENULL
