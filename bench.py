@@ -158,17 +158,17 @@ def main():
         if args.no_backward:
             raise glint.GlintError(glint.GLINT_EUNSUPPORTED, "skipped (--no-backward)")
         go = torch.randn((3, H, W), device="cuda", dtype=torch.float32)
-        ws = torch.empty(max(1, glint.glint_backward_workspace_bytes(W, H, len(mats), len(lights))),
-                         dtype=torch.uint8, device="cuda")
+        wsb = torch.empty(max(1, glint.glint_backward_workspace_bytes(W, H, len(mats), len(lights))),
+                          dtype=torch.uint8, device="cuda")
         gbn = {k: v for k, v in dgb.items() if k not in ("alpha_px", "log10_density_px")}
-        glint.glint_shade_backward(gbn, mats, lights, go, workspace=ws)
+        glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb)
         torch.cuda.synchronize()
         n_fb = max(3, args.steps // 2)
         s0 = torch.cuda.Event(enable_timing=True); s1 = torch.cuda.Event(enable_timing=True)
         s0.record(stream)
         for _ in range(n_fb):
             glint.glint_shade(gbn, mats, lights, out=out, rounding=1, workspace=ws)
-            glint.glint_shade_backward(gbn, mats, lights, go, workspace=ws)
+            glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb)
         s1.record(stream)
         torch.cuda.synchronize()
         fb_ms = s0.elapsed_time(s1) / n_fb

@@ -171,7 +171,12 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * current parameters.  Gradients are accumulated in FP32 per pixel and
  * reduced in a fixed order (deterministic).  Per-pixel overrides
  * (alpha_px, log10_density_px) are not supported (EUNSUPPORTED).
- * workspace: device memory of glint_backward_workspace_bytes(). */
+ * workspace: device memory of at least glint_backward_workspace_bytes()
+ * bytes, 8-byte aligned, owned by the caller and used by this call only
+ * (tile order, one partial row per 8x8 tile, FP64 reduction stage).  Tiles
+ * run heaviest first; the sums are reduced in a fixed order over tiles, so
+ * the result does not depend on the schedule.  Errors as glint_shade, plus
+ * ENULL (workspace, gradient outputs), EINVAL (misaligned workspace). */
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                          const glint_light *lights, int32_t n_light, const glint_params *params,
                          const float *grad_out_rgb, float *grad_alpha, float *grad_ln_density,

@@ -11,8 +11,9 @@
 //
 // Reduction (deterministic): per light, a butterfly wave sum (every lane ends
 // with the same bits); per material, fixed-order LDS sums; per tile, one
-// partial row in the workspace; a second kernel sums the rows in FP64 in a
-// fixed order.
+// partial row in the workspace (row index = tile index, so the sums do not
+// depend on the order in which tiles run); two FP64 kernels then sum the rows
+// in a fixed order.  Tiles run heaviest first (the forward's tile order).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -174,7 +175,7 @@ __device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, 
             // h = (wi + wo)/|wi + wo|, wo = d/|d|: chain through both normalisations
             const float hx = (float)le.h[0], hy = (float)le.h[1], hz = (float)le.h[2];
             const float hd = gh[0] * hx + gh[1] * hy + gh[2] * hz;
-            const float ihl = (float)(1.0 / le.hl);
+            const float ihl = (float)le.ihl;
             const float gw[3] = {(gh[0] - hd * hx) * ihl + gon * (float)n[0],
                                  (gh[1] - hd * hy) * ihl + gon * (float)n[1],
                                  (gh[2] - hd * hz) * ihl + gon * (float)n[2]};
@@ -197,12 +198,15 @@ __device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, 
 }
 
 __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, const float *gout, int tiles_x,
-                                                       float *partials, int n_par)
+                                                       const int32_t *__restrict__ order, int32_t n_tiles,
+                                                       float *partials, int n_par, int row_stride)
 {
     __shared__ BwdSmem sm;
     const int lane = threadIdx.x;
     const int tile_w = 8, tile_h = 8;
-    const int x0 = (blockIdx.x % tiles_x) * tile_w, y0 = (blockIdx.x / tiles_x) * tile_h;
+    const int tile = order ? __builtin_amdgcn_readfirstlane(order[blockIdx.x]) : (int)blockIdx.x;
+    if ((unsigned)tile >= (unsigned)n_tiles) return;
+    const int x0 = (tile % tiles_x) * tile_w, y0 = (tile / tiles_x) * tile_h;
     const int x = x0 + (lane % tile_w), y = y0 + (lane / tile_w);
     const bool inb = (x < vw.width) && (y < vw.height);
     const int64_t idx = (int64_t)y * vw.stride + x;
@@ -268,30 +272,69 @@ __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, c
         }
         __syncthreads();
     }
-    float *row = partials + (int64_t)blockIdx.x * n_par;
-    if (lane < sh.n_mat) {
-        row[2 * lane] = acc_a;
-        row[2 * lane + 1] = acc_n;
+    // row of this tile: [alpha, lnN] per material, then 3 per light, zero padding to row_stride
+    float *row = partials + (int64_t)tile * row_stride;
+    for (int c0 = 0; c0 < row_stride; c0 += kWave) {       // uniform loop: every lane takes part in the shuffles
+        const int c = c0 + lane;
+        const int m = (c >> 1) & (kWave - 1);                // material of column c (lane m holds its sums)
+        const float va = __shfl(acc_a, m), vn = __shfl(acc_n, m);
+        float v = 0.0f;
+        if (c < 2 * sh.n_mat) v = (c & 1) ? vn : va;
+        else if (c < n_par) v = (&sm.dd[0][0])[c - 2 * sh.n_mat];
+        if (c < row_stride) row[c] = v;
     }
-    if (lane < 3 * sh.n_light) row[2 * sh.n_mat + lane] = (&sm.dd[0][0])[lane];
 }
 
-// sum column c of partials[n_rows][n_par] in FP64, fixed order, one block per column
-__global__ __launch_bounds__(256) void glint_bwd_reduce(const float *partials, int64_t n_rows, int n_par,
-                                                        int n_mat, float *g_alpha, float *g_lnN, float *g_dir)
+// Two-stage FP64 column sums of partials[n_rows][stride] (stride a power of
+// two <= 128, so 256 threads walking a row-aligned flat range always hit
+// column t % stride).  Stage 1: block b sums rows [b*rpb, (b+1)*rpb) into
+// stage1[b][stride]; stage 2: one block sums stage1's rows.  Every sum runs
+// in a fixed order.
+constexpr int kReduceThreads = 256;
+constexpr int kReduceBlocks = 512;
+
+template <typename T>
+__device__ __forceinline__ void column_sums(const T *__restrict__ flat, int64_t len, int stride, double *out)
 {
-    __shared__ double s[256];
-    const int c = blockIdx.x;
+    __shared__ double s[kReduceThreads];
     double acc = 0.0;
-    for (int64_t r = threadIdx.x; r < n_rows; r += 256) acc += (double)partials[r * n_par + c];
+    int64_t i = threadIdx.x;
+    for (; i + 7 * kReduceThreads < len; i += 8 * kReduceThreads) {      // loads batched, adds in order
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = flat[i + k * kReduceThreads];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += (double)v[k];
+    }
+    for (; i < len; i += kReduceThreads) acc += (double)flat[i];
     s[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
+    if ((int)threadIdx.x < stride) {
+        double v = 0.0;
+        for (int k = threadIdx.x; k < kReduceThreads; k += stride) v += s[k];
+        out[threadIdx.x] = v;
     }
-    if (threadIdx.x == 0) {
-        const float v = (float)s[0];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void glint_bwd_reduce1(const float *partials, int64_t n_rows,
+                                                                    int stride, int64_t rpb, double *stage1)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * rpb;
+    const int64_t r1 = r0 + rpb < n_rows ? r0 + rpb : n_rows;
+    column_sums(partials + r0 * stride, r1 > r0 ? (r1 - r0) * stride : 0, stride,
+                stage1 + (int64_t)blockIdx.x * stride);
+}
+
+__global__ __launch_bounds__(kReduceThreads) void glint_bwd_reduce2(const double *stage1, int n_blk, int stride,
+                                                                    int n_mat, int n_par, float *g_alpha,
+                                                                    float *g_lnN, float *g_dir)
+{
+    __shared__ double tot[128];
+    column_sums(stage1, (int64_t)n_blk * stride, stride, tot);
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < n_par) {
+        const float v = (float)tot[c];
         if (c < 2 * n_mat) {
             if (c & 1) g_lnN[c >> 1] = v; else g_alpha[c >> 1] = v;
         } else {
@@ -305,6 +348,33 @@ static int64_t bwd_tiles(int32_t width, int32_t height)
     return (int64_t)((width + 7) / 8) * ((height + 7) / 8);
 }
 
+static int row_stride_of(int n_par)
+{
+    int p = 1;
+    while (p < n_par) p <<= 1;
+    return p;
+}
+
+struct BwdLayout {
+    size_t part_off, stage1_off, bytes;
+    int stride;
+    int64_t rpb, n_blk;
+};
+
+static BwdLayout bwd_layout(int32_t width, int32_t height, int n_par)
+{
+    BwdLayout L;
+    const size_t a = 256;
+    const int64_t tiles = bwd_tiles(width, height);
+    L.stride = row_stride_of(n_par);
+    L.rpb = (tiles + kReduceBlocks - 1) / kReduceBlocks;
+    L.n_blk = L.rpb > 0 ? (tiles + L.rpb - 1) / L.rpb : 0;
+    L.part_off = (tile_order_bytes(width, height) + a - 1) / a * a;
+    L.stage1_off = L.part_off + ((size_t)tiles * L.stride * 4 + a - 1) / a * a;
+    L.bytes = L.stage1_off + (size_t)L.n_blk * L.stride * 8;
+    return L;
+}
+
 }  // namespace glint
 
 using namespace glint;
@@ -313,8 +383,8 @@ extern "C" {
 
 size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_mat, int32_t n_light)
 {
-    if (width <= 0 || height <= 0 || n_mat < 1 || n_light < 0) return 0;
-    return (size_t)bwd_tiles(width, height) * (size_t)(2 * n_mat + 3 * n_light) * sizeof(float);
+    if (width <= 0 || height <= 0 || n_mat < 1 || n_mat > kMaxMat || n_light < 0 || n_light > kMaxLight) return 0;
+    return bwd_layout(width, height, 2 * n_mat + 3 * n_light).bytes;
 }
 
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
@@ -344,15 +414,22 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
         return e == hipSuccess ? GLINT_OK : set_hip_error(e);
     }
     if (tiles > 0x7fffffffLL) return GLINT_ESHAPE;
-    const size_t need = (size_t)tiles * n_par * sizeof(float);
+    const BwdLayout L = bwd_layout(vw.width, vw.height, n_par);
     if (!workspace) return GLINT_ENULL;
-    if (workspace_bytes < need) return GLINT_ESHAPE;
+    if (workspace_bytes < L.bytes) return GLINT_ESHAPE;
+    if ((uintptr_t)workspace & 7u) return GLINT_EINVAL;
     const int tiles_x = (vw.width + 7) / 8;
-    float *partials = (float *)workspace;
+    const int32_t *order = nullptr;
+    rc = enqueue_tile_order(vw, sh, workspace, L.part_off, &order, st);
+    if (rc) return rc;
+    float *partials = (float *)((char *)workspace + L.part_off);
+    double *stage1 = (double *)((char *)workspace + L.stage1_off);
     hipLaunchKernelGGL(glint_bwd_kernel, dim3((unsigned)tiles), dim3(kWave), 0, st, vw, sh, grad_out_rgb, tiles_x,
-                       partials, n_par);
-    hipLaunchKernelGGL(glint_bwd_reduce, dim3((unsigned)n_par), dim3(256), 0, st, partials, tiles, n_par, n_mat,
-                       grad_alpha, grad_ln_density, grad_light_dir);
+                       order, (int32_t)tiles, partials, n_par, L.stride);
+    hipLaunchKernelGGL(glint_bwd_reduce1, dim3((unsigned)L.n_blk), dim3(kReduceThreads), 0, st, partials, tiles,
+                       L.stride, L.rpb, stage1);
+    hipLaunchKernelGGL(glint_bwd_reduce2, dim3(1), dim3(kReduceThreads), 0, st, stage1, (int)L.n_blk, L.stride,
+                       n_mat, n_par, grad_alpha, grad_ln_density, grad_light_dir);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);
 }

@@ -176,12 +176,36 @@ struct Pixel {
 
 __device__ __forceinline__ bool finitef(float x) { return (__float_as_uint(x) & 0x7f800000u) != 0x7f800000u; }
 
+// FP64 1/sqrt(x) and 1/x for finite x > 0 (x != 0 for the reciprocal): the
+// hardware seed (v_rsq_f64 / v_rcp_f64) refined by two Newton steps, a few
+// ulp from the correctly rounded value at a third of the cost of the IEEE
+// sequences.  Used where an ulp-level difference cannot decide anything
+// exactly (every decision downstream has a boundary margin).
+__device__ __forceinline__ double rsqrt_d(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-x * y, y, 1.0);      // 1 - x y^2
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+__device__ __forceinline__ double rcp_d(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
 // FP64 normalisation of an FP32 input vector (identical wherever it is used)
 __device__ __forceinline__ bool normalize_in(float x, float y, float z, double out[3])
 {
     double l2 = (double)x * x + (double)y * y + (double)z * z;
-    if (!(l2 > 0.0)) return false;
-    const double il = 1.0 / sqrt(l2);
+    if (!(l2 > 0.0)) return false;          // FP32 inputs: 0 < l2 < 4e77, rsq in range
+    const double il = rsqrt_d(l2);
     out[0] = x * il; out[1] = y * il; out[2] = z * il;
     return true;
 }
@@ -417,7 +441,7 @@ __device__ __forceinline__ void simplex_locate(double cx, double cy, int l, int 
 __device__ __forceinline__ void onb(const double n[3], double t[3], double b[3])
 {
     const double sgn = copysign(1.0, n[2]);
-    const double a = -1.0 / (sgn + n[2]);
+    const double a = -rcp_d(sgn + n[2]);           // |sgn + n_z| >= 1
     const double bb = n[0] * n[1] * a;
     t[0] = 1.0 + sgn * n[0] * n[0] * a; t[1] = sgn * bb; t[2] = -sgn * n[0];
     b[0] = bb; b[1] = sgn + n[1] * n[1] * a; b[2] = -n[1];
@@ -487,7 +511,7 @@ __device__ __forceinline__ float success_prob(int ndf, float alpha, float R, flo
 // adjoint so that both take identical decisions).
 struct LightEval {
     double h[3];               // half vector (FP64, unit)
-    double hl;                 // |wi + wo| before normalisation
+    double ihl;                // 1 / |wi + wo|
     double cos_o, ch;          // <n, wo>, <n, h>
     float p;                   // success probability (Eq. 4)
     bool pclamp;
@@ -505,9 +529,10 @@ __device__ __forceinline__ bool eval_light(const double pn[3], const double pwi[
     e.cos_o = px.n[0] * L.wo[0] + px.n[1] * L.wo[1] + px.n[2] * L.wo[2];
     if (!(e.cos_o > 0.0)) return false;
     double h0 = px.wi[0] + L.wo[0], h1 = px.wi[1] + L.wo[1], h2 = px.wi[2] + L.wo[2];
-    e.hl = sqrt(h0 * h0 + h1 * h1 + h2 * h2);
-    if (!(e.hl > 0.0)) return false;
-    const double ihl = 1.0 / e.hl;
+    const double hh = h0 * h0 + h1 * h1 + h2 * h2;
+    if (!(hh > 0.0)) return false;
+    const double ihl = rsqrt_d(hh);
+    e.ihl = ihl;
     e.h[0] = h0 * ihl; e.h[1] = h1 * ihl; e.h[2] = h2 * ihl;
     e.ch = px.n[0] * e.h[0] + px.n[1] * e.h[1] + px.n[2] * e.h[2];
     e.p = success_prob(M.ndf, px.alpha, M.R, (float)(e.ch * e.ch), (float)(1.0 - e.ch * e.ch), e.pclamp);
@@ -616,7 +641,7 @@ __device__ __forceinline__ void probe_texels(const PixelRec &R, double u, double
     const int lane = threadIdx.x;
     const int npr = rec_npr(R), nn = rec_nodes(R);
     // probe centre, uniform along the major axis over length sigma0
-    const double off = ((double)kp + 0.5) / (double)npr - 0.5;
+    const double off = ((double)kp + 0.5) * rcp_d((double)npr) - 0.5;
     const double cx = u + off * R.ex, cy = v + off * R.ey;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {

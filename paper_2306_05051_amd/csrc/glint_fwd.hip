@@ -462,6 +462,34 @@ static OrderLayout order_layout(int32_t width, int32_t height)
     return L;
 }
 
+size_t tile_order_bytes(int32_t width, int32_t height)
+{
+    if (width <= 0 || height <= 0) return 0;
+    return order_layout(width, height).bytes;
+}
+
+int enqueue_tile_order(const ViewDesc &vw, const Shared &sh, void *ws, size_t ws_bytes, const int32_t **order,
+                       hipStream_t st)
+{
+    const OrderLayout L = order_layout(vw.width, vw.height);
+    if (ws_bytes < L.bytes || L.n_tiles > 0x7fffffffLL) return GLINT_ESHAPE;
+    if ((uintptr_t)ws & 3u) return GLINT_EINVAL;
+    const int tiles_x = (vw.width + 7) / 8;
+    char *w = (char *)ws;
+    int32_t *ord = (int32_t *)w;
+    uint8_t *cls = (uint8_t *)(w + L.cls_off);
+    uint32_t *cnt = (uint32_t *)(w + L.cnt_off);
+    uint32_t *offs = (uint32_t *)(w + L.offs_off);
+    const float inv_rmax = 1.0f / (float)(1 << sh.k_max);
+    hipLaunchKernelGGL(glint_order_count, dim3((unsigned)L.n_blk), dim3(kWave * kOrderWaves), 0, st, vw, tiles_x,
+                       (int32_t)L.n_tiles, sh.n_mat, inv_rmax, sh.n_probe_max, cls, cnt);
+    hipLaunchKernelGGL(glint_order_scan, dim3(1), dim3(kScanThreads), 0, st, cnt, offs, L.n_blk);
+    hipLaunchKernelGGL(glint_order_scatter, dim3((unsigned)L.n_blk), dim3(kOrderTiles), 0, st, cls, offs,
+                       (int32_t)L.n_tiles, ord);
+    *order = ord;
+    return GLINT_OK;
+}
+
 // wave-uniform copies (scalar registers) of a descriptor's fields
 __device__ __forceinline__ int32_t uni32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -610,11 +638,7 @@ const char *glint_status_string(int s)
     }
 }
 
-size_t glint_shade_workspace_bytes(int32_t width, int32_t height)
-{
-    if (width <= 0 || height <= 0) return 0;
-    return order_layout(width, height).bytes;
-}
+size_t glint_shade_workspace_bytes(int32_t width, int32_t height) { return tile_order_bytes(width, height); }
 
 int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat, const glint_light *lights,
                 int32_t n_light, const glint_params *params, float *out_rgb, const glint_debug *dbg,
@@ -635,22 +659,8 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     hipStream_t st = (hipStream_t)stream;
     const int32_t *order = nullptr;
     if (workspace) {
-        const OrderLayout L = order_layout(vw.width, vw.height);
-        if (workspace_bytes < L.bytes) return GLINT_ESHAPE;
-        if ((uintptr_t)workspace & 3u) return GLINT_EINVAL;
-        if (L.n_blk > 0x7fffffffLL) return GLINT_ESHAPE;
-        char *ws = (char *)workspace;
-        int32_t *ord = (int32_t *)ws;
-        uint8_t *cls = (uint8_t *)(ws + L.cls_off);
-        uint32_t *cnt = (uint32_t *)(ws + L.cnt_off);
-        uint32_t *offs = (uint32_t *)(ws + L.offs_off);
-        const float inv_rmax = 1.0f / (float)(1 << sh.k_max);
-        hipLaunchKernelGGL(glint_order_count, dim3((unsigned)L.n_blk), dim3(kWave * kOrderWaves), 0, st, vw, tiles_x,
-                           (int32_t)nt, sh.n_mat, inv_rmax, sh.n_probe_max, cls, cnt);
-        hipLaunchKernelGGL(glint_order_scan, dim3(1), dim3(kScanThreads), 0, st, cnt, offs, L.n_blk);
-        hipLaunchKernelGGL(glint_order_scatter, dim3((unsigned)L.n_blk), dim3(kOrderTiles), 0, st, cls, offs,
-                           (int32_t)nt, ord);
-        order = ord;
+        rc = enqueue_tile_order(vw, sh, workspace, workspace_bytes, &order, st);
+        if (rc) return rc;
     }
     if (dbg) {
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,

@@ -14,6 +14,14 @@ namespace glint {
 
 int set_hip_error(hipError_t e);   // records e for glint_last_hip_error, returns GLINT_EHIP
 
+// Heaviest-first order of the 8x8 tiles of a view (row-major tile numbering),
+// built on `st` in `ws` (tile_order_bytes(width, height) bytes, 4-byte
+// aligned).  On success *order points at n_tiles int32 tile indices inside
+// ws.  Defined with the forward kernels.
+size_t tile_order_bytes(int32_t width, int32_t height);
+int enqueue_tile_order(const ViewDesc &vw, const Shared &sh, void *ws, size_t ws_bytes, const int32_t **order,
+                       hipStream_t st);
+
 inline bool finite_host(float x) { return std::isfinite(x); }
 
 // Validates materials / lights / params and fills the kernel-argument block.
