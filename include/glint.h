@@ -134,7 +134,7 @@ typedef struct {
 typedef struct glint_plan glint_plan;
 
 /* Workspace of glint_shade for a width x height view, in bytes (0 when the
- * view is empty): about 5.5 bytes per 8x8 tile. */
+ * view is empty): about 5.5 bytes per 64-pixel tile. */
 size_t glint_shade_workspace_bytes(int32_t width, int32_t height);
 
 /* Forward shading of one view: out_rgb[3][height*stride] <- radiance
@@ -143,11 +143,13 @@ size_t glint_shade_workspace_bytes(int32_t width, int32_t height);
  * dbg may be NULL.
  * workspace: device memory of at least glint_shade_workspace_bytes(width,
  * height) bytes, 4-byte aligned, owned by the caller and used by this call
- * only (calls that overlap on the device need their own).  With a workspace
- * the 8x8 tiles are shaded heaviest first (a cost pre-pass over the
- * derivatives orders them by their number of probe items; the first
- * 4*n_tiles bytes then hold that order as int32 tile indices, row-major tile
- * numbering); with workspace == NULL they are shaded in row-major order.
+ * only (calls that overlap on the device need their own).  The view is
+ * shaded in tiles of 32 x 2 pixels (one 64-lane wave each; n_tiles =
+ * ceil(width/32) * ceil(height/2)).  With a workspace the tiles are shaded
+ * heaviest first (a cost pre-pass over the derivatives orders them by their
+ * number of probe items; the first 4*n_tiles bytes then hold that order as
+ * int32 tile indices, row-major tile numbering); with workspace == NULL they
+ * are shaded in row-major order.
  * The image is bit-identical either way.
  * Errors: ENULL (gbuf, planes, mats, out_rgb, lights when n_light > 0),
  * ESHAPE (width/height < 0, stride < width, workspace_bytes too small),

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, c
 {
     __shared__ BwdSmem sm;
     const int lane = threadIdx.x;
-    const int tile_w = 8, tile_h = 8;
+    constexpr int tile_w = kTileW, tile_h = kTileH;
     const int tile = order ? __builtin_amdgcn_readfirstlane(order[blockIdx.x]) : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)n_tiles) return;
     const int x0 = (tile % tiles_x) * tile_w, y0 = (tile / tiles_x) * tile_h;
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kReduceThreads) void glint_bwd_reduce2(const double
 
 static int64_t bwd_tiles(int32_t width, int32_t height)
 {
-    return (int64_t)((width + 7) / 8) * ((height + 7) / 8);
+    return tiles_of(width, height);
 }
 
 static int row_stride_of(int n_par)
@@ -418,7 +418,7 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
     if (!workspace) return GLINT_ENULL;
     if (workspace_bytes < L.bytes) return GLINT_ESHAPE;
     if ((uintptr_t)workspace & 7u) return GLINT_EINVAL;
-    const int tiles_x = (vw.width + 7) / 8;
+    const int tiles_x = (int)tiles_x_of(vw.width);
     const int32_t *order = nullptr;
     rc = enqueue_tile_order(vw, sh, workspace, L.part_off, &order, st);
     if (rc) return rc;

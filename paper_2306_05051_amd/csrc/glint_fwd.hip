@@ -328,7 +328,7 @@ __device__ __forceinline__ int probe_estimate(const ViewDesc &vw, int64_t idx, i
     return n >= 1.0f ? (n < (float)n_probe_max ? (int)n : n_probe_max) : 1;
 }
 
-__global__ __launch_bounds__(kWave * kOrderWaves) void glint_order_count(ViewDesc vw, int tiles_x, int32_t n_tiles,
+__global__ __launch_bounds__(kWave * kOrderWaves) void glint_order_count(ViewDesc vw, int lw, int tiles_x, int32_t n_tiles,
                                                                          int n_mat, float inv_rmax,
                                                                          int n_probe_max, uint8_t *cls,
                                                                          uint32_t *cnt)
@@ -341,7 +341,8 @@ __global__ __launch_bounds__(kWave * kOrderWaves) void glint_order_count(ViewDes
 #pragma unroll
     for (int i = 0; i < kPerWave; ++i) {
         const int64_t t = t0 + i;
-        const int x = (int)(t % tiles_x) * 8 + (lane & 7), y = (int)(t / tiles_x) * 8 + (lane >> 3);
+        const int x = ((int)(t % tiles_x) << lw) + (lane & ((1 << lw) - 1));
+        const int y = ((int)(t / tiles_x) << (6 - lw)) + (lane >> lw);
         S[i] = (t < n_tiles && x < vw.width && y < vw.height)
                    ? probe_estimate(vw, (int64_t)y * vw.stride + x, n_mat, inv_rmax, n_probe_max)
                    : 0;
@@ -452,7 +453,7 @@ struct OrderLayout {
 static OrderLayout order_layout(int32_t width, int32_t height)
 {
     OrderLayout L;
-    L.n_tiles = (int64_t)((width + 7) / 8) * ((height + 7) / 8);
+    L.n_tiles = tiles_of(width, height);
     L.n_blk = (L.n_tiles + kOrderTiles - 1) / kOrderTiles;
     const size_t a = 256, cb = (size_t)L.n_blk * kOrderClasses * 4;
     L.cls_off = ((size_t)L.n_tiles * 4 + a - 1) / a * a;
@@ -474,14 +475,14 @@ int enqueue_tile_order(const ViewDesc &vw, const Shared &sh, void *ws, size_t ws
     const OrderLayout L = order_layout(vw.width, vw.height);
     if (ws_bytes < L.bytes || L.n_tiles > 0x7fffffffLL) return GLINT_ESHAPE;
     if ((uintptr_t)ws & 3u) return GLINT_EINVAL;
-    const int tiles_x = (vw.width + 7) / 8;
+    const int tiles_x = (int)tiles_x_of(vw.width);
     char *w = (char *)ws;
     int32_t *ord = (int32_t *)w;
     uint8_t *cls = (uint8_t *)(w + L.cls_off);
     uint32_t *cnt = (uint32_t *)(w + L.cnt_off);
     uint32_t *offs = (uint32_t *)(w + L.offs_off);
     const float inv_rmax = 1.0f / (float)(1 << sh.k_max);
-    hipLaunchKernelGGL(glint_order_count, dim3((unsigned)L.n_blk), dim3(kWave * kOrderWaves), 0, st, vw, tiles_x,
+    hipLaunchKernelGGL(glint_order_count, dim3((unsigned)L.n_blk), dim3(kWave * kOrderWaves), 0, st, vw, kTileLw, tiles_x,
                        (int32_t)L.n_tiles, sh.n_mat, inv_rmax, sh.n_probe_max, cls, cnt);
     hipLaunchKernelGGL(glint_order_scan, dim3(1), dim3(kScanThreads), 0, st, cnt, offs, L.n_blk);
     hipLaunchKernelGGL(glint_order_scatter, dim3((unsigned)L.n_blk), dim3(kOrderTiles), 0, st, cls, offs,
@@ -651,10 +652,8 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     rc = make_view(gbuf, out_rgb, vw);
     if (rc) return rc;
     if ((int64_t)vw.width * vw.height == 0) return GLINT_OK;
-    const int tile_w = 8;
-    const int tiles_x = (vw.width + tile_w - 1) / tile_w;
-    const int tiles_y = (vw.height + (kWave / tile_w) - 1) / (kWave / tile_w);
-    const int64_t nt = (int64_t)tiles_x * tiles_y;
+    const int tiles_x = (int)tiles_x_of(vw.width);
+    const int64_t nt = tiles_of(vw.width, vw.height);
     if (nt > 0x7fffffffLL) return GLINT_ESHAPE;
     hipStream_t st = (hipStream_t)stream;
     const int32_t *order = nullptr;
@@ -666,11 +665,11 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light};
         hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
-                           log2_tile(tile_w), tiles_x, order, (int32_t)nt);
+                           kTileLw, tiles_x, order, (int32_t)nt);
     } else {
         DebugPlanes dp = {};
         hipLaunchKernelGGL(glint_fwd_kernel<false>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
-                           log2_tile(tile_w), tiles_x, order, (int32_t)nt);
+                           kTileLw, tiles_x, order, (int32_t)nt);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);

@@ -14,7 +14,20 @@ namespace glint {
 
 int set_hip_error(hipError_t e);   // records e for glint_last_hip_error, returns GLINT_EHIP
 
-// Heaviest-first order of the 8x8 tiles of a view (row-major tile numbering),
+// Tile shape of glint_shade and glint_shade_backward: kTileW x kTileH pixels
+// per 64-lane wave, rows of kTileW = 32 FP32 values (one 128-byte cache line
+// per G-buffer plane and row), so a tile reads whole lines whatever order the
+// tiles run in.
+constexpr int kTileLw = 5;
+constexpr int kTileW = 1 << kTileLw, kTileH = kWave / kTileW;
+
+inline int64_t tiles_x_of(int32_t width) { return (width + kTileW - 1) / kTileW; }
+inline int64_t tiles_of(int32_t width, int32_t height)
+{
+    return tiles_x_of(width) * (int64_t)((height + kTileH - 1) / kTileH);
+}
+
+// Heaviest-first order of the kTileW x kTileH tiles of a view (row-major tile numbering),
 // built on `st` in `ws` (tile_order_bytes(width, height) bytes, 4-byte
 // aligned).  On success *order points at n_tiles int32 tile indices inside
 // ws.  Defined with the forward kernels.

@@ -64,7 +64,7 @@ def test_host_validation_without_device(lib):
     assert L.glint_shade(C.byref(g), badm, 1, lts, 1, C.byref(prm), out, None, None, 0, None) == glint.GLINT_EINVAL
     # tile-order workspace: size formula, too small, misaligned (rejected before any launch)
     assert L.glint_shade_workspace_bytes(0, 5) == 0
-    tiles = 480 * 270
+    tiles = 120 * 1080                       # 32 x 2 tiles
     assert L.glint_shade_workspace_bytes(3840, 2160) >= 5 * tiles
     assert L.glint_shade_workspace_bytes(3840, 2160) < 6 * tiles + 4096
     need = L.glint_shade_workspace_bytes(4, 4)

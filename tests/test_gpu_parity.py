@@ -186,11 +186,12 @@ def test_tile_order_is_a_heaviest_first_permutation(glint):
     """The cost-ordered tile schedule: the order is a permutation of the
     tiles, sorted by cost class (heaviest first, ties in row-major order),
     and the image is bit-identical to the row-major schedule.  Ragged size:
-    a partial last count block and partial edge tiles."""
+    a partial last count block and partial edge tiles (32 x 2 tiles)."""
     gb, mats, lights = scenes.four_k(645, 363, seed=5)
     dgb = glint.to_device(gb)
     H, W = gb["u"].shape
-    tx, ty = (W + 7) // 8, (H + 7) // 8
+    TW, TH = 32, 2
+    tx, ty = (W + TW - 1) // TW, (H + TH - 1) // TH
     n = tx * ty
     nb = glint.glint_shade_workspace_bytes(W, H)
     ws = torch.full((nb,), 0xAB, dtype=torch.uint8, device="cuda")
@@ -204,9 +205,9 @@ def test_tile_order_is_a_heaviest_first_permutation(glint):
     # cost classes from the forward's own probe counts (the schedule uses an
     # FP32 estimate of them, so allow a handful of boundary disagreements)
     _, dbg = glint.glint_shade(dgb, mats, lights, debug=True)
-    npr = np.zeros((ty * 8, tx * 8), np.int64)
+    npr = np.zeros((ty * TH, tx * TW), np.int64)
     npr[:H, :W] = dbg["n_probe"].cpu().numpy()
-    S = npr.reshape(ty, 8, tx, 8).transpose(0, 2, 1, 3).reshape(n, 64).sum(1)
+    S = npr.reshape(ty, TH, tx, TW).transpose(0, 2, 1, 3).reshape(n, 64).sum(1)
     bt = (S + 63) // 64
     cls = np.select([bt < 4, bt < 6, bt < 9, bt < 14], [bt, 4, 5, 6], 7)
     seq = cls[order]
