@@ -32,6 +32,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "glint_fwd_4k_counters.txt")
+
+
+def sources_sha256():
+    """SHA-256 over the library's kernel sources and C header."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2306_05051_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.startswith("glint_") and f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "glint.h"), "rb").read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per glint_shade call at 4K from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the kernel
+    sources have changed since those counters were taken."""
+    import re
+    try:
+        txt = open(COUNTERS).read()
+    except OSError:
+        return None
+    sha = re.search(r"^sources_sha256: ([0-9a-f]{64})$", txt, re.M)
+    val = re.search(r"^traffic_bytes_per_call: (\d+)$", txt, re.M)
+    if not (sha and val) or sha.group(1) != sources_sha256():
+        return None
+    return int(val.group(1))
+
+
 def cpu_baseline(gb, mats, lights, target_s=10.0):
     """The FP64 oracle on the same frame, on the host cores: whole frames,
     repeated until about target_s seconds have elapsed (at most 10 times);
@@ -148,7 +180,7 @@ def main():
         achieved = slots / (kernel_ms / 1e3)
         roof = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(costmodel.VALU_PEAK_SLOTS / 1e12, 3), "unit": "Tslot/s",
-                "frac": round(achieved / costmodel.VALU_PEAK_SLOTS, 4), "traffic": None,
+                "frac": round(achieved / costmodel.VALU_PEAK_SLOTS, 4), "traffic": recorded_traffic(),
                 "kernel": "glint_fwd_kernel<false> + tile-order pre-pass", "kernel_ms": round(kernel_ms, 4),
                 "slots_per_launch": int(slots), "units_per_launch": units}
 

@@ -86,17 +86,17 @@ int main()
     unsigned *buf = nullptr;
     if (hipMalloc((void **)&buf, sizeof(unsigned) * (size_t)full * 256) != hipSuccess) return 1;
     int rc = 0;
-    rc |= run<0>("v_mul_f32", buf, one, 4000);
-    rc |= run<0>("v_mul_f32", buf, full, 250);
-    rc |= run<1>("v_fma_f32", buf, full, 250);
-    rc |= run<2>("v_add_u32", buf, full, 250);
-    rc |= run<3>("v_mul_lo_u32", buf, full, 250);
-    rc |= run<4>("v_fma_f64", buf, full, 250);
-    rc |= run<5>("v_mul_f64", buf, full, 250);
-    rc |= run<6>("v_exp_f32", buf, full, 250);
-    rc |= run<7>("v_sqrt_f32", buf, full, 250);
-    rc |= run<8>("v_rsq_f64", buf, full, 100);
-    rc |= run<9>("v_rcp_f64", buf, full, 100);
+    rc |= run<0>("v_mul_f32", buf, one, 16000);
+    rc |= run<0>("v_mul_f32", buf, full, 1000);
+    rc |= run<1>("v_fma_f32", buf, full, 1000);
+    rc |= run<2>("v_add_u32", buf, full, 1000);
+    rc |= run<3>("v_mul_lo_u32", buf, full, 1000);
+    rc |= run<4>("v_fma_f64", buf, full, 1000);
+    rc |= run<5>("v_mul_f64", buf, full, 1000);
+    rc |= run<6>("v_exp_f32", buf, full, 500);
+    rc |= run<7>("v_sqrt_f32", buf, full, 500);
+    rc |= run<8>("v_rsq_f64", buf, full, 250);
+    rc |= run<9>("v_rcp_f64", buf, full, 250);
     (void)hipFree(buf);
     return rc;
 }
