@@ -250,15 +250,23 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
     px.cos_i = px.n[0] * px.wi[0] + px.n[1] * px.wi[1] + px.n[2] * px.wi[2];
     if (!(px.cos_i > 0.0)) { px.flags = F_BACKFACING; return; }
     const double hd = 0.5 * (a - c);
-    const double s0sq = 0.5 * (a + c) + sqrt(hd * hd + b * b);
+    const double R = sqrt(hd * hd + b * b);
+    const double s0sq = 0.5 * (a + c) + R;
     double r = s0sq / P;
     if (r < 1.0) r = 1.0;
     double phi = 0.5 * atan2(2.0 * b, a - c);
     if (phi < 0.0) phi += kPi;
-    const double s0 = sqrt(s0sq);
+    // sigma0 (cos phi, sin phi): the eigenvector of J J^T for sigma0^2 in its
+    // well-conditioned form, (hd + R, b) or (b, R - hd), turned so that
+    // sin phi >= 0 (phi in [0, pi)); an isotropic footprint takes phi = 0
+    double vx = hd >= 0.0 ? hd + R : b, vy = hd >= 0.0 ? b : R - hd;
+    if (vy < 0.0) { vx = -vx; vy = -vy; }
+    const double vv = vx * vx + vy * vy;
+    if (!(vv > 0.0)) { vx = 1.0; vy = 0.0; }
+    const double sc = s0sq * rsqrt_d(s0sq) * (vv > 0.0 ? rsqrt_d(vv) : 1.0);
     px.u = fu; px.v = fv; px.P = P;
-    px.ex = s0 * cos(phi);
-    px.ey = s0 * sin(phi);
+    px.ex = sc * vx;
+    px.ey = sc * vy;
     // sub-footprints along the major axis when r exceeds the family's 2^K
     const int K = sh.k_max;
     const double rmax = (double)(1 << K);
@@ -643,22 +651,23 @@ __device__ __forceinline__ void probe_texels(const PixelRec &R, double u, double
     // probe centre, uniform along the major axis over length sigma0
     const double off = ((double)kp + 0.5) * rcp_d((double)npr) - 0.5;
     const double cx = u + off * R.ex, cy = v + off * R.ey;
+    // all four nodes without branching (almost every pixel has four, and
+    // straight-line code lets the nodes' FP64 and hash chains interleave);
+    // slots of nodes g >= nn are never read
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        if (g < nn) {
-            const uint32_t w = rec_node_word(R, g);
-            const int l = (int)(w & 0x7ffu) - 1024, k = (w >> 11) & 7, m = w >> 14;
-            int vi[3], vj[3];
-            float beta[3];
-            simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta);
-            const uint32_t base = hstep(M.root, w);
+        const uint32_t w = rec_node_word(R, g);
+        const int l = (int)(w & 0x7ffu) - 1024, k = (w >> 11) & 7, m = w >> 14;
+        int vi[3], vj[3];
+        float beta[3];
+        simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta);
+        const uint32_t base = hstep(M.root, w);
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
-                sm.pre[g * 3 + e][lane] = pre[g][e];
-                sm.beta[g * 3 + e][lane] = beta[e];
-                if (key_sum) *key_sum += pre[g][e];
-            }
+        for (int e = 0; e < 3; ++e) {
+            pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
+            sm.pre[g * 3 + e][lane] = pre[g][e];
+            sm.beta[g * 3 + e][lane] = beta[e];
+            if (key_sum && g < nn) *key_sum += pre[g][e];
         }
     }
 }
