@@ -17,8 +17,10 @@ per instruction class give
     v_mul_lo_u32, FP64 add/mul/FMA/compare/convert                2
     FP32 exp/log/rcp/rsq/sqrt                                     4
     FP64 rcp/rsq seeds                                            8
-An FP64 square root or quotient is a seed plus about six FP64 operations:
-20 slots.
+FP64 1/sqrt(x) and 1/x, which need only be accurate to a few ulp on this
+path, are a seed and two Newton steps: 8 + 8 FP64 operations = 24 slots,
+8 + 4 = 16 slots; a correctly rounded FP64 quotient or square root (kept
+where a decision can sit exactly on its boundary) is counted as 20 and 24.
 
 Per-unit costs: the minimal instruction sequence of each step of the method
 at the path's precision (FP64 for the footprint, the grid transforms, the
@@ -34,20 +36,23 @@ keys and gates):
       CDF (bits to x, 1-x, 1+x 7, log 6, select 1, polynomial 9, scale 2) 25,
       node mean/sigma 11, Gaussian 1, count 2, bilinear weight and
       accumulate 5 = 65
-  item-light (one pixel, probe, light): <n,wo> 8, h = wi + wo 6, |h| 26, h/|h|
-      26, <n,h> 6, cos^2/sin^2 8, GGX ratio p 12, angular cell and bilinear
-      fractions 44, Fresnel 15, Smith Lambda(wo) 20, log(1-p) 21, 4 gate
+  item-light (one pixel, probe, light; the unit half vector enters through
+      dot products: |wi + wo|^2 = 2 (1 + <wi,wo>) and so on): <n,wo> and its
+      sign 8, <wi,wo> 6, |wi + wo|^2 and guard 4, 1/|wi + wo| 24, <n,h> 4,
+      cos^2/sin^2 8, GGX ratio p 12, angular coordinates, cell and bilinear
+      fractions 50, Fresnel 13, Smith Lambda(wo) 20, log(1-p) 21, 4 gate
       set-ups (trials x log, 1-exp, guards, threshold, shift) 4 x 28 = 112,
-      4 slot-0 angular keys 4 x 12 = 48, radiance 13 = 365
-  item (one pixel, probe): probe centre 36, FP64 tangent frame 42, 4 x (key
-      unpack 5, trig table index 3, rotation 8, anisotropic scales 14, lattice
-      shear/floor/fractions 18, triangle 2, vertex selects 6, barycentrics 10,
-      node hash 9, 6 texel-key hashes 54) = 4 x 129 = 516, probe sum 3 = 597
-  pixel: density 5, FP64 normalisation of n and w 116, footprint moments 24,
-      <n,wi> 6, eigenvalue and ratio 54, atan2 80, sigma0 and sincos 84, probe
-      split 52, area level 6, ratio/orientation cell, triangle, merge, sort,
-      tetrahedron and node words 180, D(n)/(R N P 4<wi,n>) and Lambda(wi) 56
-      = 663
+      4 slot-0 angular keys 4 x 12 = 48, radiance 13 = 343
+  item (one pixel, probe): probe centre 32, FP64 tangent frame 38, <n,wi>,
+      <wi,t>, <wi,b> 18, 4 x (key unpack 5, trig table index 3, rotation 8,
+      anisotropic scales 14, lattice shear/floor/fractions 18, triangle 2,
+      vertex selects 6, barycentrics 10, node hash 9, 6 texel-key hashes 54)
+      = 4 x 129 = 516, probe sum 3 = 607
+  pixel: density 5, FP64 normalisation of n and w 84, footprint moments 24,
+      <n,wi> 6, eigenvalue and ratio 60, atan2 80, sigma0 times the major-axis
+      eigenvector 74, probe split 50, area level 6, ratio/orientation cell,
+      triangle, merge, sort, tetrahedron and node words 180,
+      D(n)/(R N P 4<wi,n>) and Lambda(wi) 56 = 625
 
 Units are counted exactly by the library's instrumented kernel (debug
 planes).  Loop control, address arithmetic, LDS traffic, recomputation,
@@ -61,14 +66,17 @@ VALU_PEAK_SLOTS = CU * SIMD_PER_CU * LANES_PER_CLK * CLOCK_HZ    # lane-slots / 
 FP32_PEAK_FLOPS = 157.3e12                                       # vendor dense FP32 vector (FMA = 2 flops)
 
 HASH = 5 + 2 * 2
-FP64_SQRT = FP64_DIV = 8 + 6 * 2
+FP64_RSQ = 8 + 8 * 2
+FP64_RCP = 8 + 4 * 2
+FP64_DIV, FP64_SQRT = 20, 24
 COST = {
     "live_gate": HASH + 1 + 2,
     "open_gate": (3 + HASH) + HASH + 25 + 11 + 1 + 2 + 5,
-    "item_light": (8 + 6 + (6 + FP64_SQRT) + (FP64_DIV + 6) + 6 + 8 + 12 + 44 + 15 + 20 + 21 + 4 * 28
-                   + 4 * (3 + HASH) + 13),
-    "item": 36 + 42 + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + HASH + 6 * HASH) + 3,
-    "pixel": 663,
+    "item_light": (8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 50 + 13 + 20 + 21 + 4 * 28 + 4 * (3 + HASH) + 13),
+    "item": (8 + FP64_RCP + 8) + (22 + FP64_RCP) + 18
+            + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + HASH + 6 * HASH) + 3,
+    "pixel": (5 + 2 * (12 + FP64_RSQ + 6) + 24 + 6 + (12 + FP64_SQRT + 2 + FP64_DIV + 2) + 80
+              + (26 + 2 * FP64_RSQ) + (8 + 2 * FP64_DIV + 2) + 6 + 180 + 56),
 }
 
 

@@ -61,8 +61,8 @@ __device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, 
     const DevMaterial &M = sh.mats[live ? rec_mat(R) : 0];
     uint32_t pre[4][3];
     if (live) probe_texels(R, u, v, kp, M, sh, pre, sm, (uint32_t *)nullptr);
-    double tt[3] = {0, 0, 0}, bb[3] = {0, 0, 0};
-    if (live) onb(n, tt, bb);
+    ViewFrame fr = {};
+    if (live) view_frame(n, wi, fr);
     const float alpha = live ? R.alpha : 1.0f;
     const float kpx = live ? R.kpx : 0.0f, lam_i = live ? R.lam_i : 0.0f;
     if (!live) dli_da = 0.0f;
@@ -71,7 +71,7 @@ __device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, 
         const DevLight &L = sh.lights[li];
         float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
         LightEval le;
-        if (live && eval_light(n, wi, alpha, L, M, tt, bb, le)) {
+        if (live && eval_light(n, wi, alpha, L, M, fr, le)) {
             const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
             const float p = le.p;
             const float lp = log1m(p);
@@ -161,7 +161,9 @@ __device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, 
             da += sk * (le.F * dG_da * B + le.F * G * Bp * dp_da) - 2.0f * sk * le.F * G * B / alpha;
             dn += sk * le.F * G * (Bm - B);
             // gradient with respect to the unit half vector h
-            const float om = (float)(1.0 - (wi[0] * le.h[0] + wi[1] * le.h[1] + wi[2] * le.h[2]));
+            // the unit half vector itself (the forward needs only its dot products)
+            const double h[3] = {(wi[0] + L.wo[0]) * le.ihl, (wi[1] + L.wo[1]) * le.ihl, (wi[2] + L.wo[2]) * le.ihl};
+            const float om = (float)(1.0 - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]));
             const float dF = -5.0f * (1.0f - M.F0) * om * om * om * om * G * B;   // times wi
             const float cn = sk * le.F * G * Bp * dp_dc2 * 2.0f * (float)le.ch;   // times n
             const float ct = sk * le.F * G * Bfx * inv_micro;                      // times t
@@ -169,11 +171,11 @@ __device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, 
             float gh[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                gh[c] = sk * dF * (float)wi[c] + cn * (float)n[c] + ct * (float)tt[c] + cb * (float)bb[c];
+                gh[c] = sk * dF * (float)wi[c] + cn * (float)n[c] + ct * (float)fr.t[c] + cb * (float)fr.b[c];
             // direct dependence on wo through Lambda(<n,wo>)
             const float gon = sk * le.F * B * (-G / (1.0f + le.lam_o)) * dlo_dc;
             // h = (wi + wo)/|wi + wo|, wo = d/|d|: chain through both normalisations
-            const float hx = (float)le.h[0], hy = (float)le.h[1], hz = (float)le.h[2];
+            const float hx = (float)h[0], hy = (float)h[1], hz = (float)h[2];
             const float hd = gh[0] * hx + gh[1] * hy + gh[2] * hz;
             const float ihl = (float)le.ihl;
             const float gw[3] = {(gh[0] - hd * hx) * ihl + gon * (float)n[0],

@@ -274,8 +274,8 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
     if (npr < 1) npr = 1;
     if (npr > sh.n_probe_max) npr = sh.n_probe_max;
     px.npr = npr;
-    const double Pk = P / npr;
-    double rk = r / npr;
+    const double Pk = npr > 1 ? P / npr : P;
+    double rk = npr > 1 ? r / npr : r;
     if (rk > rmax) { rk = rmax; px.flags |= F_CLAMP_RATIO; }
     // area level (Eq. 13): Pk = fr 2^ex exactly, l = ex - 1, top weight ts (Eq. 10)
     int ex;
@@ -515,10 +515,26 @@ __device__ __forceinline__ float success_prob(int ndf, float alpha, float R, flo
     return clamped ? 1.0f : p;
 }
 
+// Per item: the tangent frame of n and the view's projections on it.
+struct ViewFrame {
+    double t[3], b[3];         // Duff et al. ONB of n
+    double cos_i, wt, wb;      // <n, wi>, <wi, t>, <wi, b>
+};
+
+__device__ __forceinline__ void view_frame(const double n[3], const double wi[3], ViewFrame &f)
+{
+    onb(n, f.t, f.b);
+    f.cos_i = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
+    f.wt = wi[0] * f.t[0] + wi[1] * f.t[1] + wi[2] * f.t[2];
+    f.wb = wi[0] * f.b[0] + wi[1] * f.b[1] + wi[2] * f.b[2];
+}
+
 // Everything one light needs at one pixel (shared by the forward and the
-// adjoint so that both take identical decisions).
+// adjoint so that both take identical decisions).  The half vector
+// h = (wi + wo)/|wi + wo| of the unit directions enters only through dot
+// products: |wi + wo|^2 = 2 (1 + <wi,wo>), <n,h> = (<n,wi> + <n,wo>)/|wi + wo|,
+// <wi,h> = (1 + <wi,wo>)/|wi + wo| and likewise for the frame axes.
 struct LightEval {
-    double h[3];               // half vector (FP64, unit)
     double ihl;                // 1 / |wi + wo|
     double cos_o, ch;          // <n, wo>, <n, h>
     float p;                   // success probability (Eq. 4)
@@ -528,35 +544,33 @@ struct LightEval {
     float F, lam_o;            // Schlick Fresnel, Smith Lambda of wo
 };
 
-__device__ __forceinline__ bool eval_light(const double pn[3], const double pwi[3], float alpha, const DevLight &L,
-                                           const DevMaterial &M, const double tt[3], const double bb[3],
-                                           LightEval &e)
+__device__ __forceinline__ bool eval_light(const double n[3], const double wi[3], float alpha, const DevLight &L,
+                                           const DevMaterial &M, const ViewFrame &f, LightEval &e)
 {
-    struct { const double *n, *wi; float alpha; } px = {pn, pwi, alpha};
     if (!L.ok) return false;
-    e.cos_o = px.n[0] * L.wo[0] + px.n[1] * L.wo[1] + px.n[2] * L.wo[2];
+    e.cos_o = n[0] * L.wo[0] + n[1] * L.wo[1] + n[2] * L.wo[2];
     if (!(e.cos_o > 0.0)) return false;
-    double h0 = px.wi[0] + L.wo[0], h1 = px.wi[1] + L.wo[1], h2 = px.wi[2] + L.wo[2];
-    const double hh = h0 * h0 + h1 * h1 + h2 * h2;
+    const double wiwo = wi[0] * L.wo[0] + wi[1] * L.wo[1] + wi[2] * L.wo[2];
+    const double hh = 2.0 + 2.0 * wiwo;
     if (!(hh > 0.0)) return false;
     const double ihl = rsqrt_d(hh);
     e.ihl = ihl;
-    e.h[0] = h0 * ihl; e.h[1] = h1 * ihl; e.h[2] = h2 * ihl;
-    e.ch = px.n[0] * e.h[0] + px.n[1] * e.h[1] + px.n[2] * e.h[2];
-    e.p = success_prob(M.ndf, px.alpha, M.R, (float)(e.ch * e.ch), (float)(1.0 - e.ch * e.ch), e.pclamp);
+    e.ch = (f.cos_i + e.cos_o) * ihl;
+    e.p = success_prob(M.ndf, alpha, M.R, (float)(e.ch * e.ch), (float)(1.0 - e.ch * e.ch), e.pclamp);
     // angular grid over the projected half vector (Eq. 14)
-    const double ax = (e.h[0] * tt[0] + e.h[1] * tt[1] + e.h[2] * tt[2]) * M.inv_micro - 0.5;
-    const double ay = (e.h[0] * bb[0] + e.h[1] * bb[1] + e.h[2] * bb[2]) * M.inv_micro - 0.5;
+    const double sc = ihl * M.inv_micro;
+    const double ax = (f.wt + (f.t[0] * L.wo[0] + f.t[1] * L.wo[1] + f.t[2] * L.wo[2])) * sc - 0.5;
+    const double ay = (f.wb + (f.b[0] * L.wo[0] + f.b[1] * L.wo[1] + f.b[2] * L.wo[2])) * sc - 0.5;
     const double fax = floor(ax), fay = floor(ay);
     e.ai = (int)fax; e.aj = (int)fay;
     // bilinear fractions; both complements from FP64 so small weights stay accurate
     e.fx = (float)(ax - fax); e.fy = (float)(ay - fay);
     e.gx = (float)(fax + 1.0 - ax); e.gy = (float)(fay + 1.0 - ay);
     // Schlick Fresnel, Smith Lambda of the light direction (Eq. 2)
-    const float om = (float)(1.0 - (px.wi[0] * e.h[0] + px.wi[1] * e.h[1] + px.wi[2] * e.h[2]));
+    const float om = (float)(1.0 - (1.0 + wiwo) * ihl);
     const float om2 = om * om;
     e.F = M.F0 + (1.0f - M.F0) * om2 * om2 * om;
-    e.lam_o = smith_lambda(M.ndf, px.alpha, (float)e.cos_o, (float)(1.0 - e.cos_o * e.cos_o));
+    e.lam_o = smith_lambda(M.ndf, alpha, (float)e.cos_o, (float)(1.0 - e.cos_o * e.cos_o));
     return true;
 }
 

@@ -80,12 +80,12 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
     const DevMaterial &M = sh.mats[rec_mat(R)];
     uint32_t pre[4][3];
     probe_texels(R, u, v, kp, M, sh, pre, sm, DEBUG ? &o.key_sum : (uint32_t *)nullptr);
-    double tt[3], bb[3];
-    onb(n, tt, bb);
+    ViewFrame fr;
+    view_frame(n, wi, fr);
     for (int li = 0; li < sh.n_light; ++li) {
         const DevLight &L = sh.lights[li];
         LightEval le;
-        if (!eval_light(n, wi, R.alpha, L, M, tt, bb, le)) continue;
+        if (!eval_light(n, wi, R.alpha, L, M, fr, le)) continue;
         const float p = le.p;
         const float lp = log1m(p);
         uint32_t K[4], anyK = 0u;
@@ -153,12 +153,12 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
 __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 {
     const DevMaterial &M = sh.mats[px.mat];
-    double tt[3], bb[3];
-    onb(px.n, tt, bb);
+    ViewFrame fr;
+    view_frame(px.n, px.wi, fr);
     uint32_t s = 0;
     for (int li = 0; li < sh.n_light; ++li) {
         LightEval le;
-        if (!eval_light(px.n, px.wi, px.alpha, sh.lights[li], M, tt, bb, le)) continue;
+        if (!eval_light(px.n, px.wi, px.alpha, sh.lights[li], M, fr, le)) continue;
         for (int a = 0; a < 4; ++a) s += hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
     }
     return s;
