@@ -30,18 +30,15 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-struct MatSlot {
-    int mat;
-    float da, dn;
-};
-
+// Per-wave LDS (10176 bytes: 16 workgroups per CU).  As in the forward,
+// column `lane` of pre[][] is private to the lane while its item runs;
+// afterwards rows 0-2 hold the item's (material, d/d alpha, d/d ln N) for the
+// fixed-order per-material sums.
 struct BwdSmem {
     int off[kWave];
     PixelRec rec[kWave];
-    float dlam[kWave];         // d Lambda(view) / d alpha per pixel
     uint32_t pre[12][kWave];
     float beta[12][kWave];
-    MatSlot ms[kWave];
     float dd[kMaxLight][3];
 };
 
@@ -50,9 +47,8 @@ struct BwdSmem {
 // Called by every lane of the wave (live = false contributes zeros).  Gates
 // are collected in bit masks and the open ones processed in a compacted loop,
 // as in the forward.
-__device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, double v, const double n[3],
-                          const double wi[3], int kp, const Shared &sh, const float gout[3], float &da, float &dn,
-                          BwdSmem &sm)
+__device__ void grad_item(bool live, const PixelRec &R, double u, double v, const double n[3], const double wi[3],
+                          int kp, const Shared &sh, const float gout[3], float &da, float &dn, BwdSmem &sm)
 {
     da = 0.0f;
     dn = 0.0f;
@@ -65,7 +61,9 @@ __device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, 
     if (live) view_frame(n, wi, fr);
     const float alpha = live ? R.alpha : 1.0f;
     const float kpx = live ? R.kpx : 0.0f, lam_i = live ? R.lam_i : 0.0f;
-    if (!live) dli_da = 0.0f;
+    float dli_da = 0.0f, dl_dc;                 // d Lambda(view) / d alpha
+    if (live)
+        smith_lambda_grad(M.ndf, alpha, (float)fr.cos_i, (float)(1.0 - fr.cos_i * fr.cos_i), dl_dc, dli_da);
     const float inv_micro = (float)M.inv_micro;
     for (int li = 0; li < sh.n_light; ++li) {
         const DevLight &L = sh.lights[li];
@@ -199,7 +197,7 @@ __device__ void grad_item(bool live, const PixelRec &R, float dli_da, double u, 
     }
 }
 
-__global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, const float *gout, int tiles_x,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void glint_bwd_kernel(ViewDesc vw, Shared sh, const float *gout, int tiles_x,
                                                        const int32_t *__restrict__ order, int32_t n_tiles,
                                                        float *partials, int n_par, int row_stride)
 {
@@ -222,9 +220,6 @@ __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, c
         if (px.flags & F_SHADED) {
             npr = px.npr;
             sm.rec[lane] = make_rec(px, sh);
-            const float ci = (float)px.cos_i, si2 = (float)(1.0 - px.cos_i * px.cos_i);
-            float dl_dc;
-            smith_lambda_grad(sh.mats[px.mat].ndf, px.alpha, ci, si2, dl_dc, sm.dlam[lane]);
         }
     }
     int incl = npr;
@@ -259,16 +254,16 @@ __global__ __launch_bounds__(64) void glint_bwd_kernel(ViewDesc vw, Shared sh, c
             g3[2] = gout[2 * npx + pidx];
         }
         float da, dn;
-        grad_item(live, sm.rec[p], sm.dlam[p], u, v, n, wi, kp, sh, g3, da, dn, sm);
-        sm.ms[lane].mat = live ? rec_mat(sm.rec[p]) : -1;
-        sm.ms[lane].da = da;
-        sm.ms[lane].dn = dn;
+        grad_item(live, sm.rec[p], u, v, n, wi, kp, sh, g3, da, dn, sm);
+        sm.pre[0][lane] = live ? (uint32_t)rec_mat(sm.rec[p]) : 0xffffffffu;
+        sm.pre[1][lane] = __float_as_uint(da);
+        sm.pre[2][lane] = __float_as_uint(dn);
         __syncthreads();
         if (lane < sh.n_mat) {
             for (int j = 0; j < kWave; ++j) {
-                if (sm.ms[j].mat == lane) {
-                    acc_a += sm.ms[j].da;
-                    acc_n += sm.ms[j].dn;
+                if (sm.pre[0][j] == (uint32_t)lane) {
+                    acc_a += __uint_as_float(sm.pre[1][j]);
+                    acc_n += __uint_as_float(sm.pre[2][j]);
                 }
             }
         }
