@@ -31,7 +31,9 @@ keys and gates):
       xor, mul_lo, xor-shift = 5 + 2 x 2 = 9
   live gate (its node's gate probability reaches the smallest uniform 2^-24;
       the others provably cannot open and need no work): H + compare + mask
-      insert = 12
+      insert = 12; when the gate threshold is below 2^16 the hash head (H
+      without fmix32's last xor-shift, which is the identity on values below
+      2^16) decides the gate exactly: 11
   open gate (extra): slot-1 angular key (pack 3 + H) 12, H 9, inverse normal
       CDF (bits to x, 1-x, 1+x 7, log 6, select 1, polynomial 9, scale 2) 25,
       node mean/sigma 11, Gaussian 1, count 2, bilinear weight and
@@ -71,6 +73,7 @@ FP64_RCP = 8 + 4 * 2
 FP64_DIV, FP64_SQRT = 20, 24
 COST = {
     "live_gate": HASH + 1 + 2,
+    "live_gate_small": HASH - 1 + 1 + 2,
     "open_gate": (3 + HASH) + HASH + 25 + 11 + 1 + 2 + 5,
     "item_light": (8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 50 + 13 + 20 + 21 + 4 * 28 + 4 * (3 + HASH) + 13),
     "item": (8 + FP64_RCP + 8) + (22 + FP64_RCP) + 18
@@ -88,11 +91,14 @@ def units_from_debug(dbg):
     n_nodes = (dbg["cell"].astype(np.int64) >> 15) & 7
     n_gate = dbg["n_gate"].astype(np.int64) & 0xFFFFFFFF
     pairs = np.where(shaded & (n_nodes > 0), n_gate // np.maximum(12 * n_nodes, 1), 0)
+    live = int((dbg["n_live"].astype(np.int64) & 0xFFFFFFFF).sum())
+    small = int((dbg["n_live_small"].astype(np.int64) & 0xFFFFFFFF).sum()) if "n_live_small" in dbg else 0
     return {
         "pixel": int(shaded.sum()),
         "item": int(dbg["n_probe"][shaded].astype(np.int64).sum()),
         "item_light": int(pairs.sum()),
-        "live_gate": int((dbg["n_live"].astype(np.int64) & 0xFFFFFFFF).sum()),
+        "live_gate": live - small,
+        "live_gate_small": small,
         "open_gate": int((dbg["n_open"].astype(np.int64) & 0xFFFFFFFF).sum()),
         "gate": int(n_gate.sum()),
     }

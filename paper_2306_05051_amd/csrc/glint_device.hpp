@@ -61,6 +61,7 @@ struct DebugPlanes {
     int32_t *n_probe, *level;
     uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
+    uint32_t *n_live_small;
 };
 
 enum : uint32_t {
@@ -95,6 +96,19 @@ __host__ __device__ __forceinline__ uint32_t fmix32_hd(uint32_t h)
 __device__ __forceinline__ uint32_t hstep(uint32_t h, uint32_t w)
 {
     return fmix32((h ^ w) + 0x9E3779B9u);
+}
+
+// H(h, w) without fmix32's last step x ^= x >> 16.  That step keeps the top
+// 16 bits and is the identity when they are zero, so for t < 2^16:
+// H(h, w) <= t  <=>  hstep_head(h, w) <= t.
+__device__ __forceinline__ uint32_t hstep_head(uint32_t h, uint32_t w)
+{
+    uint32_t x = (h ^ w) + 0x9E3779B9u;
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    return x;
 }
 
 constexpr uint32_t kRootSalt = 0x243F6A88u;     // material seed chain start

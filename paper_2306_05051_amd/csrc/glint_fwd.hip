@@ -36,7 +36,7 @@ int set_hip_error(hipError_t e)
 
 struct ItemOut {
     float rgb[3];
-    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate, n_live;
+    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate, n_live, n_live_small;
     float b[kMaxLight];
 };
 
@@ -73,7 +73,7 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
     const int lane = threadIdx.x;
     o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
     if (DEBUG) {
-        o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = 0;
+        o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = o.n_live_small = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
     }
     const int nn = rec_nodes(R);
@@ -105,20 +105,39 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
             if (!DEBUG && K[g] == 0u) continue;   // no uniform can open these gates
             // theta0 < P>=1 (Eq. 18 gate)  <=>  (h >> 9) < K  <=>  h <= K 2^9 - 1  (K > 0)
             const uint32_t thr = (K[g] << 9) - 1u;
+            if constexpr (DEBUG) {
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
+                for (int e = 0; e < 3; ++e) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const uint32_t h0 = hstep(pre[g][e], ak0[a]);
-                    uint32_t bit;
-                    if (DEBUG) {
+                    for (int a = 0; a < 4; ++a) {
+                        const uint32_t h0 = hstep(pre[g][e], ak0[a]);
                         o.theta_sum += h0; o.n_gate += 1; o.n_live += K[g] ? 1u : 0u;
-                        bit = ((h0 >> 9) < K[g]) ? 1u : 0u;
-                    } else {
-                        bit = (h0 <= thr) ? 1u : 0u;
+                        o.n_live_small += (K[g] != 0u && K[g] <= 128u) ? 1u : 0u;
+                        const uint32_t bit = ((h0 >> 9) < K[g]) ? 1u : 0u;
+                        if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                        else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
                     }
-                    if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
-                    else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                }
+            } else if (__ballot(K[g] > 128u) == 0ull) {
+                // every lane's threshold is below 2^16: compare the hash head
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const uint32_t bit = (hstep_head(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
+                        if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                        else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const uint32_t bit = (hstep(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
+                        if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                        else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                    }
                 }
             }
         }
@@ -206,7 +225,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     sm.off[lane] = off;
     __syncthreads();
     float acc[3] = {0.0f, 0.0f, 0.0f};
-    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0;
+    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0, dns = 0;
     float db[kMaxLight];
     if (DEBUG)
         for (int l = 0; l < kMaxLight; ++l) db[l] = 0.0f;
@@ -243,6 +262,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                     acc[2] += s.rgb[2];
                     dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
                     dnl += s.n_live;
+                    dns += s.n_live_small;
                     for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
                 } else {
                     acc[0] += __uint_as_float(sm.pre[0][i - base]);
@@ -270,6 +290,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             if (dp.n_open) dp.n_open[idx] = dno;
             if (dp.n_gate) dp.n_gate[idx] = dng;
             if (dp.n_live) dp.n_live[idx] = dnl;
+            if (dp.n_live_small) dp.n_live_small[idx] = dns;
             if (dp.b_light)
                 for (int l = 0; l < sh.n_light; ++l) dp.b_light[l * npx + idx] = db[l];
         }
@@ -663,7 +684,8 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     }
     if (dbg) {
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
-                          dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light};
+                          dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light,
+                          dbg->n_live_small};
         hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
                            kTileLw, tiles_x, order, (int32_t)nt);
     } else {

@@ -33,9 +33,13 @@ def _run(glint, gb, mats, lights, **kw):
     rgb, dbg = glint.glint_shade(dgb, mats, lights, debug=True, **kw)
     rgb2 = glint.glint_shade(dgb, mats, lights, **kw)
     torch.cuda.synchronize()
-    # the production kernel (which skips gates that cannot open) gives the same bits
+    # the production kernel (which skips gates that cannot open and decides
+    # small-threshold gates on the hash head) gives the same bits
     assert torch.equal(rgb, rgb2)
-    return rgb.cpu().numpy(), dbg_to_numpy(dbg)
+    d = dbg_to_numpy(dbg)
+    small = d["n_live_small"].astype(np.int64) & 0xFFFFFFFF
+    assert np.all(small <= (d["n_live"].astype(np.int64) & 0xFFFFFFFF))
+    return rgb.cpu().numpy(), d
 
 
 def _check(glint, gb, mats, lights, label, **kw):
