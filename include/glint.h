@@ -179,7 +179,7 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * (alpha_px, log10_density_px) are not supported (EUNSUPPORTED).
  * workspace: device memory of at least glint_backward_workspace_bytes()
  * bytes, 8-byte aligned, owned by the caller and used by this call only
- * (tile order, one partial row per 8x8 tile, FP64 reduction stage).  Tiles
+ * (tile order, one partial row per 32x2 tile, FP64 reduction stage).  Tiles
  * run heaviest first; the sums are reduced in a fixed order over tiles, so
  * the result does not depend on the schedule.  Errors as glint_shade, plus
  * ENULL (workspace, gradient outputs), EINVAL (misaligned workspace). */
@@ -193,7 +193,8 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
  * glint_plan_create copies the view descriptors (device pointers inside
  * gbufs/out_rgb stay owned by the caller and must outlive the plan), the
  * materials, lights and params, builds the tile table on the device, and
- * (tune may be NULL for defaults) fixes the launch shape.
+ * (tune may be NULL: 32 x 2 tiles, 32 persistent workgroups per compute
+ * unit) fixes the launch shape.
  * glint_shade_batched enqueues [counter reset kernel, persistent kernel] on
  * `stream`; with use_graph != 0 it captures them once into a hipGraph and
  * replays the graph afterwards.  Each view's output is bit-identical to

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(64) void glint_fwd_kernel(ViewDesc vw, Shared sh, D
 }
 
 // ---------------------------------------------------------------------------
-// Tile order for glint_shade: a stable counting sort of the 8x8 tiles by cost
+// Tile order for glint_shade: a stable counting sort of the tiles by cost
 // class, heaviest class first, so that the long tiles (footprints split into
 // many probes) start early instead of trailing at the end of the grid.  The
 // order only schedules work; every tile's arithmetic is unchanged.
@@ -708,8 +708,8 @@ int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t
     if (!P) return GLINT_ENOMEM;
     int rc = prepare_shared(mats, n_mat, lights, n_light, params, P->sh);
     if (rc) { delete P; return rc; }
-    P->tile_w = 8;
-    int bpc = 8;
+    P->tile_w = kTileW;                          // defaults: the library's tile shape, 32 workgroups per CU
+    int bpc = 32;
     if (tune) {
         if (!valid_tile_w(tune->tile_w) || tune->tile_w * tune->tile_h != kWave || tune->blocks_per_cu < 1 ||
             tune->blocks_per_cu > 64) {
