@@ -23,6 +23,7 @@ PLANES = ("u", "v", "dudx", "dvdx", "dudy", "dvdy", "nx", "ny", "nz", "wx", "wy"
 
 GLINT_OK, GLINT_EINVAL, GLINT_ENULL, GLINT_ESHAPE = 0, -1, -2, -3
 GLINT_EHIP, GLINT_EUNSUPPORTED, GLINT_ENOMEM = -4, -5, -6
+GLINT_MAX_MATERIALS, GLINT_MAX_LIGHTS, GLINT_MAX_K, GLINT_MAX_PROBES = 32, 16, 4, 64
 MAX_MATERIALS, MAX_LIGHTS = 32, 16
 
 

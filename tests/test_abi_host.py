@@ -33,6 +33,14 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), f"{n} declared in glint.h but not exported"
 
 
+def test_limits_match_header():
+    from paper_2306_05051_amd import glint
+    txt = open(HEADER).read()
+    for name in ("GLINT_MAX_MATERIALS", "GLINT_MAX_LIGHTS", "GLINT_MAX_K", "GLINT_MAX_PROBES"):
+        m = re.search(r"#define " + name + r"\s+(\d+)", txt)
+        assert m and int(m.group(1)) == getattr(glint, name), name
+
+
 def test_status_strings_and_version(lib):
     lib.glint_status_string.restype = C.c_char_p
     for s in range(0, -7, -1):

@@ -118,6 +118,13 @@ def test_four_k_like_small(glint):
     st = _check(glint, gb, mats, lights, "4k-like 256x144")
 
 
+def test_maximum_materials_and_lights(glint):
+    """The largest parameter blocks the ABI takes: 32 materials, 16 lights."""
+    gb, mats, lights = scenes.four_k(160, 96, seed=8, n_mat=32, n_light=16)
+    assert len(mats) == glint.GLINT_MAX_MATERIALS and len(lights) == glint.GLINT_MAX_LIGHTS
+    _check(glint, gb, mats, lights, "32 materials, 16 lights")
+
+
 @pytest.mark.parametrize("k_max,n_probe_max", [(0, 21), (1, 21), (2, 8), (4, 1), (3, 64)])
 def test_grid_family_variants(glint, k_max, n_probe_max):
     gb, mats, lights = scenes.four_k(96, 80, seed=5, n_light=2)
