@@ -68,6 +68,7 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
     for (int li = 0; li < sh.n_light; ++li) {
         const DevLight &L = sh.lights[li];
         float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
+        bool opened = false;                     // this lane opened a gate of this light
         LightEval le;
         if (live && eval_light(n, wi, alpha, L, M, fr, le)) {
             const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
@@ -101,6 +102,7 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
                 }
             }
             float B = 0.0f, Bp = 0.0f, Bm = 0.0f, Bfx = 0.0f, Bfy = 0.0f;
+            opened = (mlo | mhi) != 0u;
             while (mlo | mhi) {
                 int idx;
                 if (mlo) { idx = __builtin_ctz(mlo); mlo &= mlo - 1u; }
@@ -136,6 +138,9 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
                     Bfy += be * dvy;
                 }
             }
+            // Every term below is proportional to one of B, Bp, Bm, Bfx, Bfy, which
+            // are exactly 0 without an open gate: such lanes skip the algebra.
+            if (opened) {
             // derivatives of p (Eq. 4) with respect to alpha and c2 = <n,h>^2
             const float c2 = (float)(le.ch * le.ch), s2 = (float)(1.0 - le.ch * le.ch);
             const float a2 = alpha * alpha;
@@ -185,14 +190,17 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
             gdx = (gw[0] - wd * wxl) * idl;
             gdy = (gw[1] - wd * wyl) * idl;
             gdz = (gw[2] - wd * wzl) * idl;
+            }
         }
-        gdx = wave_sum(gdx);
-        gdy = wave_sum(gdy);
-        gdz = wave_sum(gdz);
-        if (lane == 0) {
-            sm.dd[li][0] += gdx;
-            sm.dd[li][1] += gdy;
-            sm.dd[li][2] += gdz;
+        if (__ballot(opened) != 0ull) {          // uniform: every lane takes part in the sums
+            gdx = wave_sum(gdx);
+            gdy = wave_sum(gdy);
+            gdz = wave_sum(gdz);
+            if (lane == 0) {
+                sm.dd[li][0] += gdx;
+                sm.dd[li][1] += gdy;
+                sm.dd[li][2] += gdz;
+            }
         }
     }
 }
