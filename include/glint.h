@@ -119,13 +119,16 @@ typedef struct {
  *  n_live_small  live gated binomials whose gate threshold is below 2^16
  *             (gate probability at most 2^-16): the hash head decides them
  *             (work counter, no parity field)
+ *  n_lit      (probe, light) pairs with at least one open gate: only these
+ *             need the light's Fresnel, shadowing and radiance terms (work
+ *             counter, no parity field)
  * Asking for debug planes runs an instrumented kernel (slower, same image). */
 typedef struct {
     uint32_t *flags;
     int32_t *n_probe, *level;
     uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
-    uint32_t *n_live_small;
+    uint32_t *n_live_small, *n_lit;
 } glint_debug;
 
 /* Launch configuration of the batched path (autotuner output).

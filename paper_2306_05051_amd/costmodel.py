@@ -42,9 +42,10 @@ keys and gates):
       dot products: |wi + wo|^2 = 2 (1 + <wi,wo>) and so on): <n,wo> and its
       sign 8, <wi,wo> 6, |wi + wo|^2 and guard 4, 1/|wi + wo| 24, <n,h> 4,
       cos^2/sin^2 8, GGX ratio p 12, angular coordinates, cell and bilinear
-      fractions 50, Fresnel 13, Smith Lambda(wo) 20, log(1-p) 21, 4 gate
-      set-ups (trials x log, 1-exp, guards, threshold, shift) 4 x 28 = 112,
-      4 slot-0 angular keys 4 x 12 = 48, radiance 13 = 343
+      fractions 50, log(1-p) 21, 4 gate set-ups (trials x log, 1-exp, guards,
+      threshold, shift) 4 x 28 = 112, 4 slot-0 angular keys 4 x 12 = 48 = 297
+  lit item-light (extra, when at least one of its gates opened; otherwise it
+      adds exactly nothing): Fresnel 13, Smith Lambda(wo) 20, radiance 13 = 46
   item (one pixel, probe): probe centre 32, FP64 tangent frame 38, <n,wi>,
       <wi,t>, <wi,b> 18, 4 x (key unpack 5, trig table index 3, rotation 8,
       anisotropic scales 14, lattice shear/floor/fractions 18, triangle 2,
@@ -75,7 +76,8 @@ COST = {
     "live_gate": HASH + 1 + 2,
     "live_gate_small": HASH - 1 + 1 + 2,
     "open_gate": (3 + HASH) + HASH + 25 + 11 + 1 + 2 + 5,
-    "item_light": (8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 50 + 13 + 20 + 21 + 4 * 28 + 4 * (3 + HASH) + 13),
+    "item_light": 8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 50 + 21 + 4 * 28 + 4 * (3 + HASH),
+    "item_light_lit": 13 + 20 + 13,
     "item": (8 + FP64_RCP + 8) + (22 + FP64_RCP) + 18
             + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + HASH + 6 * HASH) + 3,
     "pixel": (5 + 2 * (12 + FP64_RSQ + 6) + 24 + 6 + (12 + FP64_SQRT + 2 + FP64_DIV + 2) + 80
@@ -97,6 +99,7 @@ def units_from_debug(dbg):
         "pixel": int(shaded.sum()),
         "item": int(dbg["n_probe"][shaded].astype(np.int64).sum()),
         "item_light": int(pairs.sum()),
+        "item_light_lit": int((dbg["n_lit"].astype(np.int64) & 0xFFFFFFFF).sum()) if "n_lit" in dbg else 0,
         "live_gate": live - small,
         "live_gate_small": small,
         "open_gate": int((dbg["n_open"].astype(np.int64) & 0xFFFFFFFF).sum()),

@@ -141,6 +141,7 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
             // Every term below is proportional to one of B, Bp, Bm, Bfx, Bfy, which
             // are exactly 0 without an open gate: such lanes skip the algebra.
             if (opened) {
+            light_brdf(M, alpha, le);
             // derivatives of p (Eq. 4) with respect to alpha and c2 = <n,h>^2
             const float c2 = (float)(le.ch * le.ch), s2 = (float)(1.0 - le.ch * le.ch);
             const float a2 = alpha * alpha;

@@ -61,7 +61,7 @@ struct DebugPlanes {
     int32_t *n_probe, *level;
     uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
-    uint32_t *n_live_small;
+    uint32_t *n_live_small, *n_lit;
 };
 
 enum : uint32_t {
@@ -550,12 +550,13 @@ __device__ __forceinline__ void view_frame(const double n[3], const double wi[3]
 // <wi,h> = (1 + <wi,wo>)/|wi + wo| and likewise for the frame axes.
 struct LightEval {
     double ihl;                // 1 / |wi + wo|
+    double wiwo;               // <wi, wo>
     double cos_o, ch;          // <n, wo>, <n, h>
     float p;                   // success probability (Eq. 4)
     bool pclamp;
     int ai, aj;                // angular cell (lower-left texel)
     float fx, fy, gx, gy;      // bilinear fractions and their complements
-    float F, lam_o;            // Schlick Fresnel, Smith Lambda of wo
+    float F, lam_o;            // Schlick Fresnel, Smith Lambda of wo (light_brdf; needed only with an open gate)
 };
 
 __device__ __forceinline__ bool eval_light(const double n[3], const double wi[3], float alpha, const DevLight &L,
@@ -565,6 +566,7 @@ __device__ __forceinline__ bool eval_light(const double n[3], const double wi[3]
     e.cos_o = n[0] * L.wo[0] + n[1] * L.wo[1] + n[2] * L.wo[2];
     if (!(e.cos_o > 0.0)) return false;
     const double wiwo = wi[0] * L.wo[0] + wi[1] * L.wo[1] + wi[2] * L.wo[2];
+    e.wiwo = wiwo;
     const double hh = 2.0 + 2.0 * wiwo;
     if (!(hh > 0.0)) return false;
     const double ihl = rsqrt_d(hh);
@@ -580,12 +582,16 @@ __device__ __forceinline__ bool eval_light(const double n[3], const double wi[3]
     // bilinear fractions; both complements from FP64 so small weights stay accurate
     e.fx = (float)(ax - fax); e.fy = (float)(ay - fay);
     e.gx = (float)(fax + 1.0 - ax); e.gy = (float)(fay + 1.0 - ay);
-    // Schlick Fresnel, Smith Lambda of the light direction (Eq. 2)
-    const float om = (float)(1.0 - (1.0 + wiwo) * ihl);
+    return true;
+}
+
+// Schlick Fresnel and Smith Lambda of the light direction (Eq. 2)
+__device__ __forceinline__ void light_brdf(const DevMaterial &M, float alpha, LightEval &e)
+{
+    const float om = (float)(1.0 - (1.0 + e.wiwo) * e.ihl);
     const float om2 = om * om;
     e.F = M.F0 + (1.0f - M.F0) * om2 * om2 * om;
     e.lam_o = smith_lambda(M.ndf, alpha, (float)e.cos_o, (float)(1.0 - e.cos_o * e.cos_o));
-    return true;
 }
 
 // Gate and Gaussian of one grid node (Eqs. 10, 16, 17): trials n = w N 2^l

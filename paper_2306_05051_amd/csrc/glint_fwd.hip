@@ -36,7 +36,7 @@ int set_hip_error(hipError_t e)
 
 struct ItemOut {
     float rgb[3];
-    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate, n_live, n_live_small;
+    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate, n_live, n_live_small, n_lit;
     float b[kMaxLight];
 };
 
@@ -73,7 +73,7 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
     const int lane = threadIdx.x;
     o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
     if (DEBUG) {
-        o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = o.n_live_small = 0;
+        o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = o.n_live_small = o.n_lit = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
     }
     const int nn = rec_nodes(R);
@@ -141,6 +141,10 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
                 }
             }
         }
+        // a light without an open gate adds exactly +0 to the (non-negative) sums
+        if ((mlo | mhi) == 0u) continue;
+        if (DEBUG) o.n_lit += 1;
+        light_brdf(M, R.alpha, le);
         float bsum = 0.0f;
         while (mlo | mhi) {
             int idx;
@@ -225,7 +229,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     sm.off[lane] = off;
     __syncthreads();
     float acc[3] = {0.0f, 0.0f, 0.0f};
-    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0, dns = 0;
+    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0, dns = 0, dlt = 0;
     float db[kMaxLight];
     if (DEBUG)
         for (int l = 0; l < kMaxLight; ++l) db[l] = 0.0f;
@@ -263,6 +267,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                     dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
                     dnl += s.n_live;
                     dns += s.n_live_small;
+                    dlt += s.n_lit;
                     for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
                 } else {
                     acc[0] += __uint_as_float(sm.pre[0][i - base]);
@@ -291,6 +296,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             if (dp.n_gate) dp.n_gate[idx] = dng;
             if (dp.n_live) dp.n_live[idx] = dnl;
             if (dp.n_live_small) dp.n_live_small[idx] = dns;
+            if (dp.n_lit) dp.n_lit[idx] = dlt;
             if (dp.b_light)
                 for (int l = 0; l < sh.n_light; ++l) dp.b_light[l * npx + idx] = db[l];
         }
@@ -300,8 +306,8 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
 // One workgroup per tile.  With a tile order (cost classes, heaviest first)
 // workgroup b shades tile order[b]; without one, tiles go in row-major order.
 template <bool DEBUG>
-__global__ __launch_bounds__(64) void glint_fwd_kernel(ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x,
-                                                       const int32_t *__restrict__ order, int32_t n_tiles)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 4))) void glint_fwd_kernel(
+    ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles)
 {
     __shared__ TileSmem<DEBUG> sm;
     const int t = order ? __builtin_amdgcn_readfirstlane(order[blockIdx.x]) : (int)blockIdx.x;
@@ -685,7 +691,7 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     if (dbg) {
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light,
-                          dbg->n_live_small};
+                          dbg->n_live_small, dbg->n_lit};
         hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
                            kTileLw, tiles_x, order, (int32_t)nt);
     } else {

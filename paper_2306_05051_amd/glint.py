@@ -60,10 +60,12 @@ DEBUG_FIELDS = (("flags", torch.int32), ("n_probe", torch.int32), ("level", torc
                 ("cell", torch.int32), ("key_sum", torch.int32), ("akey_sum", torch.int32),
                 ("theta_sum", torch.int32), ("count_sum", torch.int32), ("n_open", torch.int32),
                 ("n_gate", torch.int32), ("n_live", torch.int32))
+WORK_FIELDS = ("n_live_small", "n_lit")      # work counters of the instrumented kernel (after b_light)
 
 
 class _Debug(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n, _ in DEBUG_FIELDS] + [("b_light", C.c_void_p), ("n_live_small", C.c_void_p)]
+    _fields_ = ([(n, C.c_void_p) for n, _ in DEBUG_FIELDS] + [("b_light", C.c_void_p)]
+                + [(n, C.c_void_p) for n in WORK_FIELDS])
 
 
 class _Tune(C.Structure):
@@ -204,8 +206,9 @@ def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, ou
             setattr(dbg, n, planes[n].data_ptr())
         planes["b_light"] = torch.zeros((max(1, len(lights)), H, W), dtype=torch.float32, device=dev)
         dbg.b_light = planes["b_light"].data_ptr()
-        planes["n_live_small"] = torch.zeros((H, W), dtype=torch.int32, device=dev)
-        dbg.n_live_small = planes["n_live_small"].data_ptr()
+        for n in WORK_FIELDS:
+            planes[n] = torch.zeros((H, W), dtype=torch.int32, device=dev)
+            setattr(dbg, n, planes[n].data_ptr())
     prm = make_params(k_max, n_probe_max, rounding)
     st = glint_shade_raw(g, make_materials(materials), len(materials), make_lights(lights), len(lights),
                          prm, _dev_ptr(out, torch.float32, "out"), dbg, _stream(stream), ws_ptr, ws_bytes)
