@@ -340,13 +340,10 @@ __device__ __forceinline__ int cost_class(int S)
 }
 
 // probe count n_pr of a pixel as the forward computes it, in FP32 (an
-// estimate: only the order of the tiles depends on it)
-__device__ __forceinline__ int probe_estimate(const ViewDesc &vw, int64_t idx, int n_mat, float inv_rmax,
+// estimate: only the order of the tiles depends on it), from its derivatives
+__device__ __forceinline__ int probe_estimate(float dux, float dvx, float duy, float dvy, float inv_rmax,
                                               int n_probe_max)
 {
-    const int mat = vw.mat ? vw.mat[idx] : 0;
-    if (mat < 0 || mat >= n_mat) return 0;
-    const float dux = vw.dudx[idx], dvx = vw.dvdx[idx], duy = vw.dudy[idx], dvy = vw.dvdy[idx];
     const float a = dux * dux + duy * duy, b = dux * dvx + duy * dvy, c = dvx * dvx + dvy * dvy;
     const float P = fabsf(dux * dvy - duy * dvx);
     const float hd = 0.5f * (a - c);
@@ -364,16 +361,40 @@ __global__ __launch_bounds__(kWave * kOrderWaves) void glint_order_count(ViewDes
     __shared__ uint32_t s_cnt[kOrderWaves][kOrderClasses];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t t0 = (int64_t)blockIdx.x * kOrderTiles + w * kPerWave;
-    int S[kPerWave];
+    // two rounds of loads for all the wave's tiles, each issued without
+    // waiting: material ids, then derivatives.  Lanes outside the view or not
+    // shaded read element 0 (the view is not empty) and drop the value.
+    int64_t pix[kPerWave];
+    bool in[kPerWave];
+    int mat[kPerWave];
 #pragma unroll
     for (int i = 0; i < kPerWave; ++i) {
         const int64_t t = t0 + i;
         const int x = ((int)(t % tiles_x) << lw) + (lane & ((1 << lw) - 1));
         const int y = ((int)(t / tiles_x) << (6 - lw)) + (lane >> lw);
-        S[i] = (t < n_tiles && x < vw.width && y < vw.height)
-                   ? probe_estimate(vw, (int64_t)y * vw.stride + x, n_mat, inv_rmax, n_probe_max)
-                   : 0;
+        in[i] = t < n_tiles && x < vw.width && y < vw.height;
+        pix[i] = in[i] ? (int64_t)y * vw.stride + x : 0;
     }
+#pragma unroll
+    for (int i = 0; i < kPerWave; ++i) {
+        const int m = vw.mat ? vw.mat[pix[i]] : 0;
+        mat[i] = in[i] ? m : -1;
+    }
+    float d[kPerWave][4];
+    bool ok[kPerWave];
+#pragma unroll
+    for (int i = 0; i < kPerWave; ++i) {
+        ok[i] = mat[i] >= 0 && mat[i] < n_mat;
+        const int64_t q = ok[i] ? pix[i] : 0;
+        d[i][0] = vw.dudx[q];
+        d[i][1] = vw.dvdx[q];
+        d[i][2] = vw.dudy[q];
+        d[i][3] = vw.dvdy[q];
+    }
+    int S[kPerWave];
+#pragma unroll
+    for (int i = 0; i < kPerWave; ++i)
+        S[i] = ok[i] ? probe_estimate(d[i][0], d[i][1], d[i][2], d[i][3], inv_rmax, n_probe_max) : 0;
     uint32_t mine = 0;                    // lane c < 8: this wave's count of class c
 #pragma unroll
     for (int i = 0; i < kPerWave; ++i) {
