@@ -67,7 +67,7 @@ _DBG_FIELDS = [("flags", np.uint32), ("n_probe", np.int32), ("level", np.int32),
                ("cell", np.uint32), ("key_sum", np.uint32), ("akey_sum", np.uint32),
                ("theta_sum", np.uint32), ("count_sum", np.uint32), ("n_open", np.uint32),
                ("n_gate", np.uint32), ("n_live", np.uint32), ("margin", np.float64),
-               ("margin_kind", np.int32)]
+               ("margin_kind", np.int32), ("margin_pos", np.float64), ("margin_pos_kind", np.int32)]
 
 
 class _Dbg(C.Structure):
@@ -243,18 +243,18 @@ def grid_nodes(Pk, rk, phi, k_max=4):
     """Tetrahedron vertices of the (area, ratio, orientation) grid family:
     list of (l, k, m, w) plus the cell description and the smallest margin."""
     n = _Nodes()
-    mg, mk = C.c_double(np.inf), C.c_int(0)
-    lib().og_grid_nodes(float(Pk), float(rk), float(phi), int(k_max), C.byref(n), C.byref(mg), C.byref(mk))
+    mg, mk = (C.c_double * 2)(np.inf, np.inf), (C.c_int * 2)(0, 0)
+    lib().og_grid_nodes(float(Pk), float(rk), float(phi), int(k_max), C.byref(n), mg, mk)
     nodes = [(n.l[i], n.k[i], n.m[i], n.w[i]) for i in range(n.n)]
     cell = dict(level=n.level, kappa=n.kappa, j=n.j, tri=n.tri, pivot=n.pivot, D=n.D)
-    return nodes, cell, mg.value
+    return nodes, cell, mg[0]
 
 
 def simplex(cx, cy, l, k, m):
     vi, vj, beta = (C.c_int * 3)(), (C.c_int * 3)(), (C.c_double * 3)()
-    mg, mk = C.c_double(np.inf), C.c_int(0)
-    lib().og_simplex(float(cx), float(cy), int(l), int(k), int(m), vi, vj, beta, C.byref(mg), C.byref(mk))
-    return list(zip(vi, vj)), list(beta), mg.value
+    mg, mk = (C.c_double * 2)(np.inf, np.inf), (C.c_int * 2)(0, 0)
+    lib().og_simplex(float(cx), float(cy), int(l), int(k), int(m), vi, vj, beta, mg, mk)
+    return list(zip(vi, vj)), list(beta), mg[0]
 
 
 def gated_count(n, p, theta0, theta1, rounding=0):

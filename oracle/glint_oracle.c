@@ -78,8 +78,10 @@ typedef struct {                  /* every plane is [height*stride] or NULL */
     uint32_t *flags;
     int32_t *n_probe, *level;
     uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
-    double *margin;
+    double *margin;               /* smallest margin of any decision (0: exactly on a boundary) */
     int32_t *margin_kind;
+    double *margin_pos;           /* smallest margin rounding can decide (INFINITY when none) */
+    int32_t *margin_pos_kind;
     double *b_light;              /* [n_light][height*stride]: raw distributed counts */
 } og_debug;
 
@@ -288,9 +290,26 @@ typedef struct {
     int level, kappa, j, tri, pivot, D;
 } og_nodes;
 
+/* Decisions whose value is an exact function of exactly representable
+ * inputs wherever it lands on its boundary (probe count, ratio level,
+ * orientation, triangle, tetrahedron): an exact tie is reproduced by any
+ * implementation that rounds its operations correctly.  The others (lattice,
+ * angular cell, gate, count, light and view validity) follow rounded chains
+ * (products, square roots, trigonometry) that implementations may round
+ * differently, so an exact tie there is as undecidable as a near one. */
+static int tie_exact(int kind)
+{
+    return kind == MK_NPROBE || kind == MK_RATIO || kind == MK_ORIENT || kind == MK_TRIANGLE || kind == MK_TETRA;
+}
+
+/* margins of a pixel's decisions: mg[0] / mk[0] the smallest of all, mg[1] /
+ * mk[1] the smallest one that rounding can decide differently (positive, or
+ * an exact tie of a rounded decision).  A zero elsewhere in the pixel must
+ * not hide it. */
 static void upd_margin(double *mg, int *mk, double value, int kind)
 {
-    if (value < *mg) { *mg = value; *mk = kind; }
+    if (value < mg[0]) { mg[0] = value; mk[0] = kind; }
+    if ((value > 0.0 || !tie_exact(kind)) && value < mg[1]) { mg[1] = value; mk[1] = kind; }
 }
 
 /* distance of x to the nearest integer in [lo, hi] */
@@ -486,8 +505,8 @@ typedef struct {
     double rgb[3];
     uint32_t flags, cell, key_sum, akey_sum, theta_sum, count_sum, n_open, n_gate, n_live;
     int32_t n_probe, level;
-    double margin;
-    int32_t margin_kind;
+    double margin[2];              /* smallest, smallest positive (see upd_margin) */
+    int32_t margin_kind[2];
     double b[64];                  /* raw distributed count per light (first 64 lights) */
 } og_px_out;
 
@@ -496,10 +515,10 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
                         og_tape *T, og_px_out *o)
 {
     memset(o, 0, sizeof(*o));
-    o->margin = INFINITY;
-    o->margin_kind = MK_NONE;
-    double *mg = &o->margin;
-    int *mk = &o->margin_kind;
+    o->margin[0] = o->margin[1] = INFINITY;
+    o->margin_kind[0] = o->margin_kind[1] = MK_NONE;
+    double *mg = o->margin;
+    int *mk = o->margin_kind;
 
     const int K = prm->k_max;
     const double alpha = in->alpha + (pt ? pt->alpha_shift : 0.0);
@@ -723,7 +742,7 @@ int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_
             } else {
                 memset(&o, 0, sizeof(o));
                 o.flags = lflags;
-                o.margin = INFINITY;
+                o.margin[0] = o.margin[1] = INFINITY;
             }
             for (int c = 0; c < 3; ++c) out_rgb[c * npx + idx] = o.rgb[c];
             if (dbg) {
@@ -738,8 +757,10 @@ int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_
                 if (dbg->n_open) dbg->n_open[idx] = o.n_open;
                 if (dbg->n_gate) dbg->n_gate[idx] = o.n_gate;
                 if (dbg->n_live) dbg->n_live[idx] = o.n_live;
-                if (dbg->margin) dbg->margin[idx] = o.margin;
-                if (dbg->margin_kind) dbg->margin_kind[idx] = o.margin_kind;
+                if (dbg->margin) dbg->margin[idx] = o.margin[0];
+                if (dbg->margin_kind) dbg->margin_kind[idx] = o.margin_kind[0];
+                if (dbg->margin_pos) dbg->margin_pos[idx] = o.margin[1];
+                if (dbg->margin_pos_kind) dbg->margin_pos_kind[idx] = o.margin_kind[1];
                 if (dbg->b_light)
                     for (int li = 0; li < n_light; ++li) dbg->b_light[li * npx + idx] = o.b[li];
             }

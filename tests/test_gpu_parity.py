@@ -42,12 +42,13 @@ def _run(glint, gb, mats, lights, **kw):
     return rgb.cpu().numpy(), d
 
 
-def _check(glint, gb, mats, lights, label, **kw):
+def _check(glint, gb, mats, lights, label, min_checked=0.9, **kw):
     grgb, gdbg = _run(glint, gb, mats, lights, **kw)
     rrgb, rdbg = oracle.shade(gb, mats, lights, debug=True, **kw)
     st = compare(grgb, gdbg, rrgb, rdbg, label=label)
     print(f"  {label}: {st}", flush=True)
-    assert st["checked"] > 0.9 * st["shaded"]
+    # the comparison must not be vacuous: most shaded pixels are compared
+    assert st["checked"] > min_checked * st["shaded"]
     return st
 
 
@@ -116,6 +117,19 @@ def test_sphere_geometric_footprints(glint):
 def test_four_k_like_small(glint):
     gb, mats, lights = scenes.four_k(256, 144, seed=3)
     st = _check(glint, gb, mats, lights, "4k-like 256x144")
+
+
+@pytest.mark.parametrize("view", ["plane90", "plane25", "scattered"])
+@pytest.mark.parametrize("k_max,log10_density", [(4, 5.0), (0, 7.0)])
+def test_paper_setting_beckmann(glint, view, k_max, log10_density):
+    """The paper's performance setting: Beckmann alpha = 1.0 (p clamped to 1
+    where R D(h)/D(n) exceeds it), one light, plane views and scattered
+    anisotropy; the isotropic family (K = 0) splits every anisotropic
+    footprint."""
+    gb, mats, lights = scenes.paper_setting(192, 108, view=view, log10_density=log10_density, seed=2)
+    # dense, broad-lobed flakes open hundreds of gates per pixel, so more
+    # pixels hold a count within 1e-5 of a rounding boundary (excluded, counted)
+    _check(glint, gb, mats, lights, f"{view} K={k_max} logN={log10_density}", min_checked=0.75, k_max=k_max)
 
 
 def test_maximum_materials_and_lights(glint):
@@ -245,7 +259,7 @@ def test_full_4k_sampled_rows(glint):
     for r in rows:
         sub = {k: v[r:r + 1] for k, v in gb.items()}
         rrgb, rdbg = oracle.shade(sub, mats, lights, debug=True)
-        ok = ((rdbg["flags"] & 1) > 0) & (rdbg["margin"] >= 1e-5)
+        ok = ((rdbg["flags"] & 1) > 0) & (rdbg["margin_pos"] >= 1e-5)
         g = rgb[:, r:r + 1].astype(np.float64)
         err = np.abs(g - rrgb)[:, ok]
         assert np.all(err <= 1e-4 * np.abs(rrgb[:, ok])), f"row {r}"
