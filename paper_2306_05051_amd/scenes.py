@@ -204,6 +204,60 @@ def _light_dir(el, az, up_axis):
 # ----------------------------------------------------------------------------------------
 # Benchmark configurations
 # ----------------------------------------------------------------------------------------
+def view_plane_gbuffer(W, H, elevation_deg, fov_deg=40.0, height=1.0, uv_scale=1.0):
+    """Unbounded plane z=0 with uv = uv_scale (x, y), seen from height `height`
+    along a direction `elevation_deg` below the horizon (90: straight down).
+    Pixels above the horizon miss (material -1)."""
+    e = math.radians(elevation_deg)
+    f = (0.0, math.cos(e), -math.sin(e))
+    up = (0.0, math.sin(e), math.cos(e))
+    eye = (0.0, 0.0, height)
+    E, D, dDdx, dDdy = _camera(eye, tuple(np.add(eye, f)), up, fov_deg, W, H)
+    n = np.array([0.0, 0.0, 1.0])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = -E[2] / D[..., 2]
+    hit = (D[..., 2] < -1e-9) & (t > 0)
+    t = np.where(hit, t, 1.0)
+    X = E + t[..., None] * D
+    g = _empty(H, W)
+    nn = np.broadcast_to(n, D.shape)
+    dXdx, dXdy = _differentials(t, D, nn, dDdx, dDdy)
+    wi = -_normalize(D)
+    g["u"] = np.where(hit, uv_scale * X[..., 0], 0.0)
+    g["v"] = np.where(hit, uv_scale * X[..., 1], 0.0)
+    g["dudx"] = np.where(hit, uv_scale * dXdx[..., 0], 1.0)
+    g["dvdx"] = np.where(hit, uv_scale * dXdx[..., 1], 0.0)
+    g["dudy"] = np.where(hit, uv_scale * dXdy[..., 0], 0.0)
+    g["dvdy"] = np.where(hit, uv_scale * dXdy[..., 1], 1.0)
+    g["nx"][:] = 0.0; g["ny"][:] = 0.0; g["nz"][:] = 1.0
+    g["wx"], g["wy"], g["wz"] = wi[..., 0], wi[..., 1], wi[..., 2]
+    g["material_id"] = np.where(hit, 0, -1).astype(np.int32)
+    return g
+
+
+PAPER_VIEWS = ("plane90", "plane25", "scattered")
+
+
+def paper_setting(W=1920, H=1080, view="plane90", log10_density=5.0, seed=0):
+    """The performance setting of the paper's Table 1 on synthetic inputs: one
+    Beckmann material with alpha = 1.0 at a given flake density, one
+    directional light, 1080p.  Views: a plane seen straight down (plane90), at
+    25 degrees (plane25: footprints stretch towards the horizon, clustered
+    anisotropy and split probes), and the plane90 footprints with the ratio
+    redrawn per pixel, r ~ LogU[1, 64] (scattered anisotropy)."""
+    if view not in PAPER_VIEWS:
+        raise ValueError(f"view must be one of {PAPER_VIEWS}")
+    rng = np.random.Generator(np.random.PCG64(5000 + seed))
+    g = view_plane_gbuffer(W, H, 25.0 if view == "plane25" else 90.0)
+    if view == "scattered":
+        g = redraw_ratio(g, np.exp(rng.uniform(0.0, math.log(64.0), (H, W))))
+    el = math.radians(rng.uniform(30, 70)); az = rng.uniform(0, 2 * math.pi)
+    lights = [dict(dir=_light_dir(el, az, "z"), radiance=(1.0, 1.0, 1.0))]
+    mats = [dict(ndf=1, alpha=1.0, R=DEFAULT_R, log10_density=float(log10_density),
+                 micro_roughness=DEFAULT_MICRO, F0=DEFAULT_F0, seed=seed)]
+    return _finish(g), mats, lights
+
+
 def plain_forward(W=256, H=256, tilt_deg=60.0, seed=0):
     """Plane under a tilted camera, GGX alpha 0.3, 1e5 flakes per unit UV area,
     one directional light (elevation U(30,70) deg, azimuth U(0,360) deg)."""
