@@ -84,7 +84,7 @@ def cpu_baseline(gb, mats, lights, target_s=10.0):
         for _ in range(reps):
             oracle.shade(gb, mats, lights, n_threads=threads)
         dt = (time.perf_counter() - t0) / reps
-        n_px, what = H * W, f"full 3840x2160 frame, {reps} repetitions, {dt:.2f} s each"
+        n_px, what = H * W, f"full {W}x{H} frame, {reps} repetitions, {dt:.2f} s each"
     else:
         n_rows = int(max(16, target_s / est * H))
         rows = np.linspace(0, H - 1, n_rows).astype(int)
@@ -94,8 +94,17 @@ def cpu_baseline(gb, mats, lights, target_s=10.0):
         oracle.shade(sub, mats, lights, n_threads=threads)
         dt = time.perf_counter() - t0
         n_px, what = n_rows * W, f"{n_rows} of {H} rows (evenly spaced), {dt:.2f} s"
+    # one thread, on an evenly spaced row sample of about a fifth of target_s
+    n1 = int(max(8, min(H, target_s / 5.0 / max(est * threads, 1e-6) * H)))
+    rows1 = np.linspace(0, H - 1, n1).astype(int)
+    sub1 = {k: np.ascontiguousarray(v[rows1]) for k, v in gb.items()}
+    t0 = time.perf_counter()
+    oracle.shade(sub1, mats, lights, n_threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(n_px / 1e6 / dt, 4), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
-            "sample": what + "; FP64 C oracle (OpenMP over rows), same G-buffer, materials and lights"}
+            "sample": what + "; FP64 C oracle (OpenMP over rows), same G-buffer, materials and lights",
+            "value_1_thread": round(n1 * W / 1e6 / dt1, 4),
+            "sample_1_thread": f"{n1} of {H} rows (evenly spaced), {dt1:.2f} s on one thread"}
 
 
 def main():
