@@ -65,7 +65,7 @@ struct TileSmem {
 // Bits are taken in increasing (node, texel, angular) order: the sum order is
 // that of the plain triple loop.
 // ---------------------------------------------------------------------------
-template <bool DEBUG>
+template <bool DEBUG, bool HEAD = true>
 __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v, const double n[3],
                                            const double wi[3], int kp, const Shared &sh, TileSmem<DEBUG> &sm,
                                            ItemOut &o)
@@ -118,7 +118,7 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
                         else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
                     }
                 }
-            } else if (__ballot(K[g] > 128u) == 0ull) {
+            } else if (HEAD && __ballot(K[g] > 128u) == 0ull) {
                 // every lane's threshold is below 2^16: compare the hash head
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
@@ -190,7 +190,7 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 // ---------------------------------------------------------------------------
 // One tile of 64 pixels (tile_w x 64/tile_w) at (x0, y0) of a view.
 // ---------------------------------------------------------------------------
-template <bool DEBUG>
+template <bool DEBUG, bool HEAD = true>
 __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
                            int lw, TileSmem<DEBUG> &sm)
 {
@@ -246,7 +246,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             ItemOut o;
-            shade_item<DEBUG>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm, o);
+            shade_item<DEBUG, HEAD>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm, o);
             if constexpr (DEBUG) {
                 sm.dslot[lane] = o;
             } else {
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void gl
             // in registers across every tile and halve the occupancy)
             const Shared *sp = shp;
             asm volatile("" : "+s"(sp));
-            shade_tile<false>(vw, *sp, dp, tx << lw, ty << (6 - lw), lw, sm);
+            shade_tile<false, false>(vw, *sp, dp, tx << lw, ty << (6 - lw), lw, sm);
         }
     }
 }
