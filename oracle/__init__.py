@@ -60,7 +60,8 @@ class _Light(C.Structure):
 
 
 class _Params(C.Structure):
-    _fields_ = [("k_max", C.c_int32), ("n_probe_max", C.c_int32), ("rounding", C.c_int32)]
+    _fields_ = [("k_max", C.c_int32), ("n_probe_max", C.c_int32), ("rounding", C.c_int32),
+                ("rng_log2", C.c_int32), ("rng_seed", C.c_uint32)]
 
 
 _DBG_FIELDS = [("flags", np.uint32), ("n_probe", np.int32), ("level", np.int32),
@@ -94,6 +95,8 @@ def lib():
         L.og_fmix32.restype = C.c_uint32
         L.og_hash_step.argtypes = [C.c_uint32, C.c_uint32]
         L.og_hash_step.restype = C.c_uint32
+        L.og_rng_table_entry.argtypes = [C.c_uint32, C.c_uint32]
+        L.og_rng_table_entry.restype = C.c_uint32
         L.og_texel_hash.argtypes = [C.c_uint32] + [C.c_int] * 8
         L.og_texel_hash.restype = C.c_uint32
         L.og_ndtri.argtypes = [C.c_double]
@@ -155,12 +158,20 @@ def _lights(lights):
 
 
 def shade(gb, materials, lights, k_max=4, n_probe_max=21, rounding=0, debug=False,
-          rows=None, n_threads=0):
-    """FP64 radiance [3, H, W]; with debug=True also a dict of per-pixel planes."""
+          rows=None, n_threads=0, rng_table=None):
+    """FP64 radiance [3, H, W]; with debug=True also a dict of per-pixel planes.
+
+    rng_table=None hashes every gate uniform from its keys; rng_table=(log2,
+    seed) reads them from the table of 2**log2 words whose entry i is
+    hash_step(seed, i) (log2 in 1..32), at the index (texel key XOR angular
+    key) mod 2**log2."""
     L = lib()
     s, keep, H, W = _gbuf(gb)
     mats, lts = _mats(materials), _lights(lights)
-    prm = _Params(k_max, n_probe_max, rounding)
+    log2, seed = (0, 0) if rng_table is None else (int(rng_table[0]), int(rng_table[1]) & 0xFFFFFFFF)
+    if rng_table is not None and not 1 <= log2 <= 32:
+        raise ValueError("rng_table log2 must be in 1..32")
+    prm = _Params(k_max, n_probe_max, rounding, log2, seed)
     out = np.zeros((3, H, W), np.float64)
     dbg = None
     planes = {}
@@ -187,7 +198,7 @@ def grad(gb, materials, lights, grad_out, step=1e-6, frozen=True, k_max=4, n_pro
     L = lib()
     s, keep, H, W = _gbuf(gb)
     mats, lts = _mats(materials), _lights(lights)
-    prm = _Params(k_max, n_probe_max, 1)
+    prm = _Params(k_max, n_probe_max, 1, 0, 0)
     go = np.ascontiguousarray(grad_out, dtype=np.float64).reshape(3, H, W)
     ga = np.zeros(len(materials)); gn = np.zeros(len(materials)); gd = np.zeros(3 * len(lights))
     flip = np.zeros((H, W), np.uint8)
@@ -207,6 +218,11 @@ def fmix32(h):
 
 def hash_step(h, w):
     return lib().og_hash_step(h & 0xFFFFFFFF, w & 0xFFFFFFFF)
+
+
+def rng_table_entry(seed, i):
+    """Entry i of the random-number table of the given seed: hash_step(seed, i)."""
+    return lib().og_rng_table_entry(seed & 0xFFFFFFFF, i & 0xFFFFFFFF)
 
 
 def texel_hash(seed, l, k, m, i, j, ai, aj, s):

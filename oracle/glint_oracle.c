@@ -25,6 +25,7 @@
  *   angular bilinear grid over projected h      Sec. 5.2, Eq. 14
  *   per-texel random numbers                    Sec. 3 (seeds on spatial / angular grids)
  *   gated Gaussian binomial                     Sec. 6.3, Eqs. 16-18
+ *   uniforms from a precomputed table (variant) Sec. 6.3 (small texture of random numbers)
  *   distributed sum over grids                  Sec. 4.2, Eq. 10; Sec. 5.2
  *   glint NDF, BRDF, radiance                   Sec. 3, Eqs. 1-3
  *
@@ -72,7 +73,10 @@ typedef struct {
 
 typedef struct { float dir[3]; float radiance[3]; } og_light;
 
-typedef struct { int32_t k_max, n_probe_max, rounding; } og_params;
+/* rng_log2 = 0: gate uniforms hashed from their keys; 1..32: read from a
+ * table of 2^rng_log2 words whose entry i is H(rng_seed, i) (Sec. 6.3, the
+ * small precomputed texture of random numbers) */
+typedef struct { int32_t k_max, n_probe_max, rounding, rng_log2; uint32_t rng_seed; } og_params;
 
 typedef struct {                  /* every plane is [height*stride] or NULL */
     uint32_t *flags;
@@ -147,6 +151,25 @@ uint32_t og_fmix32(uint32_t h)
 uint32_t og_hash_step(uint32_t h, uint32_t w)
 {
     return og_fmix32((h ^ w) + 0x9E3779B9u);
+}
+
+/* Entry i of the random-number table: H(seed, i).  The table is a pure
+ * function of its index, so this oracle evaluates the entries it reads
+ * instead of storing them. */
+uint32_t og_rng_table_entry(uint32_t seed, uint32_t i)
+{
+    return og_hash_step(seed, i);
+}
+
+/* The 32-bit word behind the uniform of one gate or count: in hash mode
+ * H(texel key, angular key); in table mode the table entry at the index
+ * (texel key XOR angular key) mod 2^rng_log2.  With rng_log2 = 32 and
+ * rng_seed = 0 both modes give the same word. */
+static uint32_t gate_word(const og_params *prm, uint32_t pre, uint32_t ak)
+{
+    if (prm->rng_log2 == 0) return og_hash_step(pre, ak);
+    uint32_t mask = prm->rng_log2 >= 32 ? 0xFFFFFFFFu : ((1u << prm->rng_log2) - 1u);
+    return og_rng_table_entry(prm->rng_seed, (pre ^ ak) & mask);
 }
 
 /* key word of grid node (area level l, ratio level k, orientation m) */
@@ -644,7 +667,7 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
                 int live = pg > 0x1p-24;
                 for (int e = 0; e < 3; ++e)
                     for (int a = 0; a < 4; ++a) {
-                        uint32_t h0 = og_hash_step(pre[g][e], akey[li][a][0]);
+                        uint32_t h0 = gate_word(prm, pre[g][e], akey[li][a][0]);
                         double th0 = uniform_of(h0);
                         o->theta_sum += h0;
                         o->n_gate++;
@@ -656,7 +679,7 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
                         double c = 0.0;
                         if (open) {                   /* Eq. 18 with the gate read as theta0 < P>=1 */
                             o->n_open++;
-                            uint32_t h1 = og_hash_step(pre[g][e], akey[li][a][1]);
+                            uint32_t h1 = gate_word(prm, pre[g][e], akey[li][a][1]);
                             double x = 1.0 + mu + sg * og_ndtri(uniform_of(h1));
                             if (x >= 1.5) {
                                 double k = floor(x + 0.5);
@@ -726,6 +749,7 @@ int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_
 {
     if (!gb || !mats || n_mat <= 0 || n_light < 0 || n_light > 64 || !prm || !out_rgb) return -1;
     if (prm->k_max < 0 || prm->k_max > 4 || prm->n_probe_max < 1) return -1;
+    if (prm->rng_log2 < 0 || prm->rng_log2 > 32) return -1;
     if (row0 < 0) row0 = 0;
     if (row1 > gb->height) row1 = gb->height;
     const int64_t npx = (int64_t)gb->height * gb->stride;

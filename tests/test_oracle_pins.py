@@ -12,6 +12,7 @@ import pytest
 from scipy.special import ndtri as sp_ndtri
 
 import oracle
+from paper_2306_05051_amd import scenes
 from oracle import bruteforce as bf
 
 
@@ -157,6 +158,64 @@ def test_hash_uniform_and_independent_on_texel_keys():
     g = u.reshape(64, 64, 4)
     for a, b in [(g[1:, :, 0], g[:-1, :, 0]), (g[:, 1:, 0], g[:, :-1, 0]), (g[..., 1], g[..., 0])]:
         assert abs(np.corrcoef(a.ravel(), b.ravel())[0, 1]) < 0.05
+
+
+# ---------------------------------------------------------------------------
+# Random-number table variant (Sec. 6.3: the two uniforms of a gated binomial
+# read from a small precomputed texture)
+# ---------------------------------------------------------------------------
+def test_rng_table_entries_uniform_and_uncorrelated():
+    t = np.array([oracle.rng_table_entry(0x5EED, i) for i in range(1 << 14)], dtype=np.uint64)
+    u = ((t >> 9) * 2 + 1) / 2.0**24
+    hist = np.bincount((u * 64).astype(int), minlength=64)
+    chi2 = np.sum((hist - u.size / 64) ** 2 / (u.size / 64))
+    assert chi2 < 120.0                       # 63 dof
+    assert abs(np.corrcoef(u[1:], u[:-1])[0, 1]) < 0.05
+    assert len(np.unique(t)) > 0.999 * t.size
+    other = np.array([oracle.rng_table_entry(0x5EEE, i) for i in range(1 << 10)], dtype=np.uint64)
+    assert abs(np.corrcoef(u[: 1 << 10], ((other >> 9) * 2 + 1) / 2.0**24)[0, 1]) < 0.1
+
+
+def _table_scene():
+    gb, mats, lights = scenes.four_k(48, 24, seed=13, n_mat=3, n_light=2)
+    return gb, mats, lights
+
+
+def test_rng_table_full_width_is_the_hash():
+    """A table of 2^32 words with seed 0 holds H(0, i) = fmix32(i + c) at index
+    i, so reading it at index texel key XOR angular key gives H(texel key,
+    angular key): the table mode must then reproduce the hash mode bit for bit
+    (every debug plane, every count, the radiance)."""
+    gb, mats, lights = _table_scene()
+    ref, dr = oracle.shade(gb, mats, lights, debug=True)
+    out, dt = oracle.shade(gb, mats, lights, debug=True, rng_table=(32, 0))
+    assert int(dr["n_open"].sum()) > 20
+    np.testing.assert_array_equal(out, ref)
+    for k in dr:
+        np.testing.assert_array_equal(dt[k], dr[k], err_msg=k)
+    # a partial table or another seed changes the words, not the geometry
+    _, d12 = oracle.shade(gb, mats, lights, debug=True, rng_table=(12, 0))
+    _, ds = oracle.shade(gb, mats, lights, debug=True, rng_table=(32, 1))
+    for d in (d12, ds):
+        assert not np.array_equal(d["theta_sum"], dr["theta_sum"])
+        for k in ("flags", "n_probe", "level", "cell", "key_sum", "akey_sum", "n_gate", "n_live"):
+            np.testing.assert_array_equal(d[k], dr[k], err_msg=k)
+
+
+def test_rng_table_small_table_repeats_words():
+    """With 2^1 words every gate word is one of two table entries: theta_sum
+    of a pixel is a combination of the two with n_gate terms."""
+    gb, mats, lights = _table_scene()
+    _, d = oracle.shade(gb, mats, lights, debug=True, rng_table=(1, 7))
+    t0, t1 = oracle.rng_table_entry(7, 0), oracle.rng_table_entry(7, 1)
+    ng = d["n_gate"].astype(np.int64)
+    ts = d["theta_sum"].astype(np.int64)
+    ok = ng > 0
+    # theta_sum = a t0 + (n_gate - a) t1 (mod 2^32) for some 0 <= a <= n_gate
+    found = np.zeros(ng.shape, bool)
+    for a in range(int(ng.max()) + 1):
+        found |= ((a * t0 + (ng - a) * t1 - ts) % (1 << 32) == 0) & (a <= ng)
+    assert ok.sum() > 100 and np.all(found[ok])
 
 
 # ---------------------------------------------------------------------------

@@ -53,12 +53,16 @@ def _light_for_h(hz):
     return wo, h
 
 
+@pytest.mark.parametrize("rng_table", [None, (16, 0x5EED)], ids=["hash", "table16"])
 @pytest.mark.parametrize("P,r,phi,logN,hz", [
     (3.1e-6, 5.3, 0.7, 7.0, 0.999),
     (7.7e-7, 1.0, 0.0, 8.0, 0.995),
     (1.9e-6, 13.0, 2.9, 8.5, 0.999),
 ])
-def test_distributed_count_statistics(P, r, phi, logN, hz):
+def test_distributed_count_statistics(P, r, phi, logN, hz, rng_table):
+    """Also with the gate uniforms read from a table of 2^16 words (Sec. 6.3's
+    precomputed texture): every pixel of the sample indexes the same table, so
+    this checks that the table and its keyed index give independent uniforms."""
     S = 6000
     J = _aniso_J(P, r, phi)
     g = _single_pixel_gbuf(S, (0.0, 0.0), J)
@@ -67,7 +71,7 @@ def test_distributed_count_statistics(P, r, phi, logN, hz):
     mats = [dict(ndf=0, alpha=alpha, R=R, log10_density=logN, micro_roughness=MICRO, F0=1.0, seed=s)
             for s in range(S)]
     lights = [dict(dir=tuple(wo), radiance=(1, 1, 1))]
-    _, dbg = oracle.shade(g, mats, lights, debug=True)
+    _, dbg = oracle.shade(g, mats, lights, debug=True, rng_table=rng_table)
     b = dbg["b_light"][0, 0]
     assert np.all(dbg["n_probe"] == 1)
     # trials per node and the success probability
