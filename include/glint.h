@@ -51,6 +51,11 @@ enum {
 #define GLINT_MAX_LIGHTS 16
 #define GLINT_MAX_K 4              /* largest ratio level: r_max = 2^4 = 16 (Fig. 4)   */
 #define GLINT_MAX_PROBES 64
+#define GLINT_RNG_TABLE_MIN_LOG2 8   /* random-number table: 2^8 .. 2^32 words        */
+#define GLINT_RNG_TABLE_MAX_LOG2 32
+#define GLINT_RNG_LDS_MAX_LOG2 13    /* LDS placement: at most 2^13 words (32 KiB)     */
+#define GLINT_RNG_CACHED 0           /* table read from device memory through L1/L2    */
+#define GLINT_RNG_LDS 1              /* each tile's wave copies the table into LDS     */
 
 /* G-buffer of one view (Sec. 5.1 reads footprints from screen derivatives).
  * u, v: texture coordinates; dudx..dvdy: their screen-space derivatives
@@ -166,6 +171,37 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
                 const glint_light *lights, int32_t n_light, const glint_params *params,
                 float *out_rgb, const glint_debug *dbg, void *workspace, size_t workspace_bytes,
                 void *stream);
+
+/* Random-number table for glint_shade_rng_table (Sec. 6.3: the two uniforms
+ * of a gated binomial may be read from a small texture of random numbers
+ * precomputed once): table[i] = H(seed, i) for i < 2^log2_words, with
+ * H(h, w) = fmix32((h ^ w) + 0x9E3779B9) and fmix32 the MurmurHash3
+ * finaliser, enqueued on stream.  table: device memory of 4 * 2^log2_words
+ * bytes, 16-byte aligned, owned by the caller.  log2_words in [8, 32].
+ * Errors: ENULL (table), EINVAL (log2_words out of range, misaligned
+ * table), EHIP (launch failure). */
+int glint_rng_table_fill(uint32_t *table, int32_t log2_words, uint32_t seed, void *stream);
+
+/* glint_shade with the gate and count uniforms read from a random-number
+ * table instead of hashed (Sec. 6.3, the precomputed texture): the word of
+ * (texel key t, angular key a) is table[(t ^ a) & (2^log2_words - 1)]
+ * instead of H(t, a); everything else is glint_shade's.  With a table
+ * filled by glint_rng_table_fill(table, 32, 0) the result equals
+ * glint_shade's bit for bit (table[i] = H(0, i) and H(0, t ^ a) = H(t, a)).
+ * table: device memory of 2^log2_words words (any contents), 16-byte
+ * aligned, owned by the caller, read only.  placement: GLINT_RNG_CACHED
+ * reads the table from device memory through the caches (log2_words in
+ * [8, 32]); GLINT_RNG_LDS copies it into each tile's LDS first (log2_words
+ * in [8, 13], 4 * 2^log2_words bytes of LDS per 64-pixel tile, which lowers
+ * occupancy).  Both placements give the same image; dbg (as glint_shade's)
+ * is produced by the instrumented kernel, which reads the table through the
+ * caches.  Errors as glint_shade, plus ENULL (table), EINVAL (placement,
+ * log2_words out of range for the placement, misaligned table). */
+int glint_shade_rng_table(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
+                          const glint_light *lights, int32_t n_light, const glint_params *params,
+                          const uint32_t *table, int32_t log2_words, int32_t placement,
+                          float *out_rgb, const glint_debug *dbg, void *workspace,
+                          size_t workspace_bytes, void *stream);
 
 /* Workspace for glint_shade_backward, in bytes. */
 size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_mat, int32_t n_light);

@@ -45,6 +45,8 @@ struct Shared {
     DevLight lights[kMaxLight];
     double cs[32][2];         // cos, sin of m pi / 32: every grid orientation up to ratio level 4
     int32_t n_mat, n_light, k_max, n_probe_max, rounding;
+    const uint32_t *rng_tbl;  // random-number table variant: 2^b words (nullptr: hashed uniforms)
+    uint32_t rng_mask;        // 2^b - 1
 };
 
 struct ViewDesc {

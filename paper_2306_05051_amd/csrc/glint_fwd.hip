@@ -1,5 +1,6 @@
 // glint_fwd.hip -- forward glint shading kernels for gfx950 and the C ABI
-// entry points glint_shade, glint_plan_*, glint_shade_batched and the
+// entry points glint_shade, glint_shade_rng_table (uniforms from a random-number
+// table), glint_plan_*, glint_shade_batched and the
 // bit-exactness utilities.
 //
 // Work decomposition.  One wavefront (64 lanes) owns a tile of 64 pixels.
@@ -15,6 +16,7 @@
 //     probes in probe order (deterministic), then writes RGB planes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -65,10 +67,32 @@ struct TileSmem {
 // Bits are taken in increasing (node, texel, angular) order: the sum order is
 // that of the plain triple loop.
 // ---------------------------------------------------------------------------
-template <bool DEBUG, bool HEAD = true>
+// Source of the 32-bit word behind the uniform of a gate (slot 0) or of a
+// count (slot 1), from the item's texel key and the light's angular key:
+//   kRngHash      H(texel key, angular key), computed
+//   kRngTable     entry (texel key ^ angular key) & mask of a table of random
+//                 words in device memory, read through the caches
+//   kRngTableLds  the same entry from the wave's copy of the table in LDS
+// (Sec. 6.3: the two uniforms may come from a small texture of random
+// numbers precomputed once).
+enum : int { kRngHash = 0, kRngTable = 1, kRngTableLds = 2 };
+
+template <int RNG>
+__device__ __forceinline__ uint32_t rng_word(uint32_t pre, uint32_t ak, const Shared &sh, const uint32_t *ltbl)
+{
+    if constexpr (RNG == kRngHash) {
+        return hstep(pre, ak);
+    } else if constexpr (RNG == kRngTable) {
+        return sh.rng_tbl[(pre ^ ak) & sh.rng_mask];
+    } else {
+        return ltbl[(pre ^ ak) & sh.rng_mask];
+    }
+}
+
+template <bool DEBUG, bool HEAD = true, int RNG = kRngHash>
 __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v, const double n[3],
                                            const double wi[3], int kp, const Shared &sh, TileSmem<DEBUG> &sm,
-                                           ItemOut &o)
+                                           ItemOut &o, const uint32_t *ltbl)
 {
     const int lane = threadIdx.x;
     o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
@@ -110,7 +134,7 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
                 for (int e = 0; e < 3; ++e) {
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
-                        const uint32_t h0 = hstep(pre[g][e], ak0[a]);
+                        const uint32_t h0 = rng_word<RNG>(pre[g][e], ak0[a], sh, ltbl);
                         o.theta_sum += h0; o.n_gate += 1; o.n_live += K[g] ? 1u : 0u;
                         o.n_live_small += (K[g] != 0u && K[g] <= 128u) ? 1u : 0u;
                         const uint32_t bit = ((h0 >> 9) < K[g]) ? 1u : 0u;
@@ -118,7 +142,7 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
                         else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
                     }
                 }
-            } else if (HEAD && __ballot(K[g] > 128u) == 0ull) {
+            } else if (RNG == kRngHash && HEAD && __ballot(K[g] > 128u) == 0ull) {
                 // every lane's threshold is below 2^16: compare the hash head
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
@@ -134,7 +158,7 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
                 for (int e = 0; e < 3; ++e) {
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
-                        const uint32_t bit = (hstep(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
+                        const uint32_t bit = (rng_word<RNG>(pre[g][e], ak0[a], sh, ltbl) <= thr) ? 1u : 0u;
                         if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
                         else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
                     }
@@ -153,7 +177,7 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
             const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
             const int ge = g * 3 + e;
             const uint32_t ak1 = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
-            const uint32_t h1 = hstep(sm.pre[ge][lane], ak1);
+            const uint32_t h1 = rng_word<RNG>(sm.pre[ge][lane], ak1, sh, ltbl);
             // Eq. 17 for node g: m = max(n - 1, 0), 1 + mu, sigma (same arithmetic as eval_node)
             const float ng = R.ng[g];
             const float m = fmaxf(ng - 1.0f, 0.0f);
@@ -190,9 +214,9 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 // ---------------------------------------------------------------------------
 // One tile of 64 pixels (tile_w x 64/tile_w) at (x0, y0) of a view.
 // ---------------------------------------------------------------------------
-template <bool DEBUG, bool HEAD = true>
+template <bool DEBUG, bool HEAD = true, int RNG = kRngHash>
 __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
-                           int lw, TileSmem<DEBUG> &sm)
+                           int lw, TileSmem<DEBUG> &sm, const uint32_t *ltbl = nullptr)
 {
     const int lane = threadIdx.x;
     const int tmask = (1 << lw) - 1;
@@ -246,7 +270,8 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             ItemOut o;
-            shade_item<DEBUG, HEAD>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm, o);
+            shade_item<DEBUG, HEAD, RNG>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm, o,
+                                         ltbl);
             if constexpr (DEBUG) {
                 sm.dslot[lane] = o;
             } else {
@@ -305,15 +330,34 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
 
 // One workgroup per tile.  With a tile order (cost classes, heaviest first)
 // workgroup b shades tile order[b]; without one, tiles go in row-major order.
-template <bool DEBUG>
+// RNG selects the source of the gate uniforms (rng_word); with kRngTableLds
+// the wave first copies the table (rng_mask + 1 words, a multiple of 4,
+// 16-byte aligned) into its dynamic LDS.
+template <bool DEBUG, int RNG = kRngHash>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 4))) void glint_fwd_kernel(
     ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles)
 {
     __shared__ TileSmem<DEBUG> sm;
+    extern __shared__ uint4 glint_rng_lds[];
     const int t = order ? __builtin_amdgcn_readfirstlane(order[blockIdx.x]) : (int)blockIdx.x;
     if ((unsigned)t >= (unsigned)n_tiles) return;
     const int tx = t % tiles_x, ty = t / tiles_x;
-    shade_tile<DEBUG>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm);
+    const uint32_t *ltbl = nullptr;
+    if constexpr (RNG == kRngTableLds) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(sh.rng_tbl);
+        const int n4 = (int)((sh.rng_mask + 1u) >> 2);
+        for (int i = threadIdx.x; i < n4; i += kWave) glint_rng_lds[i] = src[i];
+        __syncthreads();
+        ltbl = reinterpret_cast<const uint32_t *>(glint_rng_lds);
+    }
+    shade_tile<DEBUG, RNG == kRngHash, RNG>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, ltbl);
+}
+
+// Random-number table: t[i] = H(seed, i) for i < n.
+__global__ __launch_bounds__(256) void glint_rng_fill_kernel(uint32_t *__restrict__ t, uint64_t n, uint32_t seed)
+{
+    const uint64_t step = (uint64_t)gridDim.x * 256u;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n; i += step) t[i] = hstep(seed, (uint32_t)i);
 }
 
 // ---------------------------------------------------------------------------
@@ -689,15 +733,15 @@ const char *glint_status_string(int s)
 
 size_t glint_shade_workspace_bytes(int32_t width, int32_t height) { return tile_order_bytes(width, height); }
 
-int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat, const glint_light *lights,
-                int32_t n_light, const glint_params *params, float *out_rgb, const glint_debug *dbg,
-                void *workspace, size_t workspace_bytes, void *stream)
+}  // extern "C"
+
+// Shared body of glint_shade and glint_shade_rng_table: tile order, then one
+// launch of the shading kernel with the uniforms' source RNG.
+static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb, const glint_debug *dbg,
+                          void *workspace, size_t workspace_bytes, int rng, size_t lds_bytes, void *stream)
 {
-    Shared sh;
-    int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
-    if (rc) return rc;
     ViewDesc vw;
-    rc = make_view(gbuf, out_rgb, vw);
+    int rc = make_view(gbuf, out_rgb, vw);
     if (rc) return rc;
     if ((int64_t)vw.width * vw.height == 0) return GLINT_OK;
     const int tiles_x = (int)tiles_x_of(vw.width);
@@ -709,19 +753,81 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
         rc = enqueue_tile_order(vw, sh, workspace, workspace_bytes, &order, st);
         if (rc) return rc;
     }
+    const dim3 grid((unsigned)nt), block(kWave);
     if (dbg) {
+        // the instrumented kernel reads a table through the caches: same words as from LDS
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light,
                           dbg->n_live_small, dbg->n_lit};
-        hipLaunchKernelGGL(glint_fwd_kernel<true>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
-                           kTileLw, tiles_x, order, (int32_t)nt);
+        if (rng == kRngHash)
+            hipLaunchKernelGGL(glint_fwd_kernel<true>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
+                               (int32_t)nt);
+        else
+            hipLaunchKernelGGL((glint_fwd_kernel<true, kRngTable>), grid, block, 0, st, vw, sh, dp, kTileLw,
+                               tiles_x, order, (int32_t)nt);
     } else {
         DebugPlanes dp = {};
-        hipLaunchKernelGGL(glint_fwd_kernel<false>, dim3((unsigned)nt), dim3(kWave), 0, st, vw, sh, dp,
-                           kTileLw, tiles_x, order, (int32_t)nt);
+        if (rng == kRngHash)
+            hipLaunchKernelGGL(glint_fwd_kernel<false>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
+                               (int32_t)nt);
+        else if (rng == kRngTable)
+            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTable>), grid, block, 0, st, vw, sh, dp, kTileLw,
+                               tiles_x, order, (int32_t)nt);
+        else
+            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTableLds>), grid, block, (unsigned)lds_bytes, st, vw,
+                               sh, dp, kTileLw, tiles_x, order, (int32_t)nt);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+}
+
+extern "C" {
+
+int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat, const glint_light *lights,
+                int32_t n_light, const glint_params *params, float *out_rgb, const glint_debug *dbg,
+                void *workspace, size_t workspace_bytes, void *stream)
+{
+    Shared sh;
+    int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
+    if (rc) return rc;
+    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, kRngHash, 0, stream);
+}
+
+int glint_rng_table_fill(uint32_t *table, int32_t log2_words, uint32_t seed, void *stream)
+{
+    if (!table) return GLINT_ENULL;
+    if (log2_words < GLINT_RNG_TABLE_MIN_LOG2 || log2_words > GLINT_RNG_TABLE_MAX_LOG2) return GLINT_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(table) & 15u) != 0) return GLINT_EINVAL;
+    const uint64_t n = 1ull << log2_words;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(glint_rng_fill_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, table, n,
+                       seed);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+}
+
+int glint_shade_rng_table(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
+                          const glint_light *lights, int32_t n_light, const glint_params *params,
+                          const uint32_t *table, int32_t log2_words, int32_t placement, float *out_rgb,
+                          const glint_debug *dbg, void *workspace, size_t workspace_bytes, void *stream)
+{
+    Shared sh;
+    int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
+    if (rc) return rc;
+    if (!table) return GLINT_ENULL;
+    if ((reinterpret_cast<uintptr_t>(table) & 15u) != 0) return GLINT_EINVAL;
+    if (placement == GLINT_RNG_CACHED) {
+        if (log2_words < GLINT_RNG_TABLE_MIN_LOG2 || log2_words > GLINT_RNG_TABLE_MAX_LOG2) return GLINT_EINVAL;
+    } else if (placement == GLINT_RNG_LDS) {
+        if (log2_words < GLINT_RNG_TABLE_MIN_LOG2 || log2_words > GLINT_RNG_LDS_MAX_LOG2) return GLINT_EINVAL;
+    } else {
+        return GLINT_EINVAL;
+    }
+    sh.rng_tbl = table;
+    sh.rng_mask = log2_words >= 32 ? 0xFFFFFFFFu : ((1u << log2_words) - 1u);
+    const int rng = placement == GLINT_RNG_LDS ? kRngTableLds : kRngTable;
+    const size_t lds_bytes = placement == GLINT_RNG_LDS ? (size_t)4 << log2_words : 0;
+    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, rng, lds_bytes, stream);
 }
 
 int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t n_views,

@@ -24,6 +24,8 @@ PLANES = ("u", "v", "dudx", "dvdx", "dudy", "dvdy", "nx", "ny", "nz", "wx", "wy"
 GLINT_OK, GLINT_EINVAL, GLINT_ENULL, GLINT_ESHAPE = 0, -1, -2, -3
 GLINT_EHIP, GLINT_EUNSUPPORTED, GLINT_ENOMEM = -4, -5, -6
 GLINT_MAX_MATERIALS, GLINT_MAX_LIGHTS, GLINT_MAX_K, GLINT_MAX_PROBES = 32, 16, 4, 64
+GLINT_RNG_TABLE_MIN_LOG2, GLINT_RNG_TABLE_MAX_LOG2, GLINT_RNG_LDS_MAX_LOG2 = 8, 32, 13
+GLINT_RNG_CACHED, GLINT_RNG_LDS = 0, 1
 MAX_MATERIALS, MAX_LIGHTS = 32, 16
 
 
@@ -87,6 +89,10 @@ def lib():
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.glint_shade.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
                                   C.POINTER(_Params), vp, C.POINTER(_Debug), vp, C.c_size_t, vp]
+        L.glint_rng_table_fill.argtypes = [vp, i32, C.c_uint32, vp]
+        L.glint_shade_rng_table.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
+                                            C.POINTER(_Params), vp, i32, i32, vp, C.POINTER(_Debug), vp,
+                                            C.c_size_t, vp]
         L.glint_shade_workspace_bytes.argtypes = [i32, i32]
         L.glint_shade_workspace_bytes.restype = C.c_size_t
         L.glint_backward_workspace_bytes.argtypes = [i32, i32, i32, i32]
@@ -184,6 +190,38 @@ def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, ou
     workspace: None allocates the tile-order workspace (heaviest tiles first),
     False shades the tiles in row-major order without one, a uint8 CUDA tensor
     of at least glint_shade_workspace_bytes(W, H) bytes is used as given."""
+    return _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, None)
+
+
+RNG_CACHED, RNG_LDS = GLINT_RNG_CACHED, GLINT_RNG_LDS
+
+
+def glint_rng_table_fill(log2_words, seed, table=None, stream=None):
+    """Random-number table of 2**log2_words words (as int32), entry i = H(seed, i),
+    filled on the GPU.  table: an int32 CUDA tensor of that many elements, or None."""
+    n = 1 << int(log2_words)
+    if table is None:
+        table = torch.empty(n, dtype=torch.int32, device="cuda")
+    elif table.numel() < n:
+        raise ValueError("table is smaller than 2**log2_words words")
+    _check(lib().glint_rng_table_fill(_dev_ptr(table, torch.int32, "table"), int(log2_words),
+                                      int(seed) & 0xFFFFFFFF, _stream(stream)), "glint_rng_table_fill")
+    return table
+
+
+def glint_shade_rng_table(gbuf, materials, lights, table, log2_words, placement=RNG_CACHED, k_max=4,
+                          n_probe_max=21, rounding=0, out=None, debug=False, workspace=None, stream=None):
+    """glint_shade with the gate and count uniforms read from a random-number
+    table (int32 CUDA tensor of at least 2**log2_words words) at index
+    (texel key ^ angular key) mod 2**log2_words; placement RNG_CACHED reads it
+    through the caches, RNG_LDS from a per-tile copy in LDS."""
+    if table.numel() < (1 << int(log2_words)):
+        raise ValueError("table is smaller than 2**log2_words words")
+    rng = (_dev_ptr(table, torch.int32, "table"), int(log2_words), int(placement))
+    return _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, rng)
+
+
+def _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, rng):
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
@@ -210,9 +248,16 @@ def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, ou
             planes[n] = torch.zeros((H, W), dtype=torch.int32, device=dev)
             setattr(dbg, n, planes[n].data_ptr())
     prm = make_params(k_max, n_probe_max, rounding)
-    st = glint_shade_raw(g, make_materials(materials), len(materials), make_lights(lights), len(lights),
-                         prm, _dev_ptr(out, torch.float32, "out"), dbg, _stream(stream), ws_ptr, ws_bytes)
-    _check(st, "glint_shade")
+    if rng is None:
+        st = glint_shade_raw(g, make_materials(materials), len(materials), make_lights(lights), len(lights),
+                             prm, _dev_ptr(out, torch.float32, "out"), dbg, _stream(stream), ws_ptr, ws_bytes)
+        _check(st, "glint_shade")
+    else:
+        st = L.glint_shade_rng_table(C.byref(g), make_materials(materials), len(materials), make_lights(lights),
+                                     len(lights), C.byref(prm), rng[0], rng[1], rng[2],
+                                     _dev_ptr(out, torch.float32, "out"),
+                                     C.byref(dbg) if dbg is not None else None, ws_ptr, ws_bytes, _stream(stream))
+        _check(st, "glint_shade_rng_table")
     return (out, planes) if debug else out
 
 

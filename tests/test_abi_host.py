@@ -36,7 +36,9 @@ def test_exports_every_declared_symbol(lib):
 def test_limits_match_header():
     from paper_2306_05051_amd import glint
     txt = open(HEADER).read()
-    for name in ("GLINT_MAX_MATERIALS", "GLINT_MAX_LIGHTS", "GLINT_MAX_K", "GLINT_MAX_PROBES"):
+    for name in ("GLINT_MAX_MATERIALS", "GLINT_MAX_LIGHTS", "GLINT_MAX_K", "GLINT_MAX_PROBES",
+                 "GLINT_RNG_TABLE_MIN_LOG2", "GLINT_RNG_TABLE_MAX_LOG2", "GLINT_RNG_LDS_MAX_LOG2",
+                 "GLINT_RNG_CACHED", "GLINT_RNG_LDS"):
         m = re.search(r"#define " + name + r"\s+(\d+)", txt)
         assert m and int(m.group(1)) == getattr(glint, name), name
 
@@ -84,6 +86,22 @@ def test_host_validation_without_device(lib):
                          None) == glint.GLINT_ESHAPE
     assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake_out, None, C.c_void_p(4098), need,
                          None) == glint.GLINT_EINVAL
+    # random-number table variant: table pointer, size and placement are checked before any launch
+    shade_t = L.glint_shade_rng_table
+    tbl = C.c_void_p(1 << 20)
+    args = lambda t, lg, pl: (C.byref(g), mats, 1, lts, 1, C.byref(prm), t, lg, pl, fake_out, None, None, 0, None)
+    assert shade_t(*args(None, 12, 0)) == glint.GLINT_ENULL
+    assert shade_t(*args(C.c_void_p((1 << 20) + 4), 12, 0)) == glint.GLINT_EINVAL      # not 16-byte aligned
+    assert shade_t(*args(tbl, 7, 0)) == glint.GLINT_EINVAL
+    assert shade_t(*args(tbl, 33, 0)) == glint.GLINT_EINVAL
+    assert shade_t(*args(tbl, 14, glint.GLINT_RNG_LDS)) == glint.GLINT_EINVAL          # LDS holds at most 2^13
+    assert shade_t(*args(tbl, 12, 2)) == glint.GLINT_EINVAL
+    assert shade_t(C.byref(g), mats, 1, lts, 1, C.byref(bad), tbl, 12, 0, fake_out, None, None, 0,
+                   None) == glint.GLINT_EINVAL
+    assert L.glint_rng_table_fill(None, 12, 0, None) == glint.GLINT_ENULL
+    assert L.glint_rng_table_fill(tbl, 7, 0, None) == glint.GLINT_EINVAL
+    assert L.glint_rng_table_fill(tbl, 33, 0, None) == glint.GLINT_EINVAL
+    assert L.glint_rng_table_fill(C.c_void_p((1 << 20) + 8), 12, 0, None) == glint.GLINT_EINVAL
     # utilities: negative sizes and NULL pointers
     assert L.glint_texel_hash(None, -1, None, None) == glint.GLINT_ESHAPE
     assert L.glint_texel_hash(None, 5, None, None) == glint.GLINT_ENULL
