@@ -172,6 +172,18 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
                 float *out_rgb, const glint_debug *dbg, void *workspace, size_t workspace_bytes,
                 void *stream);
 
+/* glint_shade that also records, for the adjoint, which lights opened at
+ * least one gate (Eq. 18) in each pixel: bit l of lit_lights[y*stride + x]
+ * is set iff some gate of light l opened in some probe of the pixel (0 for
+ * pixels that are not shaded).  The radiance equals glint_shade's bit for
+ * bit.  lit_lights: device memory of height*stride uint16 values, 2-byte
+ * aligned, owned by the caller, overwritten.  Errors as glint_shade, plus
+ * ENULL (lit_lights), EINVAL (misaligned lit_lights). */
+int glint_shade_lit(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
+                    const glint_light *lights, int32_t n_light, const glint_params *params,
+                    float *out_rgb, uint16_t *lit_lights, void *workspace, size_t workspace_bytes,
+                    void *stream);
+
 /* Random-number table for glint_shade_rng_table (Sec. 6.3: the two uniforms
  * of a gated binomial may be read from a small texture of random numbers
  * precomputed once): table[i] = H(seed, i) for i < 2^log2_words, with
@@ -220,13 +232,22 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * bytes, 8-byte aligned, owned by the caller and used by this call only
  * (tile order, one partial row per 32x2 tile, FP64 reduction stage).  Tiles
  * run heaviest first; the sums are reduced in a fixed order over tiles, so
- * the result does not depend on the schedule.  Errors as glint_shade, plus
- * ENULL (workspace, gradient outputs), EINVAL (misaligned workspace). */
+ * the result does not depend on the schedule.
+ * lit_lights (nullable): the mask glint_shade_lit wrote for the same
+ * inputs with rounding 1 (relaxed; the gates do not depend on the rounding).
+ * Every gradient term of a light is proportional to its distributed count,
+ * which is zero when none of its gates opened, so pixels with a zero mask
+ * and lights with a clear bit are skipped, at a fraction of the work: the
+ * same terms are summed, the per-material gradients in the same order (bit
+ * for bit the call without the mask), the light gradients in different
+ * per-batch groupings (equal within FP32 rounding; deterministic).  NULL
+ * evaluates every gate.  Errors as glint_shade, plus ENULL (workspace,
+ * gradient outputs), EINVAL (misaligned workspace or lit_lights). */
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                          const glint_light *lights, int32_t n_light, const glint_params *params,
-                         const float *grad_out_rgb, float *grad_alpha, float *grad_ln_density,
-                         float *grad_light_dir, void *workspace, size_t workspace_bytes,
-                         void *stream);
+                         const float *grad_out_rgb, const uint16_t *lit_lights, float *grad_alpha,
+                         float *grad_ln_density, float *grad_light_dir, void *workspace,
+                         size_t workspace_bytes, void *stream);
 
 /* Batched shading of many views of uneven size in one persistent launch.
  * glint_plan_create copies the view descriptors (device pointers inside

@@ -72,7 +72,7 @@ _DBG_FIELDS = [("flags", np.uint32), ("n_probe", np.int32), ("level", np.int32),
 
 
 class _Dbg(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n, _ in _DBG_FIELDS] + [("b_light", C.c_void_p)]
+    _fields_ = [(n, C.c_void_p) for n, _ in _DBG_FIELDS] + [("b_light", C.c_void_p), ("lit", C.c_void_p)]
 
 
 class _Nodes(C.Structure):
@@ -182,6 +182,8 @@ def shade(gb, materials, lights, k_max=4, n_probe_max=21, rounding=0, debug=Fals
             setattr(dbg, n, planes[n].ctypes.data)
         planes["b_light"] = np.zeros((max(1, len(lights)), H, W), np.float64)
         dbg.b_light = planes["b_light"].ctypes.data
+        planes["lit"] = np.zeros((H, W), np.uint32)
+        dbg.lit = planes["lit"].ctypes.data
     r0, r1 = (0, H) if rows is None else rows
     rc = L.og_shade(C.byref(s), mats, len(materials), lts, len(lights), C.byref(prm),
                     out.ctypes.data, C.byref(dbg) if dbg is not None else None, r0, r1, n_threads)

@@ -87,6 +87,7 @@ typedef struct {                  /* every plane is [height*stride] or NULL */
     double *margin_pos;           /* smallest margin rounding can decide (INFINITY when none) */
     int32_t *margin_pos_kind;
     double *b_light;              /* [n_light][height*stride]: raw distributed counts */
+    uint32_t *lit;                /* bit l: some gate of light l opened in some probe (l < 32) */
 } og_debug;
 
 /* flags */
@@ -526,7 +527,7 @@ typedef struct {
 
 typedef struct {
     double rgb[3];
-    uint32_t flags, cell, key_sum, akey_sum, theta_sum, count_sum, n_open, n_gate, n_live;
+    uint32_t flags, cell, key_sum, akey_sum, theta_sum, count_sum, n_open, n_gate, n_live, lit;
     int32_t n_probe, level;
     double margin[2];              /* smallest, smallest positive (see upd_margin) */
     int32_t margin_kind[2];
@@ -679,6 +680,7 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
                         double c = 0.0;
                         if (open) {                   /* Eq. 18 with the gate read as theta0 < P>=1 */
                             o->n_open++;
+                            if (li < 32) o->lit |= 1u << li;
                             uint32_t h1 = gate_word(prm, pre[g][e], akey[li][a][1]);
                             double x = 1.0 + mu + sg * og_ndtri(uniform_of(h1));
                             if (x >= 1.5) {
@@ -781,6 +783,7 @@ int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_
                 if (dbg->n_open) dbg->n_open[idx] = o.n_open;
                 if (dbg->n_gate) dbg->n_gate[idx] = o.n_gate;
                 if (dbg->n_live) dbg->n_live[idx] = o.n_live;
+                if (dbg->lit) dbg->lit[idx] = o.lit;
                 if (dbg->margin) dbg->margin[idx] = o.margin[0];
                 if (dbg->margin_kind) dbg->margin_kind[idx] = o.margin_kind[0];
                 if (dbg->margin_pos) dbg->margin_pos[idx] = o.margin[1];

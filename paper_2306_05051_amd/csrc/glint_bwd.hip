@@ -14,6 +14,12 @@
 // partial row in the workspace (row index = tile index, so the sums do not
 // depend on the order in which tiles run); two FP64 kernels then sum the rows
 // in a fixed order.  Tiles run heaviest first (the forward's tile order).
+//
+// Every gradient term of a light is proportional to its distributed count b,
+// which is zero unless one of its gates opened.  Given the forward's record
+// of which lights opened a gate in each pixel (glint_shade_lit), the adjoint
+// skips the pixels with none and, in the others, the lights with none: the
+// same sums, without recomputing the gates that the forward found closed.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -47,8 +53,11 @@ struct BwdSmem {
 // Called by every lane of the wave (live = false contributes zeros).  Gates
 // are collected in bit masks and the open ones processed in a compacted loop,
 // as in the forward.
+// Lights whose bit in litm is clear are skipped: the forward opened none of
+// their gates in this pixel, so they contribute exactly zero.
 __device__ void grad_item(bool live, const PixelRec &R, double u, double v, const double n[3], const double wi[3],
-                          int kp, const Shared &sh, const float gout[3], float &da, float &dn, BwdSmem &sm)
+                          int kp, const Shared &sh, const float gout[3], uint32_t litm, float &da, float &dn,
+                          BwdSmem &sm)
 {
     da = 0.0f;
     dn = 0.0f;
@@ -70,7 +79,7 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
         float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
         bool opened = false;                     // this lane opened a gate of this light
         LightEval le;
-        if (live && eval_light(n, wi, alpha, L, M, fr, le)) {
+        if (live && ((litm >> li) & 1u) && eval_light(n, wi, alpha, L, M, fr, le)) {
             const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
             const float p = le.p;
             const float lp = log1m(p);
@@ -206,9 +215,11 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
     }
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void glint_bwd_kernel(ViewDesc vw, Shared sh, const float *gout, int tiles_x,
-                                                       const int32_t *__restrict__ order, int32_t n_tiles,
-                                                       float *partials, int n_par, int row_stride)
+// lit (nullable): the forward's per-pixel mask of lights with an open gate;
+// pixels with none are skipped, and so are the other lights of a pixel.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void glint_bwd_kernel(
+    ViewDesc vw, Shared sh, const float *gout, const uint16_t *__restrict__ lit, int tiles_x,
+    const int32_t *__restrict__ order, int32_t n_tiles, float *partials, int n_par, int row_stride)
 {
     __shared__ BwdSmem sm;
     const int lane = threadIdx.x;
@@ -225,7 +236,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         Pixel px;
         px.flags = 0;
         px.npr = 0;
-        if (inb) setup_pixel<false>(vw, idx, sh, px);
+        if (inb && (!lit || lit[idx] != 0)) setup_pixel<false>(vw, idx, sh, px);
         if (px.flags & F_SHADED) {
             npr = px.npr;
             sm.rec[lane] = make_rec(px, sh);
@@ -247,6 +258,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         const bool live = q < S;
         int p = 0, kp = 0;
         float g3[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t litm = 0u;
         double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, u = 0.0, v = 0.0;
         if (live) {
 #pragma unroll
@@ -261,9 +273,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
             g3[0] = gout[pidx];
             g3[1] = gout[npx + pidx];
             g3[2] = gout[2 * npx + pidx];
+            litm = lit ? (uint32_t)lit[pidx] : 0xffffffffu;
         }
         float da, dn;
-        grad_item(live, sm.rec[p], u, v, n, wi, kp, sh, g3, da, dn, sm);
+        grad_item(live, sm.rec[p], u, v, n, wi, kp, sh, g3, litm, da, dn, sm);
         sm.pre[0][lane] = live ? (uint32_t)rec_mat(sm.rec[p]) : 0xffffffffu;
         sm.pre[1][lane] = __float_as_uint(da);
         sm.pre[2][lane] = __float_as_uint(dn);
@@ -395,8 +408,9 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
 
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                          const glint_light *lights, int32_t n_light, const glint_params *params,
-                         const float *grad_out_rgb, float *grad_alpha, float *grad_ln_density,
-                         float *grad_light_dir, void *workspace, size_t workspace_bytes, void *stream)
+                         const float *grad_out_rgb, const uint16_t *lit_lights, float *grad_alpha,
+                         float *grad_ln_density, float *grad_light_dir, void *workspace, size_t workspace_bytes,
+                         void *stream)
 {
     if (!params) return GLINT_ENULL;
     glint_params prm = *params;
@@ -405,6 +419,7 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
     int rc = prepare_shared(mats, n_mat, lights, n_light, &prm, sh);
     if (rc) return rc;
     if (!grad_alpha || !grad_ln_density || (n_light > 0 && !grad_light_dir)) return GLINT_ENULL;
+    if ((reinterpret_cast<uintptr_t>(lit_lights) & 1u) != 0) return GLINT_EINVAL;
     ViewDesc vw;
     rc = make_view(gbuf, reinterpret_cast<float *>(const_cast<float *>(grad_out_rgb)), vw);
     if (rc) return rc;
@@ -430,8 +445,8 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
     if (rc) return rc;
     float *partials = (float *)((char *)workspace + L.part_off);
     double *stage1 = (double *)((char *)workspace + L.stage1_off);
-    hipLaunchKernelGGL(glint_bwd_kernel, dim3((unsigned)tiles), dim3(kWave), 0, st, vw, sh, grad_out_rgb, tiles_x,
-                       order, (int32_t)tiles, partials, n_par, L.stride);
+    hipLaunchKernelGGL(glint_bwd_kernel, dim3((unsigned)tiles), dim3(kWave), 0, st, vw, sh, grad_out_rgb, lit_lights,
+                       tiles_x, order, (int32_t)tiles, partials, n_par, L.stride);
     hipLaunchKernelGGL(glint_bwd_reduce1, dim3((unsigned)L.n_blk), dim3(kReduceThreads), 0, st, partials, tiles,
                        L.stride, L.rpb, stage1);
     hipLaunchKernelGGL(glint_bwd_reduce2, dim3(1), dim3(kReduceThreads), 0, st, stage1, (int)L.n_blk, L.stride,

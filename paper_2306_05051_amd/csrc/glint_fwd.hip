@@ -38,6 +38,7 @@ int set_hip_error(hipError_t e)
 
 struct ItemOut {
     float rgb[3];
+    uint32_t lit;              // bit l: a gate of light l opened (recorded by glint_shade_lit)
     uint32_t key_sum, theta_sum, count_sum, n_open, n_gate, n_live, n_live_small, n_lit;
     float b[kMaxLight];
 };
@@ -89,13 +90,14 @@ __device__ __forceinline__ uint32_t rng_word(uint32_t pre, uint32_t ak, const Sh
     }
 }
 
-template <bool DEBUG, bool HEAD = true, int RNG = kRngHash>
+template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false>
 __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v, const double n[3],
                                            const double wi[3], int kp, const Shared &sh, TileSmem<DEBUG> &sm,
                                            ItemOut &o, const uint32_t *ltbl)
 {
     const int lane = threadIdx.x;
     o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
+    if (LIT) o.lit = 0u;
     if (DEBUG) {
         o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = o.n_live_small = o.n_lit = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
@@ -168,6 +170,7 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
         // a light without an open gate adds exactly +0 to the (non-negative) sums
         if ((mlo | mhi) == 0u) continue;
         if (DEBUG) o.n_lit += 1;
+        if (LIT) o.lit |= 1u << li;
         light_brdf(M, R.alpha, le);
         float bsum = 0.0f;
         while (mlo | mhi) {
@@ -214,9 +217,9 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 // ---------------------------------------------------------------------------
 // One tile of 64 pixels (tile_w x 64/tile_w) at (x0, y0) of a view.
 // ---------------------------------------------------------------------------
-template <bool DEBUG, bool HEAD = true, int RNG = kRngHash>
+template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false>
 __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
-                           int lw, TileSmem<DEBUG> &sm, const uint32_t *ltbl = nullptr)
+                           int lw, TileSmem<DEBUG> &sm, const uint32_t *ltbl = nullptr, uint16_t *lit = nullptr)
 {
     const int lane = threadIdx.x;
     const int tmask = (1 << lw) - 1;
@@ -253,6 +256,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     sm.off[lane] = off;
     __syncthreads();
     float acc[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t litacc = 0u;
     uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0, dns = 0, dlt = 0;
     float db[kMaxLight];
     if (DEBUG)
@@ -270,14 +274,15 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             ItemOut o;
-            shade_item<DEBUG, HEAD, RNG>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm, o,
-                                         ltbl);
+            shade_item<DEBUG, HEAD, RNG, LIT>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm,
+                                              o, ltbl);
             if constexpr (DEBUG) {
                 sm.dslot[lane] = o;
             } else {
                 sm.pre[0][lane] = __float_as_uint(o.rgb[0]);
                 sm.pre[1][lane] = __float_as_uint(o.rgb[1]);
                 sm.pre[2][lane] = __float_as_uint(o.rgb[2]);
+                if (LIT) sm.pre[3][lane] = o.lit;
             }
         }
         __syncthreads();
@@ -298,6 +303,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                     acc[0] += __uint_as_float(sm.pre[0][i - base]);
                     acc[1] += __uint_as_float(sm.pre[1][i - base]);
                     acc[2] += __uint_as_float(sm.pre[2][i - base]);
+                    if (LIT) litacc |= sm.pre[3][i - base];
                 }
             }
         }
@@ -308,6 +314,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
         vw.out[idx] = acc[0];
         vw.out[npx + idx] = acc[1];
         vw.out[2 * npx + idx] = acc[2];
+        if (LIT) lit[idx] = (uint16_t)litacc;
         if (DEBUG) {
             if (dp.flags) dp.flags[idx] = dflags;
             if (dp.n_probe) dp.n_probe[idx] = npr;
@@ -333,9 +340,12 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
 // RNG selects the source of the gate uniforms (rng_word); with kRngTableLds
 // the wave first copies the table (rng_mask + 1 words, a multiple of 4,
 // 16-byte aligned) into its dynamic LDS.
-template <bool DEBUG, int RNG = kRngHash>
+// With LIT the kernel also writes, per pixel, the bit mask of the lights that
+// opened a gate in any of the pixel's probes (lit[y * stride + x]).
+template <bool DEBUG, int RNG = kRngHash, bool LIT = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 4))) void glint_fwd_kernel(
-    ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles)
+    ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles,
+    uint16_t *__restrict__ lit)
 {
     __shared__ TileSmem<DEBUG> sm;
     extern __shared__ uint4 glint_rng_lds[];
@@ -350,7 +360,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 
         __syncthreads();
         ltbl = reinterpret_cast<const uint32_t *>(glint_rng_lds);
     }
-    shade_tile<DEBUG, RNG == kRngHash, RNG>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, ltbl);
+    shade_tile<DEBUG, RNG == kRngHash, RNG, LIT>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, ltbl, lit);
 }
 
 // Random-number table: t[i] = H(seed, i) for i < n.
@@ -738,7 +748,8 @@ size_t glint_shade_workspace_bytes(int32_t width, int32_t height) { return tile_
 // Shared body of glint_shade and glint_shade_rng_table: tile order, then one
 // launch of the shading kernel with the uniforms' source RNG.
 static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb, const glint_debug *dbg,
-                          void *workspace, size_t workspace_bytes, int rng, size_t lds_bytes, void *stream)
+                          void *workspace, size_t workspace_bytes, int rng, size_t lds_bytes, uint16_t *lit,
+                          void *stream)
 {
     ViewDesc vw;
     int rc = make_view(gbuf, out_rgb, vw);
@@ -761,21 +772,24 @@ static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb,
                           dbg->n_live_small, dbg->n_lit};
         if (rng == kRngHash)
             hipLaunchKernelGGL(glint_fwd_kernel<true>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
-                               (int32_t)nt);
+                               (int32_t)nt, nullptr);
         else
             hipLaunchKernelGGL((glint_fwd_kernel<true, kRngTable>), grid, block, 0, st, vw, sh, dp, kTileLw,
-                               tiles_x, order, (int32_t)nt);
+                               tiles_x, order, (int32_t)nt, nullptr);
     } else {
         DebugPlanes dp = {};
-        if (rng == kRngHash)
+        if (rng == kRngHash && lit)
+            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngHash, true>), grid, block, 0, st, vw, sh, dp, kTileLw,
+                               tiles_x, order, (int32_t)nt, lit);
+        else if (rng == kRngHash)
             hipLaunchKernelGGL(glint_fwd_kernel<false>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
-                               (int32_t)nt);
+                               (int32_t)nt, nullptr);
         else if (rng == kRngTable)
             hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTable>), grid, block, 0, st, vw, sh, dp, kTileLw,
-                               tiles_x, order, (int32_t)nt);
+                               tiles_x, order, (int32_t)nt, nullptr);
         else
             hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTableLds>), grid, block, (unsigned)lds_bytes, st, vw,
-                               sh, dp, kTileLw, tiles_x, order, (int32_t)nt);
+                               sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);
@@ -790,7 +804,19 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     Shared sh;
     int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
     if (rc) return rc;
-    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, kRngHash, 0, stream);
+    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, kRngHash, 0, nullptr, stream);
+}
+
+int glint_shade_lit(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat, const glint_light *lights,
+                    int32_t n_light, const glint_params *params, float *out_rgb, uint16_t *lit_lights,
+                    void *workspace, size_t workspace_bytes, void *stream)
+{
+    Shared sh;
+    int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
+    if (rc) return rc;
+    if (!lit_lights) return GLINT_ENULL;
+    if ((reinterpret_cast<uintptr_t>(lit_lights) & 1u) != 0) return GLINT_EINVAL;
+    return launch_forward(gbuf, sh, out_rgb, nullptr, workspace, workspace_bytes, kRngHash, 0, lit_lights, stream);
 }
 
 int glint_rng_table_fill(uint32_t *table, int32_t log2_words, uint32_t seed, void *stream)
@@ -827,7 +853,7 @@ int glint_shade_rng_table(const glint_gbuffer *gbuf, const glint_material *mats,
     sh.rng_mask = log2_words >= 32 ? 0xFFFFFFFFu : ((1u << log2_words) - 1u);
     const int rng = placement == GLINT_RNG_LDS ? kRngTableLds : kRngTable;
     const size_t lds_bytes = placement == GLINT_RNG_LDS ? (size_t)4 << log2_words : 0;
-    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, rng, lds_bytes, stream);
+    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, rng, lds_bytes, nullptr, stream);
 }
 
 int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t n_views,

@@ -98,7 +98,9 @@ def lib():
         L.glint_backward_workspace_bytes.argtypes = [i32, i32, i32, i32]
         L.glint_backward_workspace_bytes.restype = C.c_size_t
         L.glint_shade_backward.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
-                                           C.POINTER(_Params), vp, vp, vp, vp, vp, C.c_size_t, vp]
+                                           C.POINTER(_Params), vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.glint_shade_lit.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
+                                      C.POINTER(_Params), vp, vp, vp, C.c_size_t, vp]
         L.glint_plan_create.argtypes = [C.POINTER(_GBuf), C.POINTER(vp), i32, C.POINTER(_Mat), i32,
                                         C.POINTER(_Light), i32, C.POINTER(_Params), C.POINTER(_Tune),
                                         C.POINTER(vp)]
@@ -270,10 +272,35 @@ def glint_backward_workspace_bytes(width, height, n_mat, n_light):
     return lib().glint_backward_workspace_bytes(width, height, n_mat, n_light)
 
 
+def glint_shade_lit(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=1, out=None, lit=None,
+                    workspace=None, stream=None):
+    """(radiance [3, H, W], lit [H, W] int16): glint_shade that also records, per
+    pixel, the bit mask of the lights with an open gate, for glint_shade_backward."""
+    L = lib()
+    g = make_gbuffer(gbuf)
+    H, W = gbuf["u"].shape
+    dev = gbuf["u"].device
+    if out is None:
+        out = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    if lit is None:
+        lit = torch.empty((H, W), dtype=torch.int16, device=dev)
+    nbytes = L.glint_shade_workspace_bytes(W, H)
+    if workspace is None or workspace is False:
+        workspace = torch.empty(max(1, nbytes), dtype=torch.uint8, device=dev)
+    st = L.glint_shade_lit(C.byref(g), make_materials(materials), len(materials), make_lights(lights),
+                           len(lights), C.byref(make_params(k_max, n_probe_max, rounding)),
+                           _dev_ptr(out, torch.float32, "out"), _dev_ptr(lit, torch.int16, "lit"),
+                           _dev_ptr(workspace, torch.uint8, "workspace"), nbytes, _stream(stream))
+    _check(st, "glint_shade_lit")
+    return out, lit
+
+
 def glint_shade_backward(gbuf, materials, lights, grad_out, k_max=4, n_probe_max=21, workspace=None,
-                         stream=None):
+                         stream=None, lit=None):
     """(grad_alpha[n_mat], grad_ln_density[n_mat], grad_light_dir[n_light, 3]) of
-    sum(grad_out * L) for the relaxed forward."""
+    sum(grad_out * L) for the relaxed forward.  lit: the int16 mask from
+    glint_shade_lit on the same inputs (skips lights and pixels without an
+    open gate; same result), or None to evaluate every gate."""
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
@@ -288,6 +315,7 @@ def glint_shade_backward(gbuf, materials, lights, grad_out, k_max=4, n_probe_max
     st = L.glint_shade_backward(C.byref(g), make_materials(materials), nm, make_lights(lights), nl,
                                 C.byref(make_params(k_max, n_probe_max, 1)),
                                 _dev_ptr(grad_out.contiguous(), torch.float32, "grad_out"),
+                                None if lit is None else _dev_ptr(lit, torch.int16, "lit"),
                                 ga.data_ptr(), gn.data_ptr(), gd.data_ptr(), workspace.data_ptr(),
                                 nbytes, _stream(stream))
     _check(st, "glint_shade_backward")

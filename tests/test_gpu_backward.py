@@ -114,3 +114,61 @@ def test_backward_deterministic_and_errors(glint):
     with pytest.raises(glint.GlintError) as e:
         glint.glint_shade_backward(g2, mats, lights, go)
     assert e.value.status == glint.GLINT_EUNSUPPORTED
+
+
+def _lit_cases():
+    return [("backward 128x96", lambda: scenes.backward_scene(128, 96, seed=7)[:3]),
+            ("4k-like 3 lights", lambda: scenes.four_k(96, 64, seed=9, n_light=3, n_mat=4)),
+            ("4k-like 16 lights", lambda: scenes.four_k(64, 40, seed=11, n_light=16, n_mat=5)),
+            ("paper plane25", lambda: scenes.paper_setting(160, 90, view="plane25", log10_density=6.0, seed=3))]
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_lit_mask_matches_oracle(glint, case):
+    """glint_shade_lit: radiance identical to glint_shade, and per pixel the set
+    of lights with an open gate equals the oracle's on every compared pixel."""
+    from parity_util import MARGIN
+    label, make = _lit_cases()[case]
+    gb, mats, lights = make()
+    print(f"  {label}: {gb['u'].shape}, {len(lights)} lights", flush=True)
+    dgb = glint.to_device(gb)
+    out, lit = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
+    ref = glint.glint_shade(dgb, mats, lights, rounding=1)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    g = lit.cpu().numpy().view(np.uint16).astype(np.uint32)
+    _, d = oracle.shade(gb, mats, lights, rounding=1, debug=True)
+    shaded = (d["flags"] & 1) > 0
+    ok = shaded & (d["margin_pos"] >= MARGIN)
+    assert np.all(g[~shaded] == 0)
+    assert np.array_equal(g[ok], d["lit"][ok])
+    assert np.count_nonzero(g) > 20
+    print(f"  {label}: {np.count_nonzero(g)} of {shaded.sum()} shaded pixels lit, "
+          f"{int(np.unpackbits(g.view(np.uint8)).sum())} lit pixel-lights", flush=True)
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_backward_with_lit_mask_matches_full_adjoint(glint, case):
+    """The adjoint that skips the pixels and lights the forward found without an
+    open gate adds the same terms as the full adjoint: the per-material sums run
+    in the same order (bit for bit); the light sums, reduced per 64-item batch,
+    group the terms differently once unlit pixels no longer take batch slots
+    (equal within FP32 rounding)."""
+    label, make = _lit_cases()[case]
+    gb, mats, lights = make()
+    dgb = glint.to_device(gb)
+    _, lit = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
+    go = torch.randn((3,) + gb["u"].shape, device="cuda", generator=torch.Generator("cuda").manual_seed(case))
+    full = glint.glint_shade_backward(dgb, mats, lights, go)
+    fast = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit)
+    torch.cuda.synchronize()
+    print(f"  {label}: grad alpha {full[0].cpu().numpy()}", flush=True)
+    assert torch.equal(full[0], fast[0]) and torch.equal(full[1], fast[1])
+    d0, d1 = full[2].double(), fast[2].double()
+    assert float((d0 - d1).abs().max()) <= 1e-5 * float(d0.abs().max()) + 1e-30
+    assert float(full[0].abs().sum()) > 0.0
+    # the masked adjoint is deterministic too
+    again = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit)
+    torch.cuda.synchronize()
+    for x, y in zip(fast, again):
+        assert torch.equal(x, y)

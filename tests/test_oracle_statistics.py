@@ -234,3 +234,20 @@ def test_frozen_gradient_equals_free_differences():
     ga4, gn4, gd4, _ = oracle.grad(gb, mats, lights, go, step=1e-5, frozen=True)
     for a, b in ((ga, ga4), (gn, gn4), (gd, gd4)):
         assert np.allclose(a, b, rtol=1e-6, atol=1e-9 * np.abs(a).max())
+
+
+def test_lit_plane_follows_open_gates():
+    """The oracle's per-pixel lit mask (lights with an open gate) agrees with its
+    open-gate count and with the distributed counts it produced."""
+    gb, mats, lights = scenes.four_k(64, 40, seed=11, n_light=5, n_mat=3)
+    _, d = oracle.shade(gb, mats, lights, debug=True)
+    lit = d["lit"].astype(np.int64)
+    assert np.array_equal(lit != 0, d["n_open"] > 0)
+    assert np.all(lit < (1 << len(lights)))
+    for l in range(len(lights)):
+        has = (lit >> l) & 1
+        assert np.all(has[d["b_light"][l] > 0] == 1)
+    assert np.count_nonzero(lit) > 50
+    gb1, mats1, lights1 = scenes.four_k(48, 24, seed=2, n_light=1, n_mat=2)
+    _, d1 = oracle.shade(gb1, mats1, lights1, debug=True)
+    assert np.array_equal(d1["lit"], (d1["n_open"] > 0).astype(np.uint32))
