@@ -229,19 +229,20 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * reduced in a fixed order (deterministic).  Per-pixel overrides
  * (alpha_px, log10_density_px) are not supported (EUNSUPPORTED).
  * workspace: device memory of at least glint_backward_workspace_bytes()
- * bytes, 8-byte aligned, owned by the caller and used by this call only
- * (tile order, one partial row per 32x2 tile, FP64 reduction stage).  Tiles
- * run heaviest first; the sums are reduced in a fixed order over tiles, so
- * the result does not depend on the schedule.
+ * bytes (about 4 bytes per pixel plus one partial row per 32x2 tile),
+ * 8-byte aligned, owned by the caller and used by this call only (tile
+ * order, partial rows, FP64 reduction stage, lit-pixel list).  Without a
+ * mask, tiles run heaviest first; the sums are reduced in a fixed order over
+ * tiles, so the result does not depend on the schedule.
  * lit_lights (nullable): the mask glint_shade_lit wrote for the same
  * inputs with rounding 1 (relaxed; the gates do not depend on the rounding).
  * Every gradient term of a light is proportional to its distributed count,
- * which is zero when none of its gates opened, so pixels with a zero mask
- * and lights with a clear bit are skipped, at a fraction of the work: the
- * same terms are summed, the per-material gradients in the same order (bit
- * for bit the call without the mask), the light gradients in different
- * per-batch groupings (equal within FP32 rounding; deterministic).  NULL
- * evaluates every gate.  Errors as glint_shade, plus ENULL (workspace,
+ * which is zero when none of its gates opened, so only the pixels with a
+ * non-zero mask are shaded (gathered in raster order into waves of 64 lit
+ * pixels; each such chunk has its own partial row) and only their lights
+ * with a set bit: a fraction of the work, the same terms summed in another
+ * grouping (equal within FP32 rounding to the call without the mask;
+ * deterministic).  NULL evaluates every gate of every pixel.  Errors as glint_shade, plus ENULL (workspace,
  * gradient outputs), EINVAL (misaligned workspace or lit_lights). */
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                          const glint_light *lights, int32_t n_light, const glint_params *params,

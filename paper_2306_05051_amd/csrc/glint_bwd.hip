@@ -18,8 +18,9 @@
 // Every gradient term of a light is proportional to its distributed count b,
 // which is zero unless one of its gates opened.  Given the forward's record
 // of which lights opened a gate in each pixel (glint_shade_lit), the adjoint
-// skips the pixels with none and, in the others, the lights with none: the
-// same sums, without recomputing the gates that the forward found closed.
+// shades only the pixels with one, gathered into full waves, and in those
+// only the lights with one: the same terms, without recomputing the gates
+// that the forward found closed.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -215,21 +216,40 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
     }
 }
 
+// Work units: without a lit mask, workgroup b shades the 32x2 tile order[b]
+// (heaviest first); with one, workgroup b takes the lit pixels
+// list[64 b .. 64 b + 63] (raster order, built by the compaction passes
+// below), so that the few lit pixels fill whole waves.  The partial row is
+// that of the tile, or of the chunk b.
 // lit (nullable): the forward's per-pixel mask of lights with an open gate;
-// pixels with none are skipped, and so are the other lights of a pixel.
+// only the lights of a pixel whose bit is set are evaluated.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void glint_bwd_kernel(
-    ViewDesc vw, Shared sh, const float *gout, const uint16_t *__restrict__ lit, int tiles_x,
-    const int32_t *__restrict__ order, int32_t n_tiles, float *partials, int n_par, int row_stride)
+    ViewDesc vw, Shared sh, const float *gout, const uint16_t *__restrict__ lit, const uint32_t *__restrict__ list,
+    const uint32_t *__restrict__ list_len, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles,
+    float *partials, int n_par, int row_stride)
 {
     __shared__ BwdSmem sm;
     const int lane = threadIdx.x;
     constexpr int tile_w = kTileW, tile_h = kTileH;
-    const int tile = order ? __builtin_amdgcn_readfirstlane(order[blockIdx.x]) : (int)blockIdx.x;
-    if ((unsigned)tile >= (unsigned)n_tiles) return;
-    const int x0 = (tile % tiles_x) * tile_w, y0 = (tile / tiles_x) * tile_h;
-    const int x = x0 + (lane % tile_w), y = y0 + (lane / tile_w);
-    const bool inb = (x < vw.width) && (y < vw.height);
-    const int64_t idx = (int64_t)y * vw.stride + x;
+    int row;
+    bool inb;
+    int64_t idx;
+    if (list) {
+        const uint32_t len = __builtin_amdgcn_readfirstlane(list_len[0]);
+        const uint32_t q = blockIdx.x * (uint32_t)kWave + (uint32_t)lane;
+        if (blockIdx.x * (uint32_t)kWave >= len) return;
+        row = (int)blockIdx.x;
+        inb = q < len;
+        idx = inb ? (int64_t)list[q] : 0;
+    } else {
+        const int tile = order ? __builtin_amdgcn_readfirstlane(order[blockIdx.x]) : (int)blockIdx.x;
+        if ((unsigned)tile >= (unsigned)n_tiles) return;
+        row = tile;
+        const int x0 = (tile % tiles_x) * tile_w, y0 = (tile / tiles_x) * tile_h;
+        const int x = x0 + (lane % tile_w), y = y0 + (lane / tile_w);
+        inb = (x < vw.width) && (y < vw.height);
+        idx = (int64_t)y * vw.stride + x;
+    }
     const int64_t npx = (int64_t)vw.height * vw.stride;
     int npr = 0;
     {
@@ -257,15 +277,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         const int q = base + lane;
         const bool live = q < S;
         int p = 0, kp = 0;
+#pragma unroll
+        for (int st = 32; st > 0; st >>= 1)
+            if (sm.off[p + st] <= q) p += st;
+        const int64_t pidx = __shfl(idx, p);     // the item's pixel (all lanes take part)
         float g3[3] = {0.0f, 0.0f, 0.0f};
         uint32_t litm = 0u;
         double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, u = 0.0, v = 0.0;
         if (live) {
-#pragma unroll
-            for (int st = 32; st > 0; st >>= 1)
-                if (sm.off[p + st] <= q) p += st;
             kp = q - sm.off[p];
-            const int64_t pidx = (int64_t)(y0 + p / tile_w) * vw.stride + (x0 + p % tile_w);
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             u = vw.u[pidx];
@@ -292,7 +312,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         __syncthreads();
     }
     // row of this tile: [alpha, lnN] per material, then 3 per light, zero padding to row_stride
-    float *row = partials + (int64_t)tile * row_stride;
+    float *prow = partials + (int64_t)row * row_stride;
     for (int c0 = 0; c0 < row_stride; c0 += kWave) {       // uniform loop: every lane takes part in the shuffles
         const int c = c0 + lane;
         const int m = (c >> 1) & (kWave - 1);                // material of column c (lane m holds its sums)
@@ -300,7 +320,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         float v = 0.0f;
         if (c < 2 * sh.n_mat) v = (c & 1) ? vn : va;
         else if (c < n_par) v = (&sm.dd[0][0])[c - 2 * sh.n_mat];
-        if (c < row_stride) row[c] = v;
+        if (c < row_stride) prow[c] = v;
     }
 }
 
@@ -335,9 +355,16 @@ __device__ __forceinline__ void column_sums(const T *__restrict__ flat, int64_t 
     }
 }
 
+// list_len (nullable): with the lit-pixel list, only the rows of the
+// ceil(list_len / 64) chunks hold partial sums.
 __global__ __launch_bounds__(kReduceThreads) void glint_bwd_reduce1(const float *partials, int64_t n_rows,
-                                                                    int stride, int64_t rpb, double *stage1)
+                                                                    const uint32_t *list_len, int stride,
+                                                                    int64_t rpb, double *stage1)
 {
+    if (list_len) {
+        const int64_t used = ((int64_t)list_len[0] + kWave - 1) / kWave;
+        n_rows = used < n_rows ? used : n_rows;
+    }
     const int64_t r0 = (int64_t)blockIdx.x * rpb;
     const int64_t r1 = r0 + rpb < n_rows ? r0 + rpb : n_rows;
     column_sums(partials + r0 * stride, r1 > r0 ? (r1 - r0) * stride : 0, stride,
@@ -367,6 +394,81 @@ static int64_t bwd_tiles(int32_t width, int32_t height)
     return tiles_of(width, height);
 }
 
+// ---------------------------------------------------------------------------
+// Lit-pixel list for the adjoint: the pixels whose lit mask is non-zero, in
+// raster order.  Segments of kLitSeg pixels of one row, in raster order:
+//   count:   lit pixels per segment
+//   scan:    one workgroup turns the counts into offsets and the list length
+//   scatter: each segment writes its lit pixels' indices y*stride + x
+// ---------------------------------------------------------------------------
+constexpr int kLitSeg = 256;
+constexpr int kLitScan = 1024;
+
+__global__ __launch_bounds__(kLitSeg) void glint_lit_count(const uint16_t *__restrict__ lit, int32_t width,
+                                                           int64_t stride, int32_t segs_x,
+                                                           uint32_t *__restrict__ counts)
+{
+    __shared__ uint32_t wc[kLitSeg / kWave];
+    const int64_t seg = blockIdx.x;
+    const int64_t y = seg / segs_x;
+    const int x = (int)(seg - y * segs_x) * kLitSeg + (int)threadIdx.x;
+    const bool on = x < width && lit[y * stride + x] != 0;
+    const uint64_t b = __ballot(on);
+    if ((threadIdx.x & (kWave - 1)) == 0) wc[threadIdx.x / kWave] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kLitSeg / kWave; ++w) t += wc[w];
+        counts[seg] = t;
+    }
+}
+
+__global__ __launch_bounds__(kLitScan) void glint_lit_scan(const uint32_t *__restrict__ counts, int64_t n,
+                                                           uint32_t *__restrict__ offs, uint32_t *__restrict__ len)
+{
+    __shared__ uint32_t ws[kLitScan];
+    const int t = threadIdx.x;
+    const int64_t per = (n + kLitScan - 1) / kLitScan;
+    const int64_t b0 = (int64_t)t * per < n ? (int64_t)t * per : n;
+    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    uint32_t own = 0;
+    for (int64_t i = b0; i < b1; ++i) own += counts[i];
+    ws[t] = own;
+    __syncthreads();
+    for (int d = 1; d < kLitScan; d <<= 1) {        // inclusive scan of the per-thread sums
+        const uint32_t v = t >= d ? ws[t - d] : 0u;
+        __syncthreads();
+        ws[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = ws[t] - own;
+    for (int64_t i = b0; i < b1; ++i) {
+        offs[i] = run;
+        run += counts[i];
+    }
+    if (t == kLitScan - 1) len[0] = ws[t];
+}
+
+__global__ __launch_bounds__(kLitSeg) void glint_lit_scatter(const uint16_t *__restrict__ lit, int32_t width,
+                                                             int64_t stride, int32_t segs_x,
+                                                             const uint32_t *__restrict__ offs,
+                                                             uint32_t *__restrict__ list)
+{
+    __shared__ uint32_t wc[kLitSeg / kWave];
+    const int64_t seg = blockIdx.x;
+    const int64_t y = seg / segs_x;
+    const int x = (int)(seg - y * segs_x) * kLitSeg + (int)threadIdx.x;
+    const bool on = x < width && lit[y * stride + x] != 0;
+    const uint64_t b = __ballot(on);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) wc[w] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t base = offs[seg];
+    for (int k = 0; k < w; ++k) base += wc[k];
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    if (on) list[base + below] = (uint32_t)(y * stride + x);
+}
+
 static int row_stride_of(int n_par)
 {
     int p = 1;
@@ -375,9 +477,10 @@ static int row_stride_of(int n_par)
 }
 
 struct BwdLayout {
-    size_t part_off, stage1_off, bytes;
+    size_t part_off, stage1_off, list_off, counts_off, offs_off, len_off, bytes;
     int stride;
-    int64_t rpb, n_blk;
+    int64_t rpb, n_blk, n_seg;
+    int32_t segs_x;
 };
 
 static BwdLayout bwd_layout(int32_t width, int32_t height, int n_par)
@@ -390,7 +493,13 @@ static BwdLayout bwd_layout(int32_t width, int32_t height, int n_par)
     L.n_blk = L.rpb > 0 ? (tiles + L.rpb - 1) / L.rpb : 0;
     L.part_off = (tile_order_bytes(width, height) + a - 1) / a * a;
     L.stage1_off = L.part_off + ((size_t)tiles * L.stride * 4 + a - 1) / a * a;
-    L.bytes = L.stage1_off + (size_t)L.n_blk * L.stride * 8;
+    L.segs_x = (width + kLitSeg - 1) / kLitSeg;
+    L.n_seg = (int64_t)L.segs_x * height;
+    L.list_off = L.stage1_off + ((size_t)L.n_blk * L.stride * 8 + a - 1) / a * a;
+    L.counts_off = L.list_off + ((size_t)width * height * 4 + a - 1) / a * a;
+    L.offs_off = L.counts_off + ((size_t)L.n_seg * 4 + a - 1) / a * a;
+    L.len_off = L.offs_off + ((size_t)L.n_seg * 4 + a - 1) / a * a;
+    L.bytes = L.len_off + a;
     return L;
 }
 
@@ -440,15 +549,33 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
     if (workspace_bytes < L.bytes) return GLINT_ESHAPE;
     if ((uintptr_t)workspace & 7u) return GLINT_EINVAL;
     const int tiles_x = (int)tiles_x_of(vw.width);
-    const int32_t *order = nullptr;
-    rc = enqueue_tile_order(vw, sh, workspace, L.part_off, &order, st);
-    if (rc) return rc;
     float *partials = (float *)((char *)workspace + L.part_off);
     double *stage1 = (double *)((char *)workspace + L.stage1_off);
-    hipLaunchKernelGGL(glint_bwd_kernel, dim3((unsigned)tiles), dim3(kWave), 0, st, vw, sh, grad_out_rgb, lit_lights,
-                       tiles_x, order, (int32_t)tiles, partials, n_par, L.stride);
+    const uint32_t *list = nullptr, *list_len = nullptr;
+    const int32_t *order = nullptr;
+    int64_t grid = tiles;
+    // list entries are y*stride + x in 32 bits
+    if (lit_lights && (int64_t)vw.height * vw.stride <= 0xffffffffLL) {
+        uint32_t *d_list = (uint32_t *)((char *)workspace + L.list_off);
+        uint32_t *d_counts = (uint32_t *)((char *)workspace + L.counts_off);
+        uint32_t *d_offs = (uint32_t *)((char *)workspace + L.offs_off);
+        uint32_t *d_len = (uint32_t *)((char *)workspace + L.len_off);
+        hipLaunchKernelGGL(glint_lit_count, dim3((unsigned)L.n_seg), dim3(kLitSeg), 0, st, lit_lights, vw.width,
+                           vw.stride, L.segs_x, d_counts);
+        hipLaunchKernelGGL(glint_lit_scan, dim3(1), dim3(kLitScan), 0, st, d_counts, L.n_seg, d_offs, d_len);
+        hipLaunchKernelGGL(glint_lit_scatter, dim3((unsigned)L.n_seg), dim3(kLitSeg), 0, st, lit_lights, vw.width,
+                           vw.stride, L.segs_x, d_offs, d_list);
+        list = d_list;
+        list_len = d_len;
+        grid = ((int64_t)vw.width * vw.height + kWave - 1) / kWave;   // chunks beyond the list exit at once
+    } else {
+        rc = enqueue_tile_order(vw, sh, workspace, L.part_off, &order, st);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(glint_bwd_kernel, dim3((unsigned)grid), dim3(kWave), 0, st, vw, sh, grad_out_rgb, lit_lights,
+                       list, list_len, tiles_x, order, (int32_t)tiles, partials, n_par, L.stride);
     hipLaunchKernelGGL(glint_bwd_reduce1, dim3((unsigned)L.n_blk), dim3(kReduceThreads), 0, st, partials, tiles,
-                       L.stride, L.rpb, stage1);
+                       list_len, L.stride, L.rpb, stage1);
     hipLaunchKernelGGL(glint_bwd_reduce2, dim3(1), dim3(kReduceThreads), 0, st, stage1, (int)L.n_blk, L.stride,
                        n_mat, n_par, grad_alpha, grad_ln_density, grad_light_dir);
     hipError_t e = hipGetLastError();

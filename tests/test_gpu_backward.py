@@ -149,11 +149,9 @@ def test_lit_mask_matches_oracle(glint, case):
 
 @pytest.mark.parametrize("case", range(4))
 def test_backward_with_lit_mask_matches_full_adjoint(glint, case):
-    """The adjoint that skips the pixels and lights the forward found without an
-    open gate adds the same terms as the full adjoint: the per-material sums run
-    in the same order (bit for bit); the light sums, reduced per 64-item batch,
-    group the terms differently once unlit pixels no longer take batch slots
-    (equal within FP32 rounding)."""
+    """The adjoint that shades only the lit pixels (gathered into full waves) and
+    their lit lights adds the same terms as the full adjoint, grouped into other
+    waves and partial rows: equal within FP32 rounding, and deterministic."""
     label, make = _lit_cases()[case]
     gb, mats, lights = make()
     dgb = glint.to_device(gb)
@@ -163,12 +161,30 @@ def test_backward_with_lit_mask_matches_full_adjoint(glint, case):
     fast = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit)
     torch.cuda.synchronize()
     print(f"  {label}: grad alpha {full[0].cpu().numpy()}", flush=True)
-    assert torch.equal(full[0], fast[0]) and torch.equal(full[1], fast[1])
-    d0, d1 = full[2].double(), fast[2].double()
-    assert float((d0 - d1).abs().max()) <= 1e-5 * float(d0.abs().max()) + 1e-30
+    for a, b in zip(full, fast):
+        a, b = a.double(), b.double()
+        assert float((a - b).abs().max()) <= 1e-5 * float(a.abs().max()) + 1e-30
     assert float(full[0].abs().sum()) > 0.0
     # the masked adjoint is deterministic too
     again = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit)
     torch.cuda.synchronize()
     for x, y in zip(fast, again):
         assert torch.equal(x, y)
+
+
+def test_backward_with_empty_lit_mask_is_zero(glint):
+    """A mask with no lit pixel leaves nothing to differentiate: zero gradients."""
+    gb, mats, lights = scenes.four_k(300, 7, seed=12, n_light=2, n_mat=2)
+    dgb = glint.to_device(gb)
+    lit = torch.zeros(gb["u"].shape, dtype=torch.int16, device="cuda")
+    go = torch.ones((3,) + gb["u"].shape, device="cuda")
+    ga, gn, gd = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit)
+    torch.cuda.synchronize()
+    assert float(ga.abs().sum()) == 0.0 and float(gn.abs().sum()) == 0.0 and float(gd.abs().sum()) == 0.0
+    full = glint.glint_shade_backward(dgb, mats, lights, go)
+    _, lit2 = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
+    fast = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit2)
+    torch.cuda.synchronize()
+    for a, b in zip(full, fast):
+        a, b = a.double(), b.double()
+        assert float((a - b).abs().max()) <= 1e-5 * float(a.abs().max()) + 1e-30
