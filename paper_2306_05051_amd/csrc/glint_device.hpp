@@ -49,6 +49,22 @@ struct Shared {
     uint32_t rng_mask;        // 2^b - 1
 };
 
+// The pixel that owns item q of a tile: the last p in 0..63 with off[p] <= q,
+// for the non-decreasing item offsets off[] of the tile's pixels (off[0] = 0).
+// Two rounds of independent LDS reads (the 8-pixel block, then the pixel in
+// it) instead of a six-step chain of dependent ones.
+__device__ __forceinline__ int item_pixel(const int *off, int q)
+{
+    int c = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) c += (off[8 * k] <= q) ? 1 : 0;
+    const int b = 8 * c;
+    int p = b;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) p += (off[b + i] <= q) ? 1 : 0;
+    return p;
+}
+
 struct ViewDesc {
     int32_t width, height;
     int64_t stride;

@@ -264,10 +264,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     for (int base = 0; base < S; base += kWave) {
         const int q = base + lane;
         if (q < S) {
-            int p = 0;
-#pragma unroll
-            for (int st = 32; st > 0; st >>= 1)
-                if (sm.off[p + st] <= q) p += st;
+            const int p = item_pixel(sm.off, q);
             const int kp = q - sm.off[p];
             const int64_t pidx = (int64_t)(y0 + (p >> lw)) * vw.stride + (x0 + (p & tmask));
             double n[3], wi[3];
