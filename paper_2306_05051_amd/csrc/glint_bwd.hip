@@ -396,31 +396,67 @@ static int64_t bwd_tiles(int32_t width, int32_t height)
 
 // ---------------------------------------------------------------------------
 // Lit-pixel list for the adjoint: the pixels whose lit mask is non-zero, in
-// raster order.  Segments of kLitSeg pixels of one row, in raster order:
+// raster order.  A segment is kLitSeg pixels of one row (the last one of a
+// row shorter); segments are numbered in raster order.  A workgroup of
+// kLitThreads threads handles one segment, each thread kLitPer consecutive
+// pixels.
 //   count:   lit pixels per segment
 //   scan:    one workgroup turns the counts into offsets and the list length
+//            (each thread a contiguous run of segments, loads issued 8 at a
+//            time)
 //   scatter: each segment writes its lit pixels' indices y*stride + x
 // ---------------------------------------------------------------------------
-constexpr int kLitSeg = 256;
+constexpr int kLitThreads = 256;
+constexpr int kLitPer = 4;
+constexpr int kLitSeg = kLitThreads * kLitPer;
 constexpr int kLitScan = 1024;
 
-__global__ __launch_bounds__(kLitSeg) void glint_lit_count(const uint16_t *__restrict__ lit, int32_t width,
-                                                           int64_t stride, int32_t segs_x,
-                                                           uint32_t *__restrict__ counts)
+// this thread's lit flags (bit i: pixel x0 + i) in segment seg
+__device__ __forceinline__ uint32_t lit_flags(const uint16_t *__restrict__ lit, int32_t width, int64_t stride,
+                                              int32_t segs_x, int64_t seg, int64_t &y, int &x0)
 {
-    __shared__ uint32_t wc[kLitSeg / kWave];
-    const int64_t seg = blockIdx.x;
-    const int64_t y = seg / segs_x;
-    const int x = (int)(seg - y * segs_x) * kLitSeg + (int)threadIdx.x;
-    const bool on = x < width && lit[y * stride + x] != 0;
-    const uint64_t b = __ballot(on);
-    if ((threadIdx.x & (kWave - 1)) == 0) wc[threadIdx.x / kWave] = (uint32_t)__popcll(b);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < kLitSeg / kWave; ++w) t += wc[w];
-        counts[seg] = t;
+    y = seg / segs_x;
+    x0 = (int)(seg - y * segs_x) * kLitSeg + (int)threadIdx.x * kLitPer;
+    uint32_t f = 0u;
+#pragma unroll
+    for (int i = 0; i < kLitPer; ++i)
+        if (x0 + i < width && lit[y * stride + x0 + i] != 0) f |= 1u << i;
+    return f;
+}
+
+// exclusive prefix of v over the workgroup's threads (in thread order) and the total
+__device__ __forceinline__ uint32_t block_prefix(uint32_t v, uint32_t &total)
+{
+    __shared__ uint32_t wsum[kLitThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
     }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < kLitThreads / kWave; ++k) {
+        before += k < w ? wsum[k] : 0u;
+        total += wsum[k];
+    }
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(kLitThreads) void glint_lit_count(const uint16_t *__restrict__ lit, int32_t width,
+                                                               int64_t stride, int32_t segs_x,
+                                                               uint32_t *__restrict__ counts)
+{
+    int64_t y;
+    int x0;
+    const uint32_t f = lit_flags(lit, width, stride, segs_x, blockIdx.x, y, x0);
+    uint32_t total;
+    block_prefix((uint32_t)__popc(f), total);
+    if (threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(kLitScan) void glint_lit_scan(const uint32_t *__restrict__ counts, int64_t n,
@@ -432,7 +468,15 @@ __global__ __launch_bounds__(kLitScan) void glint_lit_scan(const uint32_t *__res
     const int64_t b0 = (int64_t)t * per < n ? (int64_t)t * per : n;
     const int64_t b1 = b0 + per < n ? b0 + per : n;
     uint32_t own = 0;
-    for (int64_t i = b0; i < b1; ++i) own += counts[i];
+    int64_t i = b0;
+    for (; i + 8 <= b1; i += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = counts[i + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) own += v[k];
+    }
+    for (; i < b1; ++i) own += counts[i];
     ws[t] = own;
     __syncthreads();
     for (int d = 1; d < kLitScan; d <<= 1) {        // inclusive scan of the per-thread sums
@@ -442,31 +486,37 @@ __global__ __launch_bounds__(kLitScan) void glint_lit_scan(const uint32_t *__res
         __syncthreads();
     }
     uint32_t run = ws[t] - own;
-    for (int64_t i = b0; i < b1; ++i) {
+    i = b0;
+    for (; i + 8 <= b1; i += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = counts[i + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            offs[i + k] = run;
+            run += v[k];
+        }
+    }
+    for (; i < b1; ++i) {
         offs[i] = run;
         run += counts[i];
     }
     if (t == kLitScan - 1) len[0] = ws[t];
 }
 
-__global__ __launch_bounds__(kLitSeg) void glint_lit_scatter(const uint16_t *__restrict__ lit, int32_t width,
-                                                             int64_t stride, int32_t segs_x,
-                                                             const uint32_t *__restrict__ offs,
-                                                             uint32_t *__restrict__ list)
+__global__ __launch_bounds__(kLitThreads) void glint_lit_scatter(const uint16_t *__restrict__ lit, int32_t width,
+                                                                 int64_t stride, int32_t segs_x,
+                                                                 const uint32_t *__restrict__ offs,
+                                                                 uint32_t *__restrict__ list)
 {
-    __shared__ uint32_t wc[kLitSeg / kWave];
-    const int64_t seg = blockIdx.x;
-    const int64_t y = seg / segs_x;
-    const int x = (int)(seg - y * segs_x) * kLitSeg + (int)threadIdx.x;
-    const bool on = x < width && lit[y * stride + x] != 0;
-    const uint64_t b = __ballot(on);
-    const int w = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0) wc[w] = (uint32_t)__popcll(b);
-    __syncthreads();
-    uint32_t base = offs[seg];
-    for (int k = 0; k < w; ++k) base += wc[k];
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-    if (on) list[base + below] = (uint32_t)(y * stride + x);
+    int64_t y;
+    int x0;
+    const uint32_t f = lit_flags(lit, width, stride, segs_x, blockIdx.x, y, x0);
+    uint32_t total;
+    uint32_t pos = offs[blockIdx.x] + block_prefix((uint32_t)__popc(f), total);
+#pragma unroll
+    for (int i = 0; i < kLitPer; ++i)
+        if (f & (1u << i)) list[pos++] = (uint32_t)(y * stride + x0 + i);
 }
 
 static int row_stride_of(int n_par)
@@ -560,11 +610,11 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
         uint32_t *d_counts = (uint32_t *)((char *)workspace + L.counts_off);
         uint32_t *d_offs = (uint32_t *)((char *)workspace + L.offs_off);
         uint32_t *d_len = (uint32_t *)((char *)workspace + L.len_off);
-        hipLaunchKernelGGL(glint_lit_count, dim3((unsigned)L.n_seg), dim3(kLitSeg), 0, st, lit_lights, vw.width,
-                           vw.stride, L.segs_x, d_counts);
+        hipLaunchKernelGGL(glint_lit_count, dim3((unsigned)L.n_seg), dim3(kLitThreads), 0, st, lit_lights,
+                           vw.width, vw.stride, L.segs_x, d_counts);
         hipLaunchKernelGGL(glint_lit_scan, dim3(1), dim3(kLitScan), 0, st, d_counts, L.n_seg, d_offs, d_len);
-        hipLaunchKernelGGL(glint_lit_scatter, dim3((unsigned)L.n_seg), dim3(kLitSeg), 0, st, lit_lights, vw.width,
-                           vw.stride, L.segs_x, d_offs, d_list);
+        hipLaunchKernelGGL(glint_lit_scatter, dim3((unsigned)L.n_seg), dim3(kLitThreads), 0, st, lit_lights,
+                           vw.width, vw.stride, L.segs_x, d_offs, d_list);
         list = d_list;
         list_len = d_len;
         grid = ((int64_t)vw.width * vw.height + kWave - 1) / kWave;   // chunks beyond the list exit at once

@@ -120,10 +120,11 @@ def _lit_cases():
     return [("backward 128x96", lambda: scenes.backward_scene(128, 96, seed=7)[:3]),
             ("4k-like 3 lights", lambda: scenes.four_k(96, 64, seed=9, n_light=3, n_mat=4)),
             ("4k-like 16 lights", lambda: scenes.four_k(64, 40, seed=11, n_light=16, n_mat=5)),
-            ("paper plane25", lambda: scenes.paper_setting(160, 90, view="plane25", log10_density=6.0, seed=3))]
+            ("paper plane25", lambda: scenes.paper_setting(160, 90, view="plane25", log10_density=6.0, seed=3)),
+            ("wide rows", lambda: scenes.four_k(2100, 12, seed=13, n_light=2, n_mat=3))]
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(5))
 def test_lit_mask_matches_oracle(glint, case):
     """glint_shade_lit: radiance identical to glint_shade, and per pixel the set
     of lights with an open gate equals the oracle's on every compared pixel."""
@@ -147,7 +148,7 @@ def test_lit_mask_matches_oracle(glint, case):
           f"{int(np.unpackbits(g.view(np.uint8)).sum())} lit pixel-lights", flush=True)
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(5))
 def test_backward_with_lit_mask_matches_full_adjoint(glint, case):
     """The adjoint that shades only the lit pixels (gathered into full waves) and
     their lit lights adds the same terms as the full adjoint, grouped into other
