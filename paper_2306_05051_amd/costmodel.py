@@ -49,8 +49,9 @@ keys and gates):
   item (one pixel, probe): probe centre 32, FP64 tangent frame 38, <n,wi>,
       <wi,t>, <wi,b> 18, 4 x (key unpack 5, trig table index 3, rotation 8,
       anisotropic scales 14, lattice shear/floor/fractions 18, triangle 2,
-      vertex selects 6, barycentrics 10, node hash 9, 6 texel-key hashes 54)
-      = 4 x 129 = 516, probe sum 3 = 607
+      vertex selects 6, barycentrics 10, node hash 9, texel keys H(H(node, i),
+      j) of the three vertices, which span two lattice columns: 2 + 3 hashes
+      45 and the column select 2) = 4 x 122 = 488, probe sum 3 = 579
   pixel: density 5, FP64 normalisation of n and w 84, footprint moments 24,
       <n,wi> 6, eigenvalue and ratio 60, atan2 80, sigma0 times the major-axis
       eigenvector 74, probe split 50, area level 6, ratio/orientation cell,
@@ -79,7 +80,7 @@ COST = {
     "item_light": 8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 50 + 21 + 4 * 28 + 4 * (3 + HASH),
     "item_light_lit": 13 + 20 + 13,
     "item": (8 + FP64_RCP + 8) + (22 + FP64_RCP) + 18
-            + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + HASH + 6 * HASH) + 3,
+            + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + HASH + 5 * HASH + 2) + 3,
     "pixel": (5 + 2 * (12 + FP64_RSQ + 6) + 24 + 6 + (12 + FP64_SQRT + 2 + FP64_DIV + 2) + 80
               + (26 + 2 * FP64_RSQ) + (8 + 2 * FP64_DIV + 2) + 6 + 180 + 56),
 }

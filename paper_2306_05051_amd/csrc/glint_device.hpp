@@ -714,9 +714,14 @@ __device__ __forceinline__ void probe_texels(const PixelRec &R, double u, double
         float beta[3];
         simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta);
         const uint32_t base = hstep(M.root, w);
+        // vertex keys H(H(base, i), j): the triangle's vertices span two
+        // columns i0 = vi[0] and i0 + 1 = vi[2], so two inner steps serve all three
+        const uint32_t h0 = hstep(base, (uint32_t)vi[0]), h1 = hstep(base, (uint32_t)vi[2]);
+        pre[g][0] = hstep(h0, (uint32_t)vj[0]);
+        pre[g][1] = hstep(vi[1] == vi[0] ? h0 : h1, (uint32_t)vj[1]);
+        pre[g][2] = hstep(h1, (uint32_t)vj[2]);
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
-            pre[g][e] = hstep(hstep(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
             sm.pre[g * 3 + e][lane] = pre[g][e];
             sm.beta[g * 3 + e][lane] = beta[e];
             if (key_sum && g < nn) *key_sum += pre[g][e];
