@@ -138,7 +138,9 @@ typedef struct {
 
 /* Launch configuration of the batched path (autotuner output).
  * tile_w x tile_h pixels per work unit (tile_w*tile_h == 64 * waves);
- * blocks_per_cu: persistent workgroups per compute unit. */
+ * blocks_per_cu in [1, 64]: persistent workgroups per compute unit that pop
+ * chunks of tiles from a counter; 0: one workgroup per tile (the grid covers
+ * the whole tile table, each workgroup finds its view by binary search). */
 typedef struct {
     int32_t tile_w, tile_h, blocks_per_cu, reserved;
 } glint_tune;
@@ -250,13 +252,14 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
                          float *grad_ln_density, float *grad_light_dir, void *workspace,
                          size_t workspace_bytes, void *stream);
 
-/* Batched shading of many views of uneven size in one persistent launch.
+/* Batched shading of many views of uneven size in one launch.
  * glint_plan_create copies the view descriptors (device pointers inside
  * gbufs/out_rgb stay owned by the caller and must outlive the plan), the
  * materials, lights and params, builds the tile table on the device, and
- * (tune may be NULL: 32 x 2 tiles, 32 persistent workgroups per compute
- * unit) fixes the launch shape.
- * glint_shade_batched enqueues [counter reset kernel, persistent kernel] on
+ * (tune may be NULL: 32 x 2 tiles, one workgroup per tile) fixes the launch
+ * shape.
+ * glint_shade_batched enqueues [counter reset kernel, persistent kernel]
+ * (or, with blocks_per_cu = 0, one kernel with a workgroup per tile) on
  * `stream`; with use_graph != 0 it captures them once into a hipGraph and
  * replays the graph afterwards.  Each view's output is bit-identical to
  * glint_shade on that view.  The plan must not be used by two streams at
@@ -267,7 +270,7 @@ int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t
                       glint_plan **plan);
 int glint_shade_batched(glint_plan *plan, int32_t use_graph, void *stream);
 int glint_plan_destroy(glint_plan *plan);
-/* number of tiles and of persistent workgroups of a plan (for reports) */
+/* number of tiles and of workgroups of a plan (for reports) */
 int glint_plan_info(const glint_plan *plan, int64_t *n_tiles, int32_t *n_blocks);
 
 /* The per-texel random numbers, for bit-exact checks: keys is a device array

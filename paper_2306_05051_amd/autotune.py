@@ -1,10 +1,10 @@
-"""Autotuner for the batched persistent path (glint_shade_batched).
+"""Autotuner for the batched path (glint_shade_batched).
 
 Times every candidate launch shape on the actual views with HIP events and
 returns the fastest: tile shape (tile_w x tile_h = 64 pixels per wave) and
-persistent workgroups per compute unit.  Outputs do not depend on the shape
-(each pixel's arithmetic and summation order are fixed), so tuning never
-changes the image.
+persistent workgroups per compute unit, or one workgroup per tile.  Outputs
+do not depend on the shape (each pixel's arithmetic and summation order are
+fixed), so tuning never changes the image.
 """
 from __future__ import annotations
 
@@ -15,7 +15,7 @@ import torch
 from . import glint
 
 TILES = ((8, 8), (16, 4), (32, 2), (64, 1))
-BLOCKS_PER_CU = (4, 8, 16, 32)
+BLOCKS_PER_CU = (0, 4, 8, 16, 32)      # 0: one workgroup per tile instead of persistent workgroups
 
 
 def autotune(gbufs, outs, materials, lights, tiles=TILES, blocks_per_cu=BLOCKS_PER_CU, reps=2,

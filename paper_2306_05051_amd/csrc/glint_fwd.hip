@@ -666,6 +666,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void gl
 
 __global__ void glint_reset_counter(unsigned int *counter) { *counter = 0u; }
 
+// The same tile table with one workgroup per tile (non-persistent): workgroup
+// t finds its view by binary search over the tile prefix and shades that
+// view's tile, within the single-view kernel's register budget.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void glint_batched_grid_kernel(
+    const ViewDesc *__restrict__ views, const int32_t *__restrict__ tile_start, int n_views, int32_t n_tiles,
+    int lw, const Shared *__restrict__ shp)
+{
+    __shared__ TileSmem<false> sm;
+    const int t = (int)blockIdx.x;
+    if (t >= n_tiles) return;
+    int lo = 0, hi = n_views;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_start[mid] <= t) lo = mid; else hi = mid;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const ViewDesc vw = uniform_view(views[lo]);
+    const int local = uni32(t - tile_start[lo]);
+    const int tiles_x = (vw.width + (1 << lw) - 1) >> lw;
+    const int tx = local % tiles_x, ty = local / tiles_x;
+    DebugPlanes dp = {};
+    shade_tile<false>(vw, *shp, dp, tx << lw, ty << (6 - lw), lw, sm);
+}
+
 // bit-exactness utilities ----------------------------------------------------
 __global__ void glint_texel_hash_kernel(const int32_t *keys, int64_t n, uint32_t *out)
 {
@@ -712,6 +736,7 @@ struct glint_plan {
     int tile_w = 8;
     int chunk = 4;
     int n_blocks = 0;
+    bool per_tile = false;     // one workgroup per tile instead of persistent workgroups
     Shared sh;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -864,10 +889,10 @@ int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t
     if (!P) return GLINT_ENOMEM;
     int rc = prepare_shared(mats, n_mat, lights, n_light, params, P->sh);
     if (rc) { delete P; return rc; }
-    P->tile_w = kTileW;                          // defaults: the library's tile shape, 32 workgroups per CU
-    int bpc = 32;
+    P->tile_w = kTileW;                          // defaults: the library's tile shape, a workgroup per tile
+    int bpc = 0;
     if (tune) {
-        if (!valid_tile_w(tune->tile_w) || tune->tile_w * tune->tile_h != kWave || tune->blocks_per_cu < 1 ||
+        if (!valid_tile_w(tune->tile_w) || tune->tile_w * tune->tile_h != kWave || tune->blocks_per_cu < 0 ||
             tune->blocks_per_cu > 64) {
             delete P;
             return GLINT_EINVAL;
@@ -895,6 +920,10 @@ int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t
     if (e != hipSuccess) { delete P; return set_hip_error(e); }
     int64_t want = (int64_t)n_cu * bpc;
     P->n_blocks = (int)(want < 1 ? 1 : want);
+    if (bpc == 0) {
+        P->per_tile = true;
+        P->n_blocks = (int)total;
+    }
     // chunks of tiles per pop: about 16 pops per workgroup, at most 16 tiles
     int64_t per = total / ((int64_t)P->n_blocks * 16);
     P->chunk = (int)(per < 1 ? 1 : (per > 16 ? 16 : per));
@@ -916,6 +945,12 @@ int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t
 
 static int enqueue_batched(glint_plan *P, hipStream_t st)
 {
+    if (P->per_tile) {
+        hipLaunchKernelGGL(glint_batched_grid_kernel, dim3((unsigned)P->n_tiles), dim3(kWave), 0, st, P->d_views,
+                           P->d_tile_start, P->n_views, (int32_t)P->n_tiles, log2_tile(P->tile_w), P->d_sh);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+    }
     hipLaunchKernelGGL(glint_reset_counter, dim3(1), dim3(1), 0, st, P->d_counter);
     hipLaunchKernelGGL(glint_batched_kernel, dim3((unsigned)P->n_blocks), dim3(kWave), 0, st, P->d_views,
                        P->d_tile_start, P->n_views, (int32_t)P->n_tiles, log2_tile(P->tile_w), P->chunk,

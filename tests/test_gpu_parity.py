@@ -279,11 +279,16 @@ def test_batched_bit_identical_to_per_view(glint):
         torch.cuda.synchronize()
         for a, b in zip(ref, outs):
             assert torch.equal(a, b)
-    for tune in ((16, 4, 2), (64, 1, 4), (32, 2, 1)):
+    # persistent workgroups, and one workgroup per tile (blocks_per_cu = 0),
+    # eager and replayed from a graph
+    for tune in ((16, 4, 2), (64, 1, 4), (32, 2, 1), (32, 2, 0), (8, 8, 0)):
         p2 = glint.GlintPlan(dviews, outs, mats, lights, tune=tune)
-        p2.run(use_graph=False)
-        torch.cuda.synchronize()
-        for a, b in zip(ref, outs):
-            assert torch.equal(a, b)
+        for use_graph in (False, True, True):
+            for o in outs:
+                o.fill_(-1.0)
+            p2.run(use_graph=use_graph)
+            torch.cuda.synchronize()
+            for a, b in zip(ref, outs):
+                assert torch.equal(a, b)
         p2.close()
     plan.close()
