@@ -203,8 +203,9 @@ def main():
                           dtype=torch.uint8, device="cuda")
         gbn = {k: v for k, v in dgb.items() if k not in ("alpha_px", "log10_density_px")}
         lit = torch.empty((H, W), dtype=torch.int16, device="cuda")
-        glint.glint_shade_lit(gbn, mats, lights, out=out, lit=lit, rounding=1, workspace=ws)
-        glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb, lit=lit)
+        probes = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        glint.glint_shade_lit(gbn, mats, lights, out=out, lit=lit, probes=probes, rounding=1, workspace=ws)
+        glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb, lit=lit, probes=probes)
         glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb)
         torch.cuda.synchronize()
         n_fb = max(3, args.steps // 2)
@@ -213,9 +214,9 @@ def main():
             s0 = torch.cuda.Event(enable_timing=True); s1 = torch.cuda.Event(enable_timing=True)
             s0.record(stream)
             for _ in range(n_fb):
-                if use_lit:     # the forward records which lights opened a gate; the adjoint skips the rest
-                    glint.glint_shade_lit(gbn, mats, lights, out=out, lit=lit, rounding=1, workspace=ws)
-                    glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb, lit=lit)
+                if use_lit:     # the forward records which lights and probes opened a gate; the adjoint skips the rest
+                    glint.glint_shade_lit(gbn, mats, lights, out=out, lit=lit, probes=probes, rounding=1, workspace=ws)
+                    glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb, lit=lit, probes=probes)
                 else:           # the adjoint re-evaluates every gate
                     glint.glint_shade(gbn, mats, lights, out=out, rounding=1, workspace=ws)
                     glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb)

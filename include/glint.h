@@ -174,17 +174,20 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
                 float *out_rgb, const glint_debug *dbg, void *workspace, size_t workspace_bytes,
                 void *stream);
 
-/* glint_shade that also records, for the adjoint, which lights opened at
- * least one gate (Eq. 18) in each pixel: bit l of lit_lights[y*stride + x]
- * is set iff some gate of light l opened in some probe of the pixel (0 for
- * pixels that are not shaded).  The radiance equals glint_shade's bit for
- * bit.  lit_lights: device memory of height*stride uint16 values, 2-byte
- * aligned, owned by the caller, overwritten.  Errors as glint_shade, plus
- * ENULL (lit_lights), EINVAL (misaligned lit_lights). */
+/* glint_shade that also records, for the adjoint, which lights and which
+ * probes opened at least one gate (Eq. 18) in each pixel: bit l of
+ * lit_lights[y*stride + x] is set iff some gate of light l opened in some
+ * probe of the pixel; bit k of lit_probes[y*stride + x] iff some gate opened
+ * in probe k (bit 31: in probe 31 or a later one); both 0 for pixels that
+ * are not shaded.  The radiance equals glint_shade's bit for bit.
+ * lit_lights: device memory of height*stride uint16 values, 2-byte aligned;
+ * lit_probes (nullable): height*stride uint32 values, 4-byte aligned; both
+ * owned by the caller, overwritten.  Errors as glint_shade, plus ENULL
+ * (lit_lights), EINVAL (misaligned lit_lights or lit_probes). */
 int glint_shade_lit(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                     const glint_light *lights, int32_t n_light, const glint_params *params,
-                    float *out_rgb, uint16_t *lit_lights, void *workspace, size_t workspace_bytes,
-                    void *stream);
+                    float *out_rgb, uint16_t *lit_lights, uint32_t *lit_probes, void *workspace,
+                    size_t workspace_bytes, void *stream);
 
 /* Random-number table for glint_shade_rng_table (Sec. 6.3: the two uniforms
  * of a gated binomial may be read from a small texture of random numbers
@@ -236,8 +239,11 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * order, partial rows, FP64 reduction stage, lit-pixel list).  Without a
  * mask, tiles run heaviest first; the sums are reduced in a fixed order over
  * tiles, so the result does not depend on the schedule.
- * lit_lights (nullable): the mask glint_shade_lit wrote for the same
- * inputs with rounding 1 (relaxed; the gates do not depend on the rounding).
+ * lit_lights, lit_probes (nullable): the masks glint_shade_lit wrote for
+ * the same inputs with rounding 1 (relaxed; the gates do not depend on the
+ * rounding).  lit_probes is used only with lit_lights: then only the probes
+ * of a pixel whose bit is set are shaded (pixels with more than 31 probes
+ * shade all of theirs).
  * Every gradient term of a light is proportional to its distributed count,
  * which is zero when none of its gates opened, so only the pixels with a
  * non-zero mask are shaded (gathered in raster order into waves of 64 lit
@@ -245,12 +251,13 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * with a set bit: a fraction of the work, the same terms summed in another
  * grouping (equal within FP32 rounding to the call without the mask;
  * deterministic).  NULL evaluates every gate of every pixel.  Errors as glint_shade, plus ENULL (workspace,
- * gradient outputs), EINVAL (misaligned workspace or lit_lights). */
+ * gradient outputs), EINVAL (misaligned workspace, lit_lights or lit_probes). */
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                          const glint_light *lights, int32_t n_light, const glint_params *params,
-                         const float *grad_out_rgb, const uint16_t *lit_lights, float *grad_alpha,
-                         float *grad_ln_density, float *grad_light_dir, void *workspace,
-                         size_t workspace_bytes, void *stream);
+                         const float *grad_out_rgb, const uint16_t *lit_lights,
+                         const uint32_t *lit_probes, float *grad_alpha, float *grad_ln_density,
+                         float *grad_light_dir, void *workspace, size_t workspace_bytes,
+                         void *stream);
 
 /* Batched shading of many views of uneven size in one launch.
  * glint_plan_create copies the view descriptors (device pointers inside

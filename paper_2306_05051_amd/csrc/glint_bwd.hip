@@ -222,11 +222,30 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
 // below), so that the few lit pixels fill whole waves.  The partial row is
 // that of the tile, or of the chunk b.
 // lit (nullable): the forward's per-pixel mask of lights with an open gate;
-// only the lights of a pixel whose bit is set are evaluated.
+// only the lights of a pixel whose bit is set are evaluated.  lit_probes
+// (nullable): the forward's per-pixel mask of probes with an open gate (bit
+// 31: probe 31 or a later one); only those probes become items.
+
+// position of the j-th set bit (from 0) of m, which has more than j set bits
+__device__ __forceinline__ int nth_bit(uint32_t m, int j)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        const int c = __popc(m & ((1u << w) - 1u));
+        if (j >= c) {
+            j -= c;
+            m >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void glint_bwd_kernel(
-    ViewDesc vw, Shared sh, const float *gout, const uint16_t *__restrict__ lit, const uint32_t *__restrict__ list,
-    const uint32_t *__restrict__ list_len, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles,
-    float *partials, int n_par, int row_stride)
+    ViewDesc vw, Shared sh, const float *gout, const uint16_t *__restrict__ lit,
+    const uint32_t *__restrict__ lit_probes, const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_len,
+    int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles, float *partials, int n_par, int row_stride)
 {
     __shared__ BwdSmem sm;
     const int lane = threadIdx.x;
@@ -251,7 +270,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         idx = (int64_t)y * vw.stride + x;
     }
     const int64_t npx = (int64_t)vw.height * vw.stride;
-    int npr = 0;
+    int npr = 0;                               // items of this pixel
+    uint32_t pmask = 0xffffffffu;              // its probes that become items (all ones: every probe)
     {
         Pixel px;
         px.flags = 0;
@@ -260,6 +280,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         if (px.flags & F_SHADED) {
             npr = px.npr;
             sm.rec[lane] = make_rec(px, sh);
+            if (lit_probes && npr <= 31) {
+                pmask = lit_probes[idx] & ((1u << npr) - 1u);
+                npr = __popc(pmask);
+            }
         }
     }
     int incl = npr;
@@ -281,11 +305,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         for (int st = 32; st > 0; st >>= 1)
             if (sm.off[p + st] <= q) p += st;
         const int64_t pidx = __shfl(idx, p);     // the item's pixel (all lanes take part)
+        const uint32_t pm = __shfl(pmask, p);
         float g3[3] = {0.0f, 0.0f, 0.0f};
         uint32_t litm = 0u;
         double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, u = 0.0, v = 0.0;
         if (live) {
             kp = q - sm.off[p];
+            if (pm != 0xffffffffu) kp = nth_bit(pm, kp);
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             u = vw.u[pidx];
@@ -567,9 +593,9 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
 
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                          const glint_light *lights, int32_t n_light, const glint_params *params,
-                         const float *grad_out_rgb, const uint16_t *lit_lights, float *grad_alpha,
-                         float *grad_ln_density, float *grad_light_dir, void *workspace, size_t workspace_bytes,
-                         void *stream)
+                         const float *grad_out_rgb, const uint16_t *lit_lights, const uint32_t *lit_probes,
+                         float *grad_alpha, float *grad_ln_density, float *grad_light_dir, void *workspace,
+                         size_t workspace_bytes, void *stream)
 {
     if (!params) return GLINT_ENULL;
     glint_params prm = *params;
@@ -578,7 +604,8 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
     int rc = prepare_shared(mats, n_mat, lights, n_light, &prm, sh);
     if (rc) return rc;
     if (!grad_alpha || !grad_ln_density || (n_light > 0 && !grad_light_dir)) return GLINT_ENULL;
-    if ((reinterpret_cast<uintptr_t>(lit_lights) & 1u) != 0) return GLINT_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(lit_lights) & 1u) != 0 || (reinterpret_cast<uintptr_t>(lit_probes) & 3u) != 0)
+        return GLINT_EINVAL;
     ViewDesc vw;
     rc = make_view(gbuf, reinterpret_cast<float *>(const_cast<float *>(grad_out_rgb)), vw);
     if (rc) return rc;
@@ -623,7 +650,8 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
         if (rc) return rc;
     }
     hipLaunchKernelGGL(glint_bwd_kernel, dim3((unsigned)grid), dim3(kWave), 0, st, vw, sh, grad_out_rgb, lit_lights,
-                       list, list_len, tiles_x, order, (int32_t)tiles, partials, n_par, L.stride);
+                       lit_lights ? lit_probes : nullptr, list, list_len, tiles_x, order, (int32_t)tiles, partials,
+                       n_par, L.stride);
     hipLaunchKernelGGL(glint_bwd_reduce1, dim3((unsigned)L.n_blk), dim3(kReduceThreads), 0, st, partials, tiles,
                        list_len, L.stride, L.rpb, stage1);
     hipLaunchKernelGGL(glint_bwd_reduce2, dim3(1), dim3(kReduceThreads), 0, st, stage1, (int)L.n_blk, L.stride,

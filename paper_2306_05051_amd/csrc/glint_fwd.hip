@@ -219,7 +219,8 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 // ---------------------------------------------------------------------------
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false>
 __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
-                           int lw, TileSmem<DEBUG> &sm, const uint32_t *ltbl = nullptr, uint16_t *lit = nullptr)
+                           int lw, TileSmem<DEBUG> &sm, const uint32_t *ltbl = nullptr, uint16_t *lit = nullptr,
+                           uint32_t *lit_probes = nullptr)
 {
     const int lane = threadIdx.x;
     const int tmask = (1 << lw) - 1;
@@ -256,7 +257,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     sm.off[lane] = off;
     __syncthreads();
     float acc[3] = {0.0f, 0.0f, 0.0f};
-    uint32_t litacc = 0u;
+    uint32_t litacc = 0u, probeacc = 0u;
     uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0, dns = 0, dlt = 0;
     float db[kMaxLight];
     if (DEBUG)
@@ -300,7 +301,11 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                     acc[0] += __uint_as_float(sm.pre[0][i - base]);
                     acc[1] += __uint_as_float(sm.pre[1][i - base]);
                     acc[2] += __uint_as_float(sm.pre[2][i - base]);
-                    if (LIT) litacc |= sm.pre[3][i - base];
+                    if (LIT) {
+                        const uint32_t m = sm.pre[3][i - base];
+                        litacc |= m;
+                        probeacc |= m ? 1u << min(i - off, 31) : 0u;   // bit 31: probe 31 or a later one
+                    }
                 }
             }
         }
@@ -311,7 +316,10 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
         vw.out[idx] = acc[0];
         vw.out[npx + idx] = acc[1];
         vw.out[2 * npx + idx] = acc[2];
-        if (LIT) lit[idx] = (uint16_t)litacc;
+        if (LIT) {
+            lit[idx] = (uint16_t)litacc;
+            if (lit_probes) lit_probes[idx] = probeacc;
+        }
         if (DEBUG) {
             if (dp.flags) dp.flags[idx] = dflags;
             if (dp.n_probe) dp.n_probe[idx] = npr;
@@ -338,11 +346,13 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
 // the wave first copies the table (rng_mask + 1 words, a multiple of 4,
 // 16-byte aligned) into its dynamic LDS.
 // With LIT the kernel also writes, per pixel, the bit mask of the lights that
-// opened a gate in any of the pixel's probes (lit[y * stride + x]).
+// opened a gate in any of the pixel's probes (lit[y * stride + x]) and, if
+// lit_probes is given, the bit mask of the probes that opened one (bit k:
+// probe k, bit 31: probe 31 or a later one).
 template <bool DEBUG, int RNG = kRngHash, bool LIT = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 4))) void glint_fwd_kernel(
     ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles,
-    uint16_t *__restrict__ lit)
+    uint16_t *__restrict__ lit, uint32_t *__restrict__ lit_probes)
 {
     __shared__ TileSmem<DEBUG> sm;
     extern __shared__ uint4 glint_rng_lds[];
@@ -357,7 +367,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 
         __syncthreads();
         ltbl = reinterpret_cast<const uint32_t *>(glint_rng_lds);
     }
-    shade_tile<DEBUG, RNG == kRngHash, RNG, LIT>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, ltbl, lit);
+    shade_tile<DEBUG, RNG == kRngHash, RNG, LIT>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, ltbl, lit,
+                                                lit_probes);
 }
 
 // Random-number table: t[i] = H(seed, i) for i < n.
@@ -771,7 +782,7 @@ size_t glint_shade_workspace_bytes(int32_t width, int32_t height) { return tile_
 // launch of the shading kernel with the uniforms' source RNG.
 static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb, const glint_debug *dbg,
                           void *workspace, size_t workspace_bytes, int rng, size_t lds_bytes, uint16_t *lit,
-                          void *stream)
+                          uint32_t *lit_probes, void *stream)
 {
     ViewDesc vw;
     int rc = make_view(gbuf, out_rgb, vw);
@@ -794,24 +805,24 @@ static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb,
                           dbg->n_live_small, dbg->n_lit};
         if (rng == kRngHash)
             hipLaunchKernelGGL(glint_fwd_kernel<true>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
-                               (int32_t)nt, nullptr);
+                               (int32_t)nt, nullptr, nullptr);
         else
             hipLaunchKernelGGL((glint_fwd_kernel<true, kRngTable>), grid, block, 0, st, vw, sh, dp, kTileLw,
-                               tiles_x, order, (int32_t)nt, nullptr);
+                               tiles_x, order, (int32_t)nt, nullptr, nullptr);
     } else {
         DebugPlanes dp = {};
         if (rng == kRngHash && lit)
             hipLaunchKernelGGL((glint_fwd_kernel<false, kRngHash, true>), grid, block, 0, st, vw, sh, dp, kTileLw,
-                               tiles_x, order, (int32_t)nt, lit);
+                               tiles_x, order, (int32_t)nt, lit, lit_probes);
         else if (rng == kRngHash)
             hipLaunchKernelGGL(glint_fwd_kernel<false>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
-                               (int32_t)nt, nullptr);
+                               (int32_t)nt, nullptr, nullptr);
         else if (rng == kRngTable)
             hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTable>), grid, block, 0, st, vw, sh, dp, kTileLw,
-                               tiles_x, order, (int32_t)nt, nullptr);
+                               tiles_x, order, (int32_t)nt, nullptr, nullptr);
         else
             hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTableLds>), grid, block, (unsigned)lds_bytes, st, vw,
-                               sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr);
+                               sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);
@@ -826,19 +837,21 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
     Shared sh;
     int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
     if (rc) return rc;
-    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, kRngHash, 0, nullptr, stream);
+    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, kRngHash, 0, nullptr, nullptr, stream);
 }
 
 int glint_shade_lit(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat, const glint_light *lights,
                     int32_t n_light, const glint_params *params, float *out_rgb, uint16_t *lit_lights,
-                    void *workspace, size_t workspace_bytes, void *stream)
+                    uint32_t *lit_probes, void *workspace, size_t workspace_bytes, void *stream)
 {
     Shared sh;
     int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
     if (rc) return rc;
     if (!lit_lights) return GLINT_ENULL;
-    if ((reinterpret_cast<uintptr_t>(lit_lights) & 1u) != 0) return GLINT_EINVAL;
-    return launch_forward(gbuf, sh, out_rgb, nullptr, workspace, workspace_bytes, kRngHash, 0, lit_lights, stream);
+    if ((reinterpret_cast<uintptr_t>(lit_lights) & 1u) != 0 || (reinterpret_cast<uintptr_t>(lit_probes) & 3u) != 0)
+        return GLINT_EINVAL;
+    return launch_forward(gbuf, sh, out_rgb, nullptr, workspace, workspace_bytes, kRngHash, 0, lit_lights, lit_probes,
+                          stream);
 }
 
 int glint_rng_table_fill(uint32_t *table, int32_t log2_words, uint32_t seed, void *stream)
@@ -875,7 +888,8 @@ int glint_shade_rng_table(const glint_gbuffer *gbuf, const glint_material *mats,
     sh.rng_mask = log2_words >= 32 ? 0xFFFFFFFFu : ((1u << log2_words) - 1u);
     const int rng = placement == GLINT_RNG_LDS ? kRngTableLds : kRngTable;
     const size_t lds_bytes = placement == GLINT_RNG_LDS ? (size_t)4 << log2_words : 0;
-    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, rng, lds_bytes, nullptr, stream);
+    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, rng, lds_bytes, nullptr, nullptr,
+                          stream);
 }
 
 int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t n_views,

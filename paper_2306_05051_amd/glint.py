@@ -98,9 +98,9 @@ def lib():
         L.glint_backward_workspace_bytes.argtypes = [i32, i32, i32, i32]
         L.glint_backward_workspace_bytes.restype = C.c_size_t
         L.glint_shade_backward.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
-                                           C.POINTER(_Params), vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+                                           C.POINTER(_Params), vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.glint_shade_lit.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
-                                      C.POINTER(_Params), vp, vp, vp, C.c_size_t, vp]
+                                      C.POINTER(_Params), vp, vp, vp, vp, C.c_size_t, vp]
         L.glint_plan_create.argtypes = [C.POINTER(_GBuf), C.POINTER(vp), i32, C.POINTER(_Mat), i32,
                                         C.POINTER(_Light), i32, C.POINTER(_Params), C.POINTER(_Tune),
                                         C.POINTER(vp)]
@@ -273,9 +273,10 @@ def glint_backward_workspace_bytes(width, height, n_mat, n_light):
 
 
 def glint_shade_lit(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=1, out=None, lit=None,
-                    workspace=None, stream=None):
-    """(radiance [3, H, W], lit [H, W] int16): glint_shade that also records, per
-    pixel, the bit mask of the lights with an open gate, for glint_shade_backward."""
+                    probes=None, workspace=None, stream=None):
+    """(radiance [3, H, W], lit [H, W] int16, probes [H, W] int32): glint_shade that
+    also records, per pixel, the bit masks of the lights and of the probes with
+    an open gate, for glint_shade_backward."""
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
@@ -284,23 +285,26 @@ def glint_shade_lit(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=1
         out = torch.empty((3, H, W), dtype=torch.float32, device=dev)
     if lit is None:
         lit = torch.empty((H, W), dtype=torch.int16, device=dev)
+    if probes is None:
+        probes = torch.empty((H, W), dtype=torch.int32, device=dev)
     nbytes = L.glint_shade_workspace_bytes(W, H)
     if workspace is None or workspace is False:
         workspace = torch.empty(max(1, nbytes), dtype=torch.uint8, device=dev)
     st = L.glint_shade_lit(C.byref(g), make_materials(materials), len(materials), make_lights(lights),
                            len(lights), C.byref(make_params(k_max, n_probe_max, rounding)),
                            _dev_ptr(out, torch.float32, "out"), _dev_ptr(lit, torch.int16, "lit"),
+                           _dev_ptr(probes, torch.int32, "probes"),
                            _dev_ptr(workspace, torch.uint8, "workspace"), nbytes, _stream(stream))
     _check(st, "glint_shade_lit")
-    return out, lit
+    return out, lit, probes
 
 
 def glint_shade_backward(gbuf, materials, lights, grad_out, k_max=4, n_probe_max=21, workspace=None,
-                         stream=None, lit=None):
+                         stream=None, lit=None, probes=None):
     """(grad_alpha[n_mat], grad_ln_density[n_mat], grad_light_dir[n_light, 3]) of
-    sum(grad_out * L) for the relaxed forward.  lit: the int16 mask from
-    glint_shade_lit on the same inputs (skips lights and pixels without an
-    open gate; same result), or None to evaluate every gate."""
+    sum(grad_out * L) for the relaxed forward.  lit, probes: the masks from
+    glint_shade_lit on the same inputs (skip the pixels, lights and probes
+    without an open gate; the same terms), or None to evaluate every gate."""
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
@@ -316,6 +320,7 @@ def glint_shade_backward(gbuf, materials, lights, grad_out, k_max=4, n_probe_max
                                 C.byref(make_params(k_max, n_probe_max, 1)),
                                 _dev_ptr(grad_out.contiguous(), torch.float32, "grad_out"),
                                 None if lit is None else _dev_ptr(lit, torch.int16, "lit"),
+                                None if probes is None else _dev_ptr(probes, torch.int32, "probes"),
                                 ga.data_ptr(), gn.data_ptr(), gd.data_ptr(), workspace.data_ptr(),
                                 nbytes, _stream(stream))
     _check(st, "glint_shade_backward")

@@ -103,12 +103,15 @@ def test_host_validation_without_device(lib):
     assert L.glint_rng_table_fill(tbl, 33, 0, None) == glint.GLINT_EINVAL
     assert L.glint_rng_table_fill(C.c_void_p((1 << 20) + 8), 12, 0, None) == glint.GLINT_EINVAL
     # lit-light mask: NULL and misaligned planes
-    lit_args = lambda l: (C.byref(g), mats, 1, lts, 1, C.byref(prm), fake_out, l, None, 0, None)
-    assert L.glint_shade_lit(*lit_args(None)) == glint.GLINT_ENULL
-    assert L.glint_shade_lit(*lit_args(C.c_void_p(4097))) == glint.GLINT_EINVAL
+    lit_args = lambda l, pr: (C.byref(g), mats, 1, lts, 1, C.byref(prm), fake_out, l, pr, None, 0, None)
+    assert L.glint_shade_lit(*lit_args(None, None)) == glint.GLINT_ENULL
+    assert L.glint_shade_lit(*lit_args(C.c_void_p(4097), None)) == glint.GLINT_EINVAL
+    assert L.glint_shade_lit(*lit_args(C.c_void_p(4096), C.c_void_p(4098))) == glint.GLINT_EINVAL
     fake = C.c_void_p(1 << 16)
-    assert L.glint_shade_backward(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake, C.c_void_p(4097), fake, fake,
-                                  fake, fake, 1 << 20, None) == glint.GLINT_EINVAL
+    assert L.glint_shade_backward(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake, C.c_void_p(4097), None, fake,
+                                  fake, fake, fake, 1 << 20, None) == glint.GLINT_EINVAL
+    assert L.glint_shade_backward(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake, fake, C.c_void_p(4098), fake,
+                                  fake, fake, fake, 1 << 20, None) == glint.GLINT_EINVAL
     # utilities: negative sizes and NULL pointers
     assert L.glint_texel_hash(None, -1, None, None) == glint.GLINT_ESHAPE
     assert L.glint_texel_hash(None, 5, None, None) == glint.GLINT_ENULL

@@ -133,11 +133,16 @@ def test_lit_mask_matches_oracle(glint, case):
     gb, mats, lights = make()
     print(f"  {label}: {gb['u'].shape}, {len(lights)} lights", flush=True)
     dgb = glint.to_device(gb)
-    out, lit = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
-    ref = glint.glint_shade(dgb, mats, lights, rounding=1)
+    out, lit, probes = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
+    ref, gdbg = glint.glint_shade(dgb, mats, lights, rounding=1, debug=True)
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
     g = lit.cpu().numpy().view(np.uint16).astype(np.uint32)
+    # the probe mask: non-empty exactly where a light is lit, within the pixel's probes
+    pm = probes.cpu().numpy().view(np.uint32).astype(np.int64)
+    npr = gdbg["n_probe"].cpu().numpy().astype(np.int64)
+    assert np.array_equal(pm != 0, g != 0)
+    assert np.all(pm < (np.int64(1) << np.minimum(npr, 32)))
     _, d = oracle.shade(gb, mats, lights, rounding=1, debug=True)
     shaded = (d["flags"] & 1) > 0
     ok = shaded & (d["margin_pos"] >= MARGIN)
@@ -156,20 +161,22 @@ def test_backward_with_lit_mask_matches_full_adjoint(glint, case):
     label, make = _lit_cases()[case]
     gb, mats, lights = make()
     dgb = glint.to_device(gb)
-    _, lit = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
+    _, lit, probes = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
     go = torch.randn((3,) + gb["u"].shape, device="cuda", generator=torch.Generator("cuda").manual_seed(case))
     full = glint.glint_shade_backward(dgb, mats, lights, go)
     fast = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit)
+    fastest = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit, probes=probes)
     torch.cuda.synchronize()
     print(f"  {label}: grad alpha {full[0].cpu().numpy()}", flush=True)
-    for a, b in zip(full, fast):
-        a, b = a.double(), b.double()
-        assert float((a - b).abs().max()) <= 1e-5 * float(a.abs().max()) + 1e-30
+    for res in (fast, fastest):
+        for a, b in zip(full, res):
+            a, b = a.double(), b.double()
+            assert float((a - b).abs().max()) <= 1e-5 * float(a.abs().max()) + 1e-30
     assert float(full[0].abs().sum()) > 0.0
     # the masked adjoint is deterministic too
-    again = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit)
+    again = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit, probes=probes)
     torch.cuda.synchronize()
-    for x, y in zip(fast, again):
+    for x, y in zip(fastest, again):
         assert torch.equal(x, y)
 
 
@@ -183,8 +190,8 @@ def test_backward_with_empty_lit_mask_is_zero(glint):
     torch.cuda.synchronize()
     assert float(ga.abs().sum()) == 0.0 and float(gn.abs().sum()) == 0.0 and float(gd.abs().sum()) == 0.0
     full = glint.glint_shade_backward(dgb, mats, lights, go)
-    _, lit2 = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
-    fast = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit2)
+    _, lit2, probes2 = glint.glint_shade_lit(dgb, mats, lights, rounding=1)
+    fast = glint.glint_shade_backward(dgb, mats, lights, go, lit=lit2, probes=probes2)
     torch.cuda.synchronize()
     for a, b in zip(full, fast):
         a, b = a.double(), b.double()
