@@ -87,7 +87,7 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
             uint32_t K[4], anyK = 0u;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                K[g] = gate_threshold(gate_prob(R.ng[g], p, lp));
+                K[g] = gate_K(R.ng[g], p, lp);
                 if (g < nn) anyK |= K[g];
             }
             uint32_t mlo = 0u, mhi = 0u;
@@ -182,10 +182,12 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
             const float cn = sk * le.F * G * Bp * dp_dc2 * 2.0f * (float)le.ch;   // times n
             const float ct = sk * le.F * G * Bfx * inv_micro;                      // times t
             const float cb = sk * le.F * G * Bfy * inv_micro;                      // times b
+            double ta[3], ba[3];
+            frame_axes(n, fr, ta, ba);
             float gh[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                gh[c] = sk * dF * (float)wi[c] + cn * (float)n[c] + ct * (float)fr.t[c] + cb * (float)fr.b[c];
+                gh[c] = sk * dF * (float)wi[c] + cn * (float)n[c] + ct * (float)ta[c] + cb * (float)ba[c];
             // direct dependence on wo through Lambda(<n,wo>)
             const float gon = sk * le.F * B * (-G / (1.0f + le.lam_o)) * dlo_dc;
             // h = (wi + wo)/|wi + wo|, wo = d/|d|: chain through both normalisations

@@ -477,16 +477,6 @@ __device__ __forceinline__ void simplex_locate(double cx, double cy, int l, int 
     }
 }
 
-// Orthonormal basis around a unit normal (Duff et al., JCGT 6(1), 2017)
-__device__ __forceinline__ void onb(const double n[3], double t[3], double b[3])
-{
-    const double sgn = copysign(1.0, n[2]);
-    const double a = -rcp_d(sgn + n[2]);           // |sgn + n_z| >= 1
-    const double bb = n[0] * n[1] * a;
-    t[0] = 1.0 + sgn * n[0] * n[0] * a; t[1] = sgn * bb; t[2] = -sgn * n[0];
-    b[0] = bb; b[1] = sgn + n[1] * n[1] * a; b[2] = -n[1];
-}
-
 // v_rcp_f32 (1 ulp): the relative error of every quotient below stays ~1e-7
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -547,18 +537,40 @@ __device__ __forceinline__ float success_prob(int ndf, float alpha, float R, flo
     return clamped ? 1.0f : p;
 }
 
-// Per item: the tangent frame of n and the view's projections on it.
+// Per item: the tangent frame of n (Duff et al. 2017) in implicit form and
+// the view's projections on it.  With s = sign(n_z) and a = -1/(s + n_z) the
+// axes are t = (1 + s a nx^2, s a nx ny, -s nx) and b = (a nx ny, s + a ny^2,
+// -ny), so for any w, with d = a (nx wx + ny wy) - wz:
+//   <t, w> = wx + s nx d,   <b, w> = s wy + ny d.
 struct ViewFrame {
-    double t[3], b[3];         // Duff et al. ONB of n
+    double a, s, snx;          // a, s = sign(n_z), s n_x
     double cos_i, wt, wb;      // <n, wi>, <wi, t>, <wi, b>
 };
 
+// <t, w> and <b, w> from nw = nx wx + ny wy
+__device__ __forceinline__ void frame_dots(const double n[3], const ViewFrame &f, const double w[3], double nw,
+                                           double &tw, double &bw)
+{
+    const double d = f.a * nw - w[2];
+    tw = fma(f.snx, d, w[0]);
+    bw = fma(n[1], d, f.s * w[1]);
+}
+
+// the axes themselves (the adjoint's light-direction gradient)
+__device__ __forceinline__ void frame_axes(const double n[3], const ViewFrame &f, double t[3], double b[3])
+{
+    const double bb = n[0] * n[1] * f.a;
+    t[0] = 1.0 + f.snx * n[0] * f.a; t[1] = f.s * bb; t[2] = -f.snx;
+    b[0] = bb; b[1] = f.s + n[1] * n[1] * f.a; b[2] = -n[1];
+}
+
 __device__ __forceinline__ void view_frame(const double n[3], const double wi[3], ViewFrame &f)
 {
-    onb(n, f.t, f.b);
+    f.s = copysign(1.0, n[2]);
+    f.a = -rcp_d(f.s + n[2]);                      // |s + n_z| >= 1
+    f.snx = f.s * n[0];
     f.cos_i = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
-    f.wt = wi[0] * f.t[0] + wi[1] * f.t[1] + wi[2] * f.t[2];
-    f.wb = wi[0] * f.b[0] + wi[1] * f.b[1] + wi[2] * f.b[2];
+    frame_dots(n, f, wi, n[0] * wi[0] + n[1] * wi[1], f.wt, f.wb);
 }
 
 // Everything one light needs at one pixel (shared by the forward and the
@@ -581,7 +593,8 @@ __device__ __forceinline__ bool eval_light(const double n[3], const double wi[3]
                                            const DevMaterial &M, const ViewFrame &f, LightEval &e)
 {
     if (!L.ok) return false;
-    e.cos_o = n[0] * L.wo[0] + n[1] * L.wo[1] + n[2] * L.wo[2];
+    const double nw = n[0] * L.wo[0] + n[1] * L.wo[1];
+    e.cos_o = nw + n[2] * L.wo[2];
     if (!(e.cos_o > 0.0)) return false;
     const double wiwo = wi[0] * L.wo[0] + wi[1] * L.wo[1] + wi[2] * L.wo[2];
     e.wiwo = wiwo;
@@ -593,8 +606,10 @@ __device__ __forceinline__ bool eval_light(const double n[3], const double wi[3]
     e.p = success_prob(M.ndf, alpha, M.R, (float)(e.ch * e.ch), (float)(1.0 - e.ch * e.ch), e.pclamp);
     // angular grid over the projected half vector (Eq. 14)
     const double sc = ihl * M.inv_micro;
-    const double ax = (f.wt + (f.t[0] * L.wo[0] + f.t[1] * L.wo[1] + f.t[2] * L.wo[2])) * sc - 0.5;
-    const double ay = (f.wb + (f.b[0] * L.wo[0] + f.b[1] * L.wo[1] + f.b[2] * L.wo[2])) * sc - 0.5;
+    double tw, bw;
+    frame_dots(n, f, L.wo, nw, tw, bw);
+    const double ax = (f.wt + tw) * sc - 0.5;
+    const double ay = (f.wb + bw) * sc - 0.5;
     const double fax = floor(ax), fay = floor(ay);
     e.ai = (int)fax; e.aj = (int)fay;
     // bilinear fractions; both complements from FP64 so small weights stay accurate
@@ -612,39 +627,19 @@ __device__ __forceinline__ void light_brdf(const DevMaterial &M, float alpha, Li
     e.lam_o = smith_lambda(M.ndf, alpha, (float)e.cos_o, (float)(1.0 - e.cos_o * e.cos_o));
 }
 
-// Gate and Gaussian of one grid node (Eqs. 10, 16, 17): trials n = w N 2^l
-struct NodeEval {
-    float n, m, mu1, sg;
-    uint32_t K;                // gate threshold on the top 23 hash bits
-};
-
-// gate probability P>=1 = 1 - (1 - p)^n (Eq. 16) from lp = log(1 - p)
-__device__ __forceinline__ float gate_prob(float n, float p, float lp)
+// Gate threshold of one grid node with n = w N 2^l trials (Eqs. 10, 16):
+// P>=1 = 1 - (1 - p)^n from lp = log(1 - p), and the uniform (2k+1) 2^-24 is
+// below P>=1  <=>  k < K.  Every branch is a select (the four nodes of a
+// light are set up side by side): K = 0 when n <= 0 or p <= 0, P>=1 = 1 when
+// p >= 1 (lp is then -inf or NaN and its value is discarded).
+__device__ __forceinline__ uint32_t gate_K(float n, float p, float lp)
 {
-    if (!(n > 0.0f) || !(p > 0.0f)) return 0.0f;
-    return p >= 1.0f ? 1.0f : one_minus_exp(n * lp);
-}
-
-__device__ __forceinline__ void eval_node(float w, int l, float N, float p, float lp, NodeEval &ne);
-
-// gate threshold: the uniform (2k+1) 2^-24 is below pg  <=>  k < K
-__device__ __forceinline__ uint32_t gate_threshold(float pg)
-{
+    const float pg = p >= 1.0f ? 1.0f : one_minus_exp(n * lp);
     const float kf = ceilf((pg * 16777216.0f - 1.0f) * 0.5f);
-    return kf <= 0.0f ? 0u : (kf >= 8388608.0f ? 8388608u : (uint32_t)kf);
+    const uint32_t K = kf >= 8388608.0f ? 8388608u : (kf > 0.0f ? (uint32_t)kf : 0u);
+    return (n > 0.0f && p > 0.0f) ? K : 0u;
 }
 
-}  // namespace glint
-
-namespace glint {
-__device__ __forceinline__ void eval_node(float w, int l, float N, float p, float lp, NodeEval &ne)
-{
-    ne.n = w * ldexpf(N, l);
-    ne.K = gate_threshold(gate_prob(ne.n, p, lp));
-    ne.m = fmaxf(ne.n - 1.0f, 0.0f);
-    ne.mu1 = 1.0f + ne.m * p;
-    ne.sg = __builtin_amdgcn_sqrtf(ne.m * p * (1.0f - p));
-}
 }  // namespace glint
 
 namespace glint {

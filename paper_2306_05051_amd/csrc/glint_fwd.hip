@@ -90,11 +90,19 @@ __device__ __forceinline__ uint32_t rng_word(uint32_t pre, uint32_t ak, const Sh
     }
 }
 
-template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false>
+// LK = 2 shades one item on two lanes: the even lane takes the even lights,
+// the odd lane the odd ones, and after every pair of lights the even lane
+// (the item's owner) receives its partner's factor and extends the radiance
+// chain with both, in light order.  With LK = 1 one lane takes every light.
+// Either way the chain is o.rgb = fma(E_l, f_l, o.rgb) over l = 0, 1, ...
+// with f_l = +0 for a light without an open gate, so the image has the same
+// bits.
+template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LK = 1>
 __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v, const double n[3],
                                            const double wi[3], int kp, const Shared &sh, TileSmem<DEBUG> &sm,
                                            ItemOut &o, const uint32_t *ltbl)
 {
+    static_assert(LK == 1 || (LK == 2 && !DEBUG), "two lanes per item only in the production kernels");
     const int lane = threadIdx.x;
     o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
     if (LIT) o.lit = 0u;
@@ -108,95 +116,116 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
     probe_texels(R, u, v, kp, M, sh, pre, sm, DEBUG ? &o.key_sum : (uint32_t *)nullptr);
     ViewFrame fr;
     view_frame(n, wi, fr);
-    for (int li = 0; li < sh.n_light; ++li) {
-        const DevLight &L = sh.lights[li];
-        LightEval le;
-        if (!eval_light(n, wi, R.alpha, L, M, fr, le)) continue;
-        const float p = le.p;
-        const float lp = log1m(p);
-        uint32_t K[4], anyK = 0u;
+    const int n_light = sh.n_light;
+    const int trips = LK == 1 ? n_light : (n_light + 1) >> 1;
+    for (int j = 0; j < trips; ++j) {
+        const int li = LK == 1 ? j : 2 * j + (lane & 1);
+        float f = 0.0f;                        // this light's radiance factor F G D_P / (4 <wi,n>)
+        do {
+            if (LK == 2 && li >= n_light) break;
+            const DevLight &L = sh.lights[li];
+            LightEval le;
+            if (!eval_light(n, wi, R.alpha, L, M, fr, le)) break;
+            const float p = le.p;
+            const float lp = log1m(p);
+            uint32_t K[4], anyK = 0u;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            K[g] = gate_threshold(gate_prob(R.ng[g], p, lp));
-            if (g < nn) anyK |= K[g];
-        }
-        if (!DEBUG && anyK == 0u) continue;    // no gate of this light can open
-        uint32_t ak0[4];
+            for (int g = 0; g < 4; ++g) {
+                K[g] = gate_K(R.ng[g], p, lp);
+                if (g < nn) anyK |= K[g];
+            }
+            if (!DEBUG && anyK == 0u) break;   // no gate of this light can open
+            uint32_t ak0[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
-        uint32_t mlo = 0u, mhi = 0u;           // open gates: bit g*16 + e*4 + a (g < 2 in mlo)
+            for (int a = 0; a < 4; ++a)
+                ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
+            uint32_t mlo = 0u, mhi = 0u;       // open gates: bit g*16 + e*4 + a (g < 2 in mlo)
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            if (g >= nn) continue;
-            if (!DEBUG && K[g] == 0u) continue;   // no uniform can open these gates
-            // theta0 < P>=1 (Eq. 18 gate)  <=>  (h >> 9) < K  <=>  h <= K 2^9 - 1  (K > 0)
-            const uint32_t thr = (K[g] << 9) - 1u;
-            if constexpr (DEBUG) {
+            for (int g = 0; g < 4; ++g) {
+                if (g >= nn) continue;
+                if (!DEBUG && K[g] == 0u) continue;   // no uniform can open these gates
+                // theta0 < P>=1 (Eq. 18 gate)  <=>  (h >> 9) < K  <=>  h <= K 2^9 - 1  (K > 0)
+                const uint32_t thr = (K[g] << 9) - 1u;
+                if constexpr (DEBUG) {
 #pragma unroll
-                for (int e = 0; e < 3; ++e) {
+                    for (int e = 0; e < 3; ++e) {
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const uint32_t h0 = rng_word<RNG>(pre[g][e], ak0[a], sh, ltbl);
-                        o.theta_sum += h0; o.n_gate += 1; o.n_live += K[g] ? 1u : 0u;
-                        o.n_live_small += (K[g] != 0u && K[g] <= 128u) ? 1u : 0u;
-                        const uint32_t bit = ((h0 >> 9) < K[g]) ? 1u : 0u;
-                        if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
-                        else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                        for (int a = 0; a < 4; ++a) {
+                            const uint32_t h0 = rng_word<RNG>(pre[g][e], ak0[a], sh, ltbl);
+                            o.theta_sum += h0; o.n_gate += 1; o.n_live += K[g] ? 1u : 0u;
+                            o.n_live_small += (K[g] != 0u && K[g] <= 128u) ? 1u : 0u;
+                            const uint32_t bit = ((h0 >> 9) < K[g]) ? 1u : 0u;
+                            if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                            else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                        }
                     }
-                }
-            } else if (RNG == kRngHash && HEAD && __ballot(K[g] > 128u) == 0ull) {
-                // every lane's threshold is below 2^16: compare the hash head
+                } else if (RNG == kRngHash && HEAD && __ballot(K[g] > 128u) == 0ull) {
+                    // every lane's threshold is below 2^16: compare the hash head
 #pragma unroll
-                for (int e = 0; e < 3; ++e) {
+                    for (int e = 0; e < 3; ++e) {
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const uint32_t bit = (hstep_head(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
-                        if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
-                        else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                        for (int a = 0; a < 4; ++a) {
+                            const uint32_t bit = (hstep_head(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
+                            if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                            else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                        }
                     }
-                }
-            } else {
+                } else {
 #pragma unroll
-                for (int e = 0; e < 3; ++e) {
+                    for (int e = 0; e < 3; ++e) {
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const uint32_t bit = (rng_word<RNG>(pre[g][e], ak0[a], sh, ltbl) <= thr) ? 1u : 0u;
-                        if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
-                        else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                        for (int a = 0; a < 4; ++a) {
+                            const uint32_t bit = (rng_word<RNG>(pre[g][e], ak0[a], sh, ltbl) <= thr) ? 1u : 0u;
+                            if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                            else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                        }
                     }
                 }
             }
+            // a light without an open gate adds exactly +0 to the (non-negative) sums
+            if ((mlo | mhi) == 0u) break;
+            if (DEBUG) o.n_lit += 1;
+            if (LIT) o.lit |= 1u << li;
+            light_brdf(M, R.alpha, le);
+            float bsum = 0.0f;
+            while (mlo | mhi) {
+                int idx;
+                if (mlo) { idx = __builtin_ctz(mlo); mlo &= mlo - 1u; }
+                else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
+                const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
+                const int ge = g * 3 + e;
+                const uint32_t ak1 = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
+                const uint32_t h1 = rng_word<RNG>(sm.pre[ge][lane], ak1, sh, ltbl);
+                // Eq. 17 for node g: m = max(n - 1, 0), 1 + mu, sigma (the adjoint repeats this arithmetic)
+                const float ng = R.ng[g];
+                const float m = fmaxf(ng - 1.0f, 0.0f);
+                const float x = fmaf(__builtin_amdgcn_sqrtf(m * p * (1.0f - p)), ndtri_bits(h1), 1.0f + m * p);
+                const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
+                const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);   // bilinear weight (Eq. 14)
+                bsum = fmaf(sm.beta[ge][lane] * va, c, bsum);
+                if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
+            }
+            const float G = 1.0f / ((1.0f + R.lam_i) * (1.0f + le.lam_o));
+            f = le.F * G * R.kpx * bsum;
+            if (DEBUG) o.b[li] = bsum;
+        } while (false);
+        if constexpr (LK == 1) {
+            const DevLight &L = sh.lights[j];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.rgb[c] = fmaf(L.rad[c], f, o.rgb[c]);
+        } else {
+            const float f1 = __shfl_xor(f, 1);     // the partner's light: 2j + 1 for the even lane
+            const DevLight &L0 = sh.lights[2 * j];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.rgb[c] = fmaf(L0.rad[c], f, o.rgb[c]);
+            if (2 * j + 1 < n_light) {
+                const DevLight &L1 = sh.lights[2 * j + 1];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o.rgb[c] = fmaf(L1.rad[c], f1, o.rgb[c]);
+            }
         }
-        // a light without an open gate adds exactly +0 to the (non-negative) sums
-        if ((mlo | mhi) == 0u) continue;
-        if (DEBUG) o.n_lit += 1;
-        if (LIT) o.lit |= 1u << li;
-        light_brdf(M, R.alpha, le);
-        float bsum = 0.0f;
-        while (mlo | mhi) {
-            int idx;
-            if (mlo) { idx = __builtin_ctz(mlo); mlo &= mlo - 1u; }
-            else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
-            const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
-            const int ge = g * 3 + e;
-            const uint32_t ak1 = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
-            const uint32_t h1 = rng_word<RNG>(sm.pre[ge][lane], ak1, sh, ltbl);
-            // Eq. 17 for node g: m = max(n - 1, 0), 1 + mu, sigma (same arithmetic as eval_node)
-            const float ng = R.ng[g];
-            const float m = fmaxf(ng - 1.0f, 0.0f);
-            const float x = fmaf(__builtin_amdgcn_sqrtf(m * p * (1.0f - p)), ndtri_bits(h1), 1.0f + m * p);
-            const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
-            const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);   // bilinear weight (Eq. 14)
-            bsum = fmaf(sm.beta[ge][lane] * va, c, bsum);
-            if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
-        }
-        const float G = 1.0f / ((1.0f + R.lam_i) * (1.0f + le.lam_o));
-        const float f = le.F * G * R.kpx * bsum;
-        o.rgb[0] = fmaf(L.rad[0], f, o.rgb[0]);
-        o.rgb[1] = fmaf(L.rad[1], f, o.rgb[1]);
-        o.rgb[2] = fmaf(L.rad[2], f, o.rgb[2]);
-        if (DEBUG) o.b[li] = bsum;
     }
+    if (LIT && LK == 2) o.lit |= __shfl_xor(o.lit, 1);
 }
 
 // per-pixel angular fingerprint (debug only): sum of slot-0 angular keys
@@ -263,7 +292,11 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     if (DEBUG)
         for (int l = 0; l < kMaxLight; ++l) db[l] = 0.0f;
     for (int base = 0; base < S; base += kWave) {
-        const int q = base + lane;
+        // a last batch of at most 32 items takes two lanes per item, each
+        // shading half of the lights (the even or the odd ones); the item's
+        // result is on its even lane
+        const int lk = (!DEBUG && S - base <= kWave / 2 && sh.n_light > 1) ? 2 : 1;
+        const int q = base + (lk == 2 ? lane >> 1 : lane);
         if (q < S) {
             const int p = item_pixel(sm.off, q);
             const int kp = q - sm.off[p];
@@ -272,8 +305,12 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             ItemOut o;
-            shade_item<DEBUG, HEAD, RNG, LIT>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp, sh, sm,
-                                              o, ltbl);
+            if (DEBUG || lk == 1)
+                shade_item<DEBUG, HEAD, RNG, LIT, 1>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp,
+                                                     sh, sm, o, ltbl);
+            else
+                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx],
+                                                                 n, wi, kp, sh, sm, o, ltbl);
             if constexpr (DEBUG) {
                 sm.dslot[lane] = o;
             } else {
@@ -298,11 +335,12 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                     dlt += s.n_lit;
                     for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
                 } else {
-                    acc[0] += __uint_as_float(sm.pre[0][i - base]);
-                    acc[1] += __uint_as_float(sm.pre[1][i - base]);
-                    acc[2] += __uint_as_float(sm.pre[2][i - base]);
+                    const int slot = (i - base) * lk;      // the item's owner lane
+                    acc[0] += __uint_as_float(sm.pre[0][slot]);
+                    acc[1] += __uint_as_float(sm.pre[1][slot]);
+                    acc[2] += __uint_as_float(sm.pre[2][slot]);
                     if (LIT) {
-                        const uint32_t m = sm.pre[3][i - base];
+                        const uint32_t m = sm.pre[3][slot];
                         litacc |= m;
                         probeacc |= m ? 1u << min(i - off, 31) : 0u;   // bit 31: probe 31 or a later one
                     }

@@ -139,6 +139,24 @@ def test_maximum_materials_and_lights(glint):
     _check(glint, gb, mats, lights, "32 materials, 16 lights")
 
 
+@pytest.mark.parametrize("n_light", [2, 3, 5])
+def test_two_lanes_per_item_in_short_batches(glint, n_light):
+    """A tile's last batch of at most 32 items runs each item on two lanes
+    (even and odd lights); the radiance chain keeps light order, so the image
+    equals the instrumented kernel's (one lane per item) bit for bit, also for
+    an odd number of lights."""
+    gb, mats, lights = scenes.four_k(200, 90, seed=12, n_light=n_light)
+    grgb, gdbg = _run(glint, gb, mats, lights)
+    H, W = gb["u"].shape
+    npr = np.zeros(((H + 1) // 2 * 2, (W + 31) // 32 * 32), np.int64)
+    npr[:H, :W] = gdbg["n_probe"]
+    S = npr.reshape(npr.shape[0] // 2, 2, npr.shape[1] // 32, 32).sum((1, 3)).ravel()
+    short = int(np.sum((S > 0) & ((S - 1) % 64 < 32)))
+    print(f"  tiles with a last batch of <= 32 items: {short} of {int(np.sum(S > 0))}", flush=True)
+    assert short > 20 and np.sum(S > 64) > 20
+    _check(glint, gb, mats, lights, f"two lanes per item, {n_light} lights")
+
+
 @pytest.mark.parametrize("k_max,n_probe_max", [(0, 21), (1, 21), (2, 8), (4, 1), (3, 64)])
 def test_grid_family_variants(glint, k_max, n_probe_max):
     gb, mats, lights = scenes.four_k(96, 80, seed=5, n_light=2)
