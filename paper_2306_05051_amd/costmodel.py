@@ -42,16 +42,19 @@ keys and gates):
       dot products: |wi + wo|^2 = 2 (1 + <wi,wo>) and so on): <n,wo> and its
       sign 8, <wi,wo> 6, |wi + wo|^2 and guard 4, 1/|wi + wo| 24, <n,h> 4,
       cos^2/sin^2 8, GGX ratio p 12, angular coordinates, cell and bilinear
-      fractions 50, log(1-p) 21, 4 gate set-ups (trials x log, 1-exp, guards,
-      threshold, shift) 4 x 28 = 112, 4 slot-0 angular keys 4 x 12 = 48 = 297
+      fractions 46 (the frame projections <t,wo>, <b,wo> through the implicit
+      frame: 4 FP64 operations), log(1-p) 21, 4 gate set-ups (trials x log,
+      1-exp, guards, threshold, shift) 4 x 28 = 112, 4 slot-0 angular keys
+      4 x 12 = 48 = 293
   lit item-light (extra, when at least one of its gates opened; otherwise it
       adds exactly nothing): Fresnel 13, Smith Lambda(wo) 20, radiance 13 = 46
-  item (one pixel, probe): probe centre 32, FP64 tangent frame 38, <n,wi>,
-      <wi,t>, <wi,b> 18, 4 x (key unpack 5, trig table index 3, rotation 8,
+  item (one pixel, probe): probe centre 32, FP64 tangent frame of n in
+      implicit form (sign s, a = -1/(s + n_z), s n_x) 21, <n,wi> 6 and
+      <wi,t>, <wi,b> from it 8, 4 x (key unpack 5, trig table index 3, rotation 8,
       anisotropic scales 14, lattice shear/floor/fractions 18, triangle 2,
       vertex selects 6, barycentrics 10, node hash 9, texel keys H(H(node, i),
       j) of the three vertices, which span two lattice columns: 2 + 3 hashes
-      45 and the column select 2) = 4 x 122 = 488, probe sum 3 = 579
+      45 and the column select 2) = 4 x 122 = 488, probe sum 3 = 558
   pixel: density 5, FP64 normalisation of n and w 84, footprint moments 24,
       <n,wi> 6, eigenvalue and ratio 60, atan2 80, sigma0 times the major-axis
       eigenvector 74, probe split 50, area level 6, ratio/orientation cell,
@@ -77,9 +80,9 @@ COST = {
     "live_gate": HASH + 1 + 2,
     "live_gate_small": HASH - 1 + 1 + 2,
     "open_gate": (3 + HASH) + HASH + 25 + 11 + 1 + 2 + 5,
-    "item_light": 8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 50 + 21 + 4 * 28 + 4 * (3 + HASH),
+    "item_light": 8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 46 + 21 + 4 * 28 + 4 * (3 + HASH),
     "item_light_lit": 13 + 20 + 13,
-    "item": (8 + FP64_RCP + 8) + (22 + FP64_RCP) + 18
+    "item": (8 + FP64_RCP + 8) + (5 + FP64_RCP) + 6 + 8
             + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + HASH + 5 * HASH + 2) + 3,
     "pixel": (5 + 2 * (12 + FP64_RSQ + 6) + 24 + 6 + (12 + FP64_SQRT + 2 + FP64_DIV + 2) + 80
               + (26 + 2 * FP64_RSQ) + (8 + 2 * FP64_DIV + 2) + 6 + 180 + 56),

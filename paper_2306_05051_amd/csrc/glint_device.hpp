@@ -242,6 +242,31 @@ __device__ __forceinline__ bool normalize_in(float x, float y, float z, double o
     return true;
 }
 
+// log2 x for x >= 1 (a footprint's ratio), exact at powers of two and
+// within about 1e-15 elsewhere: x = m 2^e with m in [1/sqrt 2, sqrt 2) and
+// log2 m = (2 / ln 2) atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, from the
+// odd series of atanh through s^21 (truncation below 1e-18 relative)
+__device__ __forceinline__ double log2_ratio(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.70710678118654752440) { m *= 2.0; e -= 1; }
+    const double s = (m - 1.0) * rcp_d(m + 1.0);
+    const double s2 = s * s;
+    double t = 1.0 / 21.0;
+    t = fma(t, s2, 1.0 / 19.0);
+    t = fma(t, s2, 1.0 / 17.0);
+    t = fma(t, s2, 1.0 / 15.0);
+    t = fma(t, s2, 1.0 / 13.0);
+    t = fma(t, s2, 1.0 / 11.0);
+    t = fma(t, s2, 1.0 / 9.0);
+    t = fma(t, s2, 1.0 / 7.0);
+    t = fma(t, s2, 1.0 / 5.0);
+    t = fma(t, s2, 1.0 / 3.0);
+    t = fma(t, s2, 1.0);
+    return (double)e + (2.88539008177792681472 * s) * t;
+}
+
 template <bool DEBUG>
 __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, const Shared &sh, Pixel &px)
 {
@@ -325,12 +350,14 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
         nv = 1; tk[0] = 0; tm[0] = 0; lam[0] = 1.0;
         tk[1] = tk[2] = 0; tm[1] = tm[2] = 0; lam[1] = lam[2] = 0.0;
     } else {
-        double rho = log2(rk);
+        double rho = log2_ratio(rk);
         rho = fmin(fmax(rho, 0.0), (double)K);
         kap = min((int)floor(rho), K - 1);
         const double u = rho - (double)kap;
         const int M = 1 << (kap + 1);
-        const double q = phi / (kPi / (double)M);   // exact boundary hits reproduce (pi/M is exact)
+        // phi / (pi / M) with pi / M = pi 2^-(kap+1) exact: the scaled quotient
+        // phi / pi (exact boundary hits reproduce)
+        const double q = ldexp(phi / kPi, kap + 1);
         j = (int)floor(q);
         j = max(0, min(j, M - 1));
         const double t = q - (double)j;
