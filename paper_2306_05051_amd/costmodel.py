@@ -17,10 +17,11 @@ per instruction class give
     v_mul_lo_u32, FP64 add/mul/FMA/compare/convert                2
     FP32 exp/log/rcp/rsq/sqrt                                     4
     FP64 rcp/rsq seeds                                            8
-FP64 1/sqrt(x) and 1/x, which need only be accurate to a few ulp on this
-path, are a seed and two Newton steps: 8 + 8 FP64 operations = 24 slots,
-8 + 4 = 16 slots; a correctly rounded FP64 quotient or square root (kept
-where a decision can sit exactly on its boundary) is counted as 20 and 24.
+FP64 1/sqrt(x) and 1/x, which need only be accurate to about 1e-14 on this
+path, are a seed (within 6e-8 on gfx950) and one Newton step: 8 + 4 FP64
+operations = 16 slots, 8 + 2 = 12 slots; a correctly rounded FP64 quotient
+or square root (kept where a decision can sit exactly on its boundary) is
+counted as 20 and 24.
 
 Per-unit costs: the minimal instruction sequence of each step of the method
 at the path's precision (FP64 for the footprint, the grid transforms, the
@@ -40,26 +41,26 @@ keys and gates):
       accumulate 5 = 65
   item-light (one pixel, probe, light; the unit half vector enters through
       dot products: |wi + wo|^2 = 2 (1 + <wi,wo>) and so on): <n,wo> and its
-      sign 8, <wi,wo> 6, |wi + wo|^2 and guard 4, 1/|wi + wo| 24, <n,h> 4,
+      sign 8, <wi,wo> 6, |wi + wo|^2 and guard 4, 1/|wi + wo| 16, <n,h> 4,
       cos^2/sin^2 8, GGX ratio p 12, angular coordinates, cell and bilinear
       fractions 46 (the frame projections <t,wo>, <b,wo> through the implicit
       frame: 4 FP64 operations), log(1-p) 21, 4 gate set-ups (trials x log,
       1-exp, guards, threshold, shift) 4 x 28 = 112, 4 slot-0 angular keys
-      4 x 12 = 48 = 293
+      4 x 12 = 48 = 285
   lit item-light (extra, when at least one of its gates opened; otherwise it
       adds exactly nothing): Fresnel 13, Smith Lambda(wo) 20, radiance 13 = 46
-  item (one pixel, probe): probe centre 32, FP64 tangent frame of n in
-      implicit form (sign s, a = -1/(s + n_z), s n_x) 21, <n,wi> 6 and
+  item (one pixel, probe): probe centre 28, FP64 tangent frame of n in
+      implicit form (sign s, a = -1/(s + n_z), s n_x) 17, <n,wi> 6 and
       <wi,t>, <wi,b> from it 8, 4 x (key unpack 5, trig table index 3, rotation 8,
       anisotropic scales 14, lattice shear/floor/fractions 18, triangle 2,
       vertex selects 6, barycentrics 10, node hash 9, texel keys H(H(node, i),
       j) of the three vertices, which span two lattice columns: 2 + 3 hashes
-      45 and the column select 2) = 4 x 122 = 488, probe sum 3 = 558
-  pixel: density 5, FP64 normalisation of n and w 84, footprint moments 24,
+      45 and the column select 2) = 4 x 122 = 488, probe sum 3 = 550
+  pixel: density 5, FP64 normalisation of n and w 68, footprint moments 24,
       <n,wi> 6, eigenvalue and ratio 60, atan2 80, sigma0 times the major-axis
-      eigenvector 74, probe split 50, area level 6, ratio/orientation cell,
+      eigenvector 58, probe split 50, area level 6, ratio/orientation cell,
       triangle, merge, sort, tetrahedron and node words 180,
-      D(n)/(R N P 4<wi,n>) and Lambda(wi) 56 = 625
+      D(n)/(R N P 4<wi,n>) and Lambda(wi) 56 = 593
 
 Units are counted exactly by the library's instrumented kernel (debug
 planes).  Loop control, address arithmetic, LDS traffic, recomputation,
@@ -73,8 +74,8 @@ VALU_PEAK_SLOTS = CU * SIMD_PER_CU * LANES_PER_CLK * CLOCK_HZ    # lane-slots / 
 FP32_PEAK_FLOPS = 157.3e12                                       # vendor dense FP32 vector (FMA = 2 flops)
 
 HASH = 5 + 2 * 2
-FP64_RSQ = 8 + 8 * 2
-FP64_RCP = 8 + 4 * 2
+FP64_RSQ = 8 + 4 * 2
+FP64_RCP = 8 + 2 * 2
 FP64_DIV, FP64_SQRT = 20, 24
 COST = {
     "live_gate": HASH + 1 + 2,
