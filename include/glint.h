@@ -241,17 +241,20 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * tiles, so the result does not depend on the schedule.
  * lit_lights, lit_probes (nullable): the masks glint_shade_lit wrote for
  * the same inputs with rounding 1 (relaxed; the gates do not depend on the
- * rounding).  lit_probes is used only with lit_lights: then only the probes
- * of a pixel whose bit is set are shaded (pixels with more than 31 probes
- * shade all of theirs).
- * Every gradient term of a light is proportional to its distributed count,
- * which is zero when none of its gates opened, so only the pixels with a
- * non-zero mask are shaded (gathered in raster order into waves of 64 lit
- * pixels; each such chunk has its own partial row) and only their lights
+ * rounding).  lit_probes is used only with lit_lights.
+ * Every gradient term of a light vanishes when none of its gates opened, so
+ * only the pixels with a non-zero mask are shaded, and only their lights
  * with a set bit: a fraction of the work, the same terms summed in another
  * grouping (equal within FP32 rounding to the call without the mask;
- * deterministic).  NULL evaluates every gate of every pixel.  Errors as glint_shade, plus ENULL (workspace,
- * gradient outputs), EINVAL (misaligned workspace, lit_lights or lit_probes). */
+ * deterministic).  With lit_lights alone the lit pixels are gathered in
+ * raster order into waves of 64 (each chunk has its own partial row).  With
+ * both masks (and n_light > 0) the work is cut into units of 64
+ * (pixel, lit probe, lit light) items, one light per lane (bit 31 of the
+ * probe mask stands for probes 31 to n_pr - 1), and 4096 workgroups take
+ * equal contiguous ranges of units, each with its own partial row.  NULL
+ * evaluates every gate of every pixel.  Errors as glint_shade, plus ENULL
+ * (workspace, gradient outputs), EINVAL (misaligned workspace, lit_lights
+ * or lit_probes). */
 int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                          const glint_light *lights, int32_t n_light, const glint_params *params,
                          const float *grad_out_rgb, const uint16_t *lit_lights,

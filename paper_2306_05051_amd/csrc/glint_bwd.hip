@@ -23,6 +23,7 @@
 // that the forward found closed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "glint_device.hpp"
@@ -49,11 +50,150 @@ struct BwdSmem {
     float dd[kMaxLight][3];
 };
 
+// The adjoint terms of one light at one (pixel, probe) item: adds d/d alpha
+// and d/d ln N of the item's material to da, dn and returns d/d dir of the
+// light in gd.  Returns whether one of the light's gates opened: otherwise
+// every term is exactly zero (each is proportional to a distributed count or
+// to one of its derivatives).  Gates are collected in bit masks and the open
+// ones processed in a compacted loop, as in the forward.
+__device__ __forceinline__ bool light_grad(const PixelRec &R, const double n[3], const double wi[3],
+                                           const DevMaterial &M, const ViewFrame &fr, const uint32_t (&pre)[4][3],
+                                           int nn, float alpha, float kpx, float lam_i, float dli_da, float inv_micro,
+                                           const DevLight &L, const float gout[3], BwdSmem &sm, float &da, float &dn,
+                                           float gd[3])
+{
+    const int lane = threadIdx.x;
+    gd[0] = gd[1] = gd[2] = 0.0f;
+    LightEval le;
+    if (!eval_light(n, wi, alpha, L, M, fr, le)) return false;
+    const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
+    const float p = le.p;
+    const float lp = log1m(p);
+    uint32_t K[4], anyK = 0u;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        K[g] = gate_K(R.ng[g], p, lp);
+        if (g < nn) anyK |= K[g];
+    }
+    uint32_t mlo = 0u, mhi = 0u;
+    if (anyK) {
+        uint32_t ak0[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            if (g >= nn || K[g] == 0u) continue;
+            const uint32_t thr = (K[g] << 9) - 1u;   // (h >> 9) < K  <=>  h <= K 2^9 - 1
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const uint32_t bit = (hstep(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
+                    if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
+                    else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
+                }
+            }
+        }
+    }
+    float B = 0.0f, Bp = 0.0f, Bm = 0.0f, Bfx = 0.0f, Bfy = 0.0f;
+    const bool opened = (mlo | mhi) != 0u;
+    while (mlo | mhi) {
+        int idx;
+        if (mlo) { idx = __builtin_ctz(mlo); mlo &= mlo - 1u; }
+        else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
+        const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
+        const int ge = g * 3 + e;
+        const uint32_t ak1 = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
+        const uint32_t h1 = hstep(sm.pre[ge][lane], ak1);
+        const float z = ndtri_bits(h1);
+        // Eq. 17 for node g (same arithmetic as the forward)
+        const float ng = R.ng[g];
+        const float m = fmaxf(ng - 1.0f, 0.0f);
+        const float sgg = __builtin_amdgcn_sqrtf(m * p * (1.0f - p));
+        const float x = fmaf(sgg, z, 1.0f + m * p);
+        const float be = sm.beta[ge][lane];
+        const float wx = (a & 1) ? le.fx : le.gx, wy = (a & 2) ? le.fy : le.gy;
+        const float va = wx * wy;                             // bilinear weight (Eq. 14)
+        const float dvx = (a & 1) ? wy : -wy, dvy = (a & 2) ? wx : -wx;
+        if (x >= 1.0f) {                                      // relaxed count c = x
+            const float isg = sgg > 0.0f ? 0.5f / sgg : 0.0f;
+            const float dsdp = m * (1.0f - 2.0f * p) * isg;   // d sigma / d p
+            const float dsdm = p * (1.0f - p) * isg;          // d sigma / d m
+            const float dmdl = ng > 1.0f ? ng : 0.0f;         // d m / d ln N
+            const float bv = be * va;
+            B = fmaf(bv, x, B);
+            Bp = fmaf(bv, m + z * dsdp, Bp);
+            Bm = fmaf(bv, (p + z * dsdm) * dmdl, Bm);
+            Bfx = fmaf(be * dvx, x, Bfx);
+            Bfy = fmaf(be * dvy, x, Bfy);
+        } else {                                              // clamped: c = 1
+            B = fmaf(be, va, B);
+            Bfx += be * dvx;
+            Bfy += be * dvy;
+        }
+    }
+    // Every term below is proportional to one of B, Bp, Bm, Bfx, Bfy, which
+    // are exactly 0 without an open gate: such lanes skip the algebra.
+    if (!opened) return false;
+    light_brdf(M, alpha, le);
+    // derivatives of p (Eq. 4) with respect to alpha and c2 = <n,h>^2
+    const float c2 = (float)(le.ch * le.ch), s2 = (float)(1.0 - le.ch * le.ch);
+    const float a2 = alpha * alpha;
+    float dp_da = 0.0f, dp_dc2 = 0.0f;
+    if (!le.pclamp && p > 0.0f) {
+        if (M.ndf == 0) {
+            const float d = s2 + c2 * a2;
+            dp_da = 4.0f * p / alpha * (1.0f - a2 * c2 / d);
+            dp_dc2 = 2.0f * p * (1.0f - a2) / d;
+        } else {
+            dp_da = 2.0f * p * s2 / (c2 * a2 * alpha);
+            dp_dc2 = p * (1.0f / (c2 * c2 * a2) - 2.0f / c2);
+        }
+    }
+    const float co = (float)le.cos_o, so2 = (float)(1.0 - le.cos_o * le.cos_o);
+    float dlo_dc, dlo_da;
+    smith_lambda_grad(M.ndf, alpha, co, so2, dlo_dc, dlo_da);
+    const float G = 1.0f / ((1.0f + lam_i) * (1.0f + le.lam_o));
+    const float dG_da = -G * (dli_da / (1.0f + lam_i) + dlo_da / (1.0f + le.lam_o));
+    const float sk = s * kpx;
+    da += sk * (le.F * dG_da * B + le.F * G * Bp * dp_da) - 2.0f * sk * le.F * G * B / alpha;
+    dn += sk * le.F * G * (Bm - B);
+    // gradient with respect to the unit half vector h
+    // the unit half vector itself (the forward needs only its dot products)
+    const double h[3] = {(wi[0] + L.wo[0]) * le.ihl, (wi[1] + L.wo[1]) * le.ihl, (wi[2] + L.wo[2]) * le.ihl};
+    const float om = (float)(1.0 - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]));
+    const float dF = -5.0f * (1.0f - M.F0) * om * om * om * om * G * B;   // times wi
+    const float cn = sk * le.F * G * Bp * dp_dc2 * 2.0f * (float)le.ch;   // times n
+    const float ct = sk * le.F * G * Bfx * inv_micro;                      // times t
+    const float cb = sk * le.F * G * Bfy * inv_micro;                      // times b
+    double ta[3], ba[3];
+    frame_axes(n, fr, ta, ba);
+    float gh[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        gh[c] = sk * dF * (float)wi[c] + cn * (float)n[c] + ct * (float)ta[c] + cb * (float)ba[c];
+    // direct dependence on wo through Lambda(<n,wo>)
+    const float gon = sk * le.F * B * (-G / (1.0f + le.lam_o)) * dlo_dc;
+    // h = (wi + wo)/|wi + wo|, wo = d/|d|: chain through both normalisations
+    const float hx = (float)h[0], hy = (float)h[1], hz = (float)h[2];
+    const float hd = gh[0] * hx + gh[1] * hy + gh[2] * hz;
+    const float ihl = (float)le.ihl;
+    const float gw[3] = {(gh[0] - hd * hx) * ihl + gon * (float)n[0],
+                         (gh[1] - hd * hy) * ihl + gon * (float)n[1],
+                         (gh[2] - hd * hz) * ihl + gon * (float)n[2]};
+    const float wxl = (float)L.wo[0], wyl = (float)L.wo[1], wzl = (float)L.wo[2];
+    const float wd = gw[0] * wxl + gw[1] * wyl + gw[2] * wzl;
+    const float idl = L.inv_len;
+    gd[0] = (gw[0] - wd * wxl) * idl;
+    gd[1] = (gw[1] - wd * wyl) * idl;
+    gd[2] = (gw[2] - wd * wzl) * idl;
+    return true;
+}
+
 // one (pixel, probe) item: accumulates d/d alpha and d/d ln N of the pixel's
 // material into da, dn, and d/d dir of each light into sm.dd (wave-reduced).
-// Called by every lane of the wave (live = false contributes zeros).  Gates
-// are collected in bit masks and the open ones processed in a compacted loop,
-// as in the forward.
+// Called by every lane of the wave (live = false contributes zeros).
 // Lights whose bit in litm is clear are skipped: the forward opened none of
 // their gates in this pixel, so they contribute exactly zero.
 __device__ void grad_item(bool live, const PixelRec &R, double u, double v, const double n[3], const double wi[3],
@@ -77,134 +217,13 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
     const float inv_micro = (float)M.inv_micro;
     for (int li = 0; li < sh.n_light; ++li) {
         const DevLight &L = sh.lights[li];
-        float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
+        float gd[3];
         bool opened = false;                     // this lane opened a gate of this light
-        LightEval le;
-        if (live && ((litm >> li) & 1u) && eval_light(n, wi, alpha, L, M, fr, le)) {
-            const float s = gout[0] * L.rad[0] + gout[1] * L.rad[1] + gout[2] * L.rad[2];
-            const float p = le.p;
-            const float lp = log1m(p);
-            uint32_t K[4], anyK = 0u;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                K[g] = gate_K(R.ng[g], p, lp);
-                if (g < nn) anyK |= K[g];
-            }
-            uint32_t mlo = 0u, mhi = 0u;
-            if (anyK) {
-                uint32_t ak0[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-                    ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    if (g >= nn || K[g] == 0u) continue;
-                    const uint32_t thr = (K[g] << 9) - 1u;   // (h >> 9) < K  <=>  h <= K 2^9 - 1
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) {
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const uint32_t bit = (hstep(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
-                            if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
-                            else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
-                        }
-                    }
-                }
-            }
-            float B = 0.0f, Bp = 0.0f, Bm = 0.0f, Bfx = 0.0f, Bfy = 0.0f;
-            opened = (mlo | mhi) != 0u;
-            while (mlo | mhi) {
-                int idx;
-                if (mlo) { idx = __builtin_ctz(mlo); mlo &= mlo - 1u; }
-                else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
-                const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
-                const int ge = g * 3 + e;
-                const uint32_t ak1 = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
-                const uint32_t h1 = hstep(sm.pre[ge][lane], ak1);
-                const float z = ndtri_bits(h1);
-                // Eq. 17 for node g (same arithmetic as the forward)
-                const float ng = R.ng[g];
-                const float m = fmaxf(ng - 1.0f, 0.0f);
-                const float sgg = __builtin_amdgcn_sqrtf(m * p * (1.0f - p));
-                const float x = fmaf(sgg, z, 1.0f + m * p);
-                const float be = sm.beta[ge][lane];
-                const float wx = (a & 1) ? le.fx : le.gx, wy = (a & 2) ? le.fy : le.gy;
-                const float va = wx * wy;                             // bilinear weight (Eq. 14)
-                const float dvx = (a & 1) ? wy : -wy, dvy = (a & 2) ? wx : -wx;
-                if (x >= 1.0f) {                                      // relaxed count c = x
-                    const float isg = sgg > 0.0f ? 0.5f / sgg : 0.0f;
-                    const float dsdp = m * (1.0f - 2.0f * p) * isg;   // d sigma / d p
-                    const float dsdm = p * (1.0f - p) * isg;          // d sigma / d m
-                    const float dmdl = ng > 1.0f ? ng : 0.0f;         // d m / d ln N
-                    const float bv = be * va;
-                    B = fmaf(bv, x, B);
-                    Bp = fmaf(bv, m + z * dsdp, Bp);
-                    Bm = fmaf(bv, (p + z * dsdm) * dmdl, Bm);
-                    Bfx = fmaf(be * dvx, x, Bfx);
-                    Bfy = fmaf(be * dvy, x, Bfy);
-                } else {                                              // clamped: c = 1
-                    B = fmaf(be, va, B);
-                    Bfx += be * dvx;
-                    Bfy += be * dvy;
-                }
-            }
-            // Every term below is proportional to one of B, Bp, Bm, Bfx, Bfy, which
-            // are exactly 0 without an open gate: such lanes skip the algebra.
-            if (opened) {
-            light_brdf(M, alpha, le);
-            // derivatives of p (Eq. 4) with respect to alpha and c2 = <n,h>^2
-            const float c2 = (float)(le.ch * le.ch), s2 = (float)(1.0 - le.ch * le.ch);
-            const float a2 = alpha * alpha;
-            float dp_da = 0.0f, dp_dc2 = 0.0f;
-            if (!le.pclamp && p > 0.0f) {
-                if (M.ndf == 0) {
-                    const float d = s2 + c2 * a2;
-                    dp_da = 4.0f * p / alpha * (1.0f - a2 * c2 / d);
-                    dp_dc2 = 2.0f * p * (1.0f - a2) / d;
-                } else {
-                    dp_da = 2.0f * p * s2 / (c2 * a2 * alpha);
-                    dp_dc2 = p * (1.0f / (c2 * c2 * a2) - 2.0f / c2);
-                }
-            }
-            const float co = (float)le.cos_o, so2 = (float)(1.0 - le.cos_o * le.cos_o);
-            float dlo_dc, dlo_da;
-            smith_lambda_grad(M.ndf, alpha, co, so2, dlo_dc, dlo_da);
-            const float G = 1.0f / ((1.0f + lam_i) * (1.0f + le.lam_o));
-            const float dG_da = -G * (dli_da / (1.0f + lam_i) + dlo_da / (1.0f + le.lam_o));
-            const float sk = s * kpx;
-            da += sk * (le.F * dG_da * B + le.F * G * Bp * dp_da) - 2.0f * sk * le.F * G * B / alpha;
-            dn += sk * le.F * G * (Bm - B);
-            // gradient with respect to the unit half vector h
-            // the unit half vector itself (the forward needs only its dot products)
-            const double h[3] = {(wi[0] + L.wo[0]) * le.ihl, (wi[1] + L.wo[1]) * le.ihl, (wi[2] + L.wo[2]) * le.ihl};
-            const float om = (float)(1.0 - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]));
-            const float dF = -5.0f * (1.0f - M.F0) * om * om * om * om * G * B;   // times wi
-            const float cn = sk * le.F * G * Bp * dp_dc2 * 2.0f * (float)le.ch;   // times n
-            const float ct = sk * le.F * G * Bfx * inv_micro;                      // times t
-            const float cb = sk * le.F * G * Bfy * inv_micro;                      // times b
-            double ta[3], ba[3];
-            frame_axes(n, fr, ta, ba);
-            float gh[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                gh[c] = sk * dF * (float)wi[c] + cn * (float)n[c] + ct * (float)ta[c] + cb * (float)ba[c];
-            // direct dependence on wo through Lambda(<n,wo>)
-            const float gon = sk * le.F * B * (-G / (1.0f + le.lam_o)) * dlo_dc;
-            // h = (wi + wo)/|wi + wo|, wo = d/|d|: chain through both normalisations
-            const float hx = (float)h[0], hy = (float)h[1], hz = (float)h[2];
-            const float hd = gh[0] * hx + gh[1] * hy + gh[2] * hz;
-            const float ihl = (float)le.ihl;
-            const float gw[3] = {(gh[0] - hd * hx) * ihl + gon * (float)n[0],
-                                 (gh[1] - hd * hy) * ihl + gon * (float)n[1],
-                                 (gh[2] - hd * hz) * ihl + gon * (float)n[2]};
-            const float wxl = (float)L.wo[0], wyl = (float)L.wo[1], wzl = (float)L.wo[2];
-            const float wd = gw[0] * wxl + gw[1] * wyl + gw[2] * wzl;
-            const float idl = L.inv_len;
-            gdx = (gw[0] - wd * wxl) * idl;
-            gdy = (gw[1] - wd * wyl) * idl;
-            gdz = (gw[2] - wd * wzl) * idl;
-            }
-        }
+        if (live && ((litm >> li) & 1u))
+            opened = light_grad(R, n, wi, M, fr, pre, nn, alpha, kpx, lam_i, dli_da, inv_micro, L, gout, sm, da, dn, gd);
+        else
+            gd[0] = gd[1] = gd[2] = 0.0f;
+        float gdx = gd[0], gdy = gd[1], gdz = gd[2];
         if (__ballot(opened) != 0ull) {          // uniform: every lane takes part in the sums
             gdx = wave_sum(gdx);
             gdy = wave_sum(gdy);
@@ -216,6 +235,29 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
             }
         }
     }
+}
+
+// one (pixel, probe, light) item of the masked adjoint, light li being the
+// lane's own: d/d alpha and d/d ln N of the pixel's material (da, dn) and
+// d/d dir of light li (gd).  Lanes with live = false return zeros.
+__device__ __forceinline__ void grad_item_light(bool live, const PixelRec &R, double u, double v, const double n[3],
+                                const double wi[3], int kp, int li, const Shared &sh, const float gout[3], float &da,
+                                float &dn, float gd[3], BwdSmem &sm)
+{
+    da = 0.0f;
+    dn = 0.0f;
+    gd[0] = gd[1] = gd[2] = 0.0f;
+    if (!live) return;
+    const int nn = rec_nodes(R);
+    const DevMaterial &M = sh.mats[rec_mat(R)];
+    uint32_t pre[4][3];
+    probe_texels(R, u, v, kp, M, sh, pre, sm, (uint32_t *)nullptr);
+    ViewFrame fr;
+    view_frame(n, wi, fr);
+    float dli_da, dl_dc;                          // d Lambda(view) / d alpha
+    smith_lambda_grad(M.ndf, R.alpha, (float)fr.cos_i, (float)(1.0 - fr.cos_i * fr.cos_i), dl_dc, dli_da);
+    light_grad(R, n, wi, M, fr, pre, nn, R.alpha, R.kpx, R.lam_i, dli_da, (float)M.inv_micro, sh.lights[li], gout,
+               sm, da, dn, gd);
 }
 
 // Work units: without a lit mask, workgroup b shades the 32x2 tile order[b]
@@ -349,6 +391,206 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         if (c < 2 * sh.n_mat) v = (c & 1) ? vn : va;
         else if (c < n_par) v = (&sm.dd[0][0])[c - 2 * sh.n_mat];
         if (c < row_stride) prow[c] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Masked adjoint in balanced work units.  With both masks the items are
+// (pixel, lit probe, lit light) triples, so each lane evaluates one light and
+// no lane waits on a light another lane needs.  Chunk c is the lit-list
+// entries [64c, 64c + 64); its items are numbered pixel by pixel (probe
+// rank major, light rank minor) and cut into batches of 64, the work units.
+// A fixed grid of kUnitGroups workgroups takes contiguous ranges of units
+// (the same number each), redoes a chunk's pixel set-up only when its range
+// enters that chunk, and writes one partial row per workgroup: the sums run
+// in a fixed order whatever the schedule.
+// ---------------------------------------------------------------------------
+constexpr int kUnitWaves = 4;          // chunks per workgroup of the count pass
+constexpr int kUnitGroups = 4096;      // persistent workgroups (partial rows) of the unit kernel
+
+// probe items of a lit pixel: its probes with an open gate (bit k: probe k;
+// bit 31: probes 31 to npr - 1)
+__device__ __forceinline__ int lit_probe_count(uint32_t pm, int npr)
+{
+    return __popc(pm & 0x7fffffffu) + ((pm >> 31) ? max(npr - 31, 0) : 0);
+}
+
+// nb[c] = number of 64-item batches of chunk c, for the chunks of the list
+// (a grid-stride loop over them)
+__global__ __launch_bounds__(kWave * kUnitWaves) void glint_unit_count(ViewDesc vw, Shared sh,
+                                                                         const uint16_t *__restrict__ lit,
+                                                                         const uint32_t *__restrict__ lit_probes,
+                                                                         const uint32_t *__restrict__ list,
+                                                                         const uint32_t *__restrict__ list_len,
+                                                                         int64_t n_chunks, uint32_t *__restrict__ nb)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t len = list_len[0];
+    const int64_t used = (len + kWave - 1) / kWave < n_chunks ? (len + kWave - 1) / kWave : n_chunks;
+    const uint32_t lmask = (1u << sh.n_light) - 1u;
+    const int64_t waves = (int64_t)gridDim.x * kUnitWaves;
+    for (int64_t c = (int64_t)blockIdx.x * kUnitWaves + (int)(threadIdx.x / kWave); c < used; c += waves) {
+        const int64_t e = c * kWave + lane;
+        int cnt = 0;
+        if (e < len) {
+            const uint32_t idx = list[e];
+            const uint32_t pm = lit_probes[idx];
+            int npr = 0;
+            if (pm >> 31) {                    // probes from 31 on: the pixel's probe count
+                Pixel px;
+                px.flags = 0;
+                px.npr = 0;
+                setup_pixel<false>(vw, idx, sh, px);
+                npr = px.npr;
+            }
+            cnt = lit_probe_count(pm, npr) * __popc((uint32_t)lit[idx] & lmask);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
+        if (lane == 0) nb[c] = (uint32_t)((cnt + kWave - 1) / kWave);
+    }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void glint_bwd_unit_kernel(
+    ViewDesc vw, Shared sh, const float *gout, const uint16_t *__restrict__ lit,
+    const uint32_t *__restrict__ lit_probes, const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_len,
+    const uint32_t *__restrict__ unit_off, const uint32_t *__restrict__ n_units_p, float *partials, int n_par,
+    int row_stride)
+{
+    __shared__ BwdSmem sm;
+    const int lane = threadIdx.x;
+    const int64_t npx = (int64_t)vw.height * vw.stride;
+    const uint32_t lmask = (1u << sh.n_light) - 1u;
+    const uint32_t len = (uint32_t)__builtin_amdgcn_readfirstlane((int)list_len[0]);
+    const uint32_t n_units = (uint32_t)__builtin_amdgcn_readfirstlane((int)n_units_p[0]);
+    const uint32_t n_chunks = (len + kWave - 1) / kWave;
+    const uint32_t per = (n_units + gridDim.x - 1) / gridDim.x;
+    uint32_t u = blockIdx.x * per;
+    const uint32_t u_end = min(u + per, n_units);
+    if (lane < kMaxLight * 3) (&sm.dd[0][0])[lane] = 0.0f;
+    __syncthreads();
+    float acc_a = 0.0f, acc_n = 0.0f;          // lane m < n_mat: material m
+    if (u < u_end) {
+        // the chunk of unit u: the last c with unit_off[c] <= u (every chunk of
+        // the list has at least one batch, and unit_off[0] = 0), by 64-way search
+        uint32_t lo = 0, hi = n_chunks;
+        while (hi - lo > 1) {
+            const uint32_t step = (hi - lo + kWave - 1) / kWave;
+            const uint32_t pos = lo + (uint32_t)lane * step;
+            const uint64_t m = __ballot(pos < hi && unit_off[pos] <= u);
+            lo += (uint32_t)(63 - __clzll(m)) * step;
+            hi = min(lo + step, hi);
+        }
+        uint32_t c = lo;
+        uint32_t b = u - (uint32_t)__builtin_amdgcn_readfirstlane((int)unit_off[c]);
+        int cur = -1, S = 0;
+        while (u < u_end && c < n_chunks) {
+            if ((int)c != cur) {
+                // the chunk's pixel set-up: records (probe count 0 for a pixel
+                // that is not shaded) and the first item of each pixel
+                __syncthreads();               // the previous chunk's records are no longer read
+                const uint32_t e = c * kWave + (uint32_t)lane;
+                const bool has = e < len;
+                const uint32_t pix = has ? list[e] : 0u;
+                const uint32_t pm = has ? lit_probes[pix] : 0u;
+                const uint32_t litm = has ? ((uint32_t)lit[pix] & lmask) : 0u;
+                Pixel px;
+                px.flags = 0;
+                px.npr = 0;
+                if (has) setup_pixel<false>(vw, pix, sh, px);
+                if (px.flags & F_SHADED) sm.rec[lane] = make_rec(px, sh);
+                else sm.rec[lane].pk = 0u;
+                const int cnt = has ? lit_probe_count(pm, px.npr) * __popc(litm) : 0;
+                int incl = cnt;
+#pragma unroll
+                for (int d = 1; d < kWave; d <<= 1) {
+                    const int t = __shfl_up(incl, d);
+                    if (lane >= d) incl += t;
+                }
+                S = __shfl(incl, kWave - 1);
+                sm.off[lane] = incl - cnt;
+                cur = (int)c;
+                __syncthreads();
+            }
+            if (S == 0) {                      // no item (masks that disagree): no unit either
+                ++c;
+                b = 0;
+                continue;
+            }
+            // batch b of chunk c: item r -> pixel p (the last with off <= r),
+            // then probe rank r' / nl and light rank r' % nl, r' = r - off
+            const int r = (int)b * kWave + lane;
+            int p = 0;
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1)
+                if (sm.off[p + st] <= r) p += st;
+            const bool live = r < S && rec_npr(sm.rec[p]) > 0;
+            int kp = 0, li = 0;
+            float g3[3] = {0.0f, 0.0f, 0.0f};
+            double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, uu = 0.0, vv = 0.0;
+            if (live) {
+                const uint32_t pidx = list[c * kWave + (uint32_t)p];
+                const uint32_t pm = lit_probes[pidx], litm = (uint32_t)lit[pidx] & lmask;
+                const int nl = __popc(litm);
+                const int rr = r - sm.off[p];
+                const int pr = rr / nl, lr = rr - pr * nl;
+                const uint32_t low = pm & 0x7fffffffu;
+                const int nlow = __popc(low);
+                kp = pr < nlow ? nth_bit(low, pr) : 31 + (pr - nlow);
+                li = nth_bit(litm, lr);
+                normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
+                normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
+                uu = vw.u[pidx];
+                vv = vw.v[pidx];
+                g3[0] = gout[pidx];
+                g3[1] = gout[npx + pidx];
+                g3[2] = gout[2 * npx + pidx];
+            }
+            float da, dn, gd[3];
+            grad_item_light(live, sm.rec[p], uu, vv, n, wi, kp, li, sh, g3, da, dn, gd, sm);
+            // per material and per light, a wave sum over the lanes of that
+            // material or light (fixed order); lane m keeps material m's sums
+            const int mat = live ? rec_mat(sm.rec[p]) : -1;
+            for (int m = 0; m < sh.n_mat; ++m) {
+                const bool mine = mat == m;
+                if (__ballot(mine) == 0ull) continue;
+                const float xa = wave_sum(mine ? da : 0.0f);
+                const float xn = wave_sum(mine ? dn : 0.0f);
+                if (lane == m) {
+                    acc_a += xa;
+                    acc_n += xn;
+                }
+            }
+            for (int l = 0; l < sh.n_light; ++l) {
+                const bool mine = live && li == l;
+                if (__ballot(mine) == 0ull) continue;
+                const float x = wave_sum(mine ? gd[0] : 0.0f);
+                const float y = wave_sum(mine ? gd[1] : 0.0f);
+                const float z = wave_sum(mine ? gd[2] : 0.0f);
+                if (lane == 0) {
+                    sm.dd[l][0] += x;
+                    sm.dd[l][1] += y;
+                    sm.dd[l][2] += z;
+                }
+            }
+            __syncthreads();                   // this item's texel columns are free again
+            ++u;
+            if ((int)(++b) * kWave >= S) {
+                ++c;
+                b = 0;
+            }
+        }
+    }
+    // this workgroup's row: [alpha, lnN] per material, then 3 per light, zero padding
+    float *prow = partials + (int64_t)blockIdx.x * row_stride;
+    for (int c0 = 0; c0 < row_stride; c0 += kWave) {
+        const int col = c0 + lane;
+        const int m = (col >> 1) & (kWave - 1);
+        const float va = __shfl(acc_a, m), vn = __shfl(acc_n, m);
+        float v = 0.0f;
+        if (col < 2 * sh.n_mat) v = (col & 1) ? vn : va;
+        else if (col < n_par) v = (&sm.dd[0][0])[col - 2 * sh.n_mat];
+        if (col < row_stride) prow[col] = v;
     }
 }
 
@@ -487,11 +729,18 @@ __global__ __launch_bounds__(kLitThreads) void glint_lit_count(const uint16_t *_
     if (threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
+// n_dev (nullable): scan only the first ceil(n_dev[0] / 64) counts (the
+// chunks of a list of n_dev[0] entries), at most n
 __global__ __launch_bounds__(kLitScan) void glint_lit_scan(const uint32_t *__restrict__ counts, int64_t n,
-                                                           uint32_t *__restrict__ offs, uint32_t *__restrict__ len)
+                                                           uint32_t *__restrict__ offs, uint32_t *__restrict__ len,
+                                                           const uint32_t *__restrict__ n_dev)
 {
     __shared__ uint32_t ws[kLitScan];
     const int t = threadIdx.x;
+    if (n_dev) {
+        const int64_t m = ((int64_t)n_dev[0] + kWave - 1) / kWave;
+        n = m < n ? m : n;
+    }
     const int64_t per = (n + kLitScan - 1) / kLitScan;
     const int64_t b0 = (int64_t)t * per < n ? (int64_t)t * per : n;
     const int64_t b1 = b0 + per < n ? b0 + per : n;
@@ -555,29 +804,40 @@ static int row_stride_of(int n_par)
 }
 
 struct BwdLayout {
-    size_t part_off, stage1_off, list_off, counts_off, offs_off, len_off, bytes;
+    size_t part_off, stage1_off, list_off, counts_off, offs_off, len_off, nb_off, uoff_off, nunits_off, bytes;
     int stride;
-    int64_t rpb, n_blk, n_seg;
+    int64_t rpb, n_blk, n_seg, n_chunks;
     int32_t segs_x;
 };
+
+// rows -> (rows per first-stage block, first-stage blocks)
+static void reduce_shape(int64_t rows, int64_t &rpb, int64_t &n_blk)
+{
+    rpb = (rows + kReduceBlocks - 1) / kReduceBlocks;
+    n_blk = rpb > 0 ? (rows + rpb - 1) / rpb : 0;
+}
 
 static BwdLayout bwd_layout(int32_t width, int32_t height, int n_par)
 {
     BwdLayout L;
     const size_t a = 256;
     const int64_t tiles = bwd_tiles(width, height);
+    const int64_t rows = tiles > kUnitGroups ? tiles : kUnitGroups;   // tiles, list chunks or unit workgroups
     L.stride = row_stride_of(n_par);
-    L.rpb = (tiles + kReduceBlocks - 1) / kReduceBlocks;
-    L.n_blk = L.rpb > 0 ? (tiles + L.rpb - 1) / L.rpb : 0;
+    reduce_shape(tiles, L.rpb, L.n_blk);
     L.part_off = (tile_order_bytes(width, height) + a - 1) / a * a;
-    L.stage1_off = L.part_off + ((size_t)tiles * L.stride * 4 + a - 1) / a * a;
+    L.stage1_off = L.part_off + ((size_t)rows * L.stride * 4 + a - 1) / a * a;
     L.segs_x = (width + kLitSeg - 1) / kLitSeg;
     L.n_seg = (int64_t)L.segs_x * height;
-    L.list_off = L.stage1_off + ((size_t)L.n_blk * L.stride * 8 + a - 1) / a * a;
+    L.n_chunks = ((int64_t)width * height + kWave - 1) / kWave;
+    L.list_off = L.stage1_off + ((size_t)kReduceBlocks * L.stride * 8 + a - 1) / a * a;
     L.counts_off = L.list_off + ((size_t)width * height * 4 + a - 1) / a * a;
     L.offs_off = L.counts_off + ((size_t)L.n_seg * 4 + a - 1) / a * a;
     L.len_off = L.offs_off + ((size_t)L.n_seg * 4 + a - 1) / a * a;
-    L.bytes = L.len_off + a;
+    L.nb_off = L.len_off + a;
+    L.uoff_off = L.nb_off + ((size_t)L.n_chunks * 4 + a - 1) / a * a;
+    L.nunits_off = L.uoff_off + ((size_t)L.n_chunks * 4 + a - 1) / a * a;
+    L.bytes = L.nunits_off + a;
     return L;
 }
 
@@ -634,14 +894,46 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
     const int32_t *order = nullptr;
     int64_t grid = tiles;
     // list entries are y*stride + x in 32 bits
-    if (lit_lights && (int64_t)vw.height * vw.stride <= 0xffffffffLL) {
+    const bool fits = (int64_t)vw.height * vw.stride <= 0xffffffffLL;
+    if (lit_lights && lit_probes && n_light > 0 && fits) {
+        // both masks: balanced units of (pixel, lit probe, lit light) items
+        uint32_t *d_list = (uint32_t *)((char *)workspace + L.list_off);
+        uint32_t *d_counts = (uint32_t *)((char *)workspace + L.counts_off);
+        uint32_t *d_offs = (uint32_t *)((char *)workspace + L.offs_off);
+        uint32_t *d_len = (uint32_t *)((char *)workspace + L.len_off);
+        uint32_t *d_nb = (uint32_t *)((char *)workspace + L.nb_off);
+        uint32_t *d_uoff = (uint32_t *)((char *)workspace + L.uoff_off);
+        uint32_t *d_nunits = (uint32_t *)((char *)workspace + L.nunits_off);
+        hipLaunchKernelGGL(glint_lit_count, dim3((unsigned)L.n_seg), dim3(kLitThreads), 0, st, lit_lights,
+                           vw.width, vw.stride, L.segs_x, d_counts);
+        hipLaunchKernelGGL(glint_lit_scan, dim3(1), dim3(kLitScan), 0, st, d_counts, L.n_seg, d_offs, d_len,
+                           (const uint32_t *)nullptr);
+        hipLaunchKernelGGL(glint_lit_scatter, dim3((unsigned)L.n_seg), dim3(kLitThreads), 0, st, lit_lights,
+                           vw.width, vw.stride, L.segs_x, d_offs, d_list);
+        const int64_t count_groups = std::min<int64_t>((L.n_chunks + kUnitWaves - 1) / kUnitWaves, 2048);
+        hipLaunchKernelGGL(glint_unit_count, dim3((unsigned)count_groups), dim3(kWave * kUnitWaves), 0, st, vw, sh,
+                           lit_lights, lit_probes, d_list, d_len, L.n_chunks, d_nb);
+        hipLaunchKernelGGL(glint_lit_scan, dim3(1), dim3(kLitScan), 0, st, d_nb, L.n_chunks, d_uoff, d_nunits, d_len);
+        hipLaunchKernelGGL(glint_bwd_unit_kernel, dim3(kUnitGroups), dim3(kWave), 0, st, vw, sh, grad_out_rgb,
+                           lit_lights, lit_probes, d_list, d_len, d_uoff, d_nunits, partials, n_par, L.stride);
+        int64_t rpb, n_blk;
+        reduce_shape(kUnitGroups, rpb, n_blk);
+        hipLaunchKernelGGL(glint_bwd_reduce1, dim3((unsigned)n_blk), dim3(kReduceThreads), 0, st, partials,
+                           (int64_t)kUnitGroups, (const uint32_t *)nullptr, L.stride, rpb, stage1);
+        hipLaunchKernelGGL(glint_bwd_reduce2, dim3(1), dim3(kReduceThreads), 0, st, stage1, (int)n_blk, L.stride,
+                           n_mat, n_par, grad_alpha, grad_ln_density, grad_light_dir);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? GLINT_OK : set_hip_error(e);
+    }
+    if (lit_lights && fits) {
         uint32_t *d_list = (uint32_t *)((char *)workspace + L.list_off);
         uint32_t *d_counts = (uint32_t *)((char *)workspace + L.counts_off);
         uint32_t *d_offs = (uint32_t *)((char *)workspace + L.offs_off);
         uint32_t *d_len = (uint32_t *)((char *)workspace + L.len_off);
         hipLaunchKernelGGL(glint_lit_count, dim3((unsigned)L.n_seg), dim3(kLitThreads), 0, st, lit_lights,
                            vw.width, vw.stride, L.segs_x, d_counts);
-        hipLaunchKernelGGL(glint_lit_scan, dim3(1), dim3(kLitScan), 0, st, d_counts, L.n_seg, d_offs, d_len);
+        hipLaunchKernelGGL(glint_lit_scan, dim3(1), dim3(kLitScan), 0, st, d_counts, L.n_seg, d_offs, d_len,
+                           (const uint32_t *)nullptr);
         hipLaunchKernelGGL(glint_lit_scatter, dim3((unsigned)L.n_seg), dim3(kLitThreads), 0, st, lit_lights,
                            vw.width, vw.stride, L.segs_x, d_offs, d_list);
         list = d_list;

@@ -180,6 +180,26 @@ def test_backward_with_lit_mask_matches_full_adjoint(glint, case):
         assert torch.equal(x, y)
 
 
+def test_backward_units_expand_probes_beyond_31(glint):
+    """Footprints split into more than 31 probes: bit 31 of the probe mask
+    stands for probes 31 on, and the masked adjoint (work units of
+    (pixel, lit probe, lit light) items) expands it from the pixel's own probe
+    count: the same gradient as the adjoint without masks."""
+    gb, mats, lights = scenes.four_k(128, 48, seed=14, n_light=3, n_mat=3, n_probe_max=64)
+    dgb = glint.to_device(gb)
+    _, lit, probes = glint.glint_shade_lit(dgb, mats, lights, rounding=1, n_probe_max=64)
+    go = torch.randn((3,) + gb["u"].shape, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    full = glint.glint_shade_backward(dgb, mats, lights, go, n_probe_max=64)
+    fast = glint.glint_shade_backward(dgb, mats, lights, go, n_probe_max=64, lit=lit, probes=probes)
+    torch.cuda.synchronize()
+    beyond = int(((probes.cpu().numpy().view(np.uint32) >> 31) & 1).sum())
+    print(f"  pixels with a lit probe from 31 on: {beyond}", flush=True)
+    assert beyond > 0
+    for a, b in zip(full, fast):
+        a, b = a.double(), b.double()
+        assert float((a - b).abs().max()) <= 1e-5 * float(a.abs().max()) + 1e-30
+
+
 def test_backward_with_empty_lit_mask_is_zero(glint):
     """A mask with no lit pixel leaves nothing to differentiate: zero gradients."""
     gb, mats, lights = scenes.four_k(300, 7, seed=12, n_light=2, n_mat=2)
