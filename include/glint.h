@@ -250,7 +250,7 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * raster order into waves of 64 (each chunk has its own partial row).  With
  * both masks (and n_light > 0) the work is cut into units of 64
  * (pixel, lit probe, lit light) items, one light per lane (bit 31 of the
- * probe mask stands for probes 31 to n_pr - 1), and 4096 workgroups take
+ * probe mask stands for probes 31 to n_pr - 1), and 8192 workgroups take
  * equal contiguous ranges of units, each with its own partial row.  NULL
  * evaluates every gate of every pixel.  Errors as glint_shade, plus ENULL
  * (workspace, gradient outputs), EINVAL (misaligned workspace, lit_lights
