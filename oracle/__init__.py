@@ -30,7 +30,7 @@ PLANES = ("u", "v", "dudx", "dvdx", "dudy", "dvdy", "nx", "ny", "nz", "wx", "wy"
 FLAG_SHADED, FLAG_CLAMP_RATIO, FLAG_CLAMP_P, FLAG_BAD_INPUT = 1, 2, 4, 8
 FLAG_BACKFACING, FLAG_SKIPPED, FLAG_BAD_MAT = 16, 32, 64
 MARGIN_KINDS = ("none", "nprobe", "ratio", "orient", "triangle", "tetra", "lattice",
-                "angular", "gate", "count", "light", "view")
+                "angular", "gate", "count", "light", "view", "zk_switch")
 
 
 def build(force: bool = False) -> str:
@@ -61,7 +61,7 @@ class _Light(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("n_probe_max", C.c_int32), ("rounding", C.c_int32),
-                ("rng_log2", C.c_int32), ("rng_seed", C.c_uint32)]
+                ("rng_log2", C.c_int32), ("rng_seed", C.c_uint32), ("count_law", C.c_int32)]
 
 
 _DBG_FIELDS = [("flags", np.uint32), ("n_probe", np.int32), ("level", np.int32),
@@ -113,6 +113,8 @@ def lib():
                                  C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.og_gated_count.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]
         L.og_gated_count.restype = C.c_double
+        L.og_zk_count.argtypes = [C.c_double, C.c_double, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.og_zk_count.restype = C.c_double
         _lib = L
     return _lib
 
@@ -158,20 +160,25 @@ def _lights(lights):
 
 
 def shade(gb, materials, lights, k_max=4, n_probe_max=21, rounding=0, debug=False,
-          rows=None, n_threads=0, rng_table=None):
+          rows=None, n_threads=0, rng_table=None, count_law=0):
     """FP64 radiance [3, H, W]; with debug=True also a dict of per-pixel planes.
 
     rng_table=None hashes every gate uniform from its keys; rng_table=(log2,
     seed) reads them from the table of 2**log2 words whose entry i is
     hash_step(seed, i) (log2 in 1..32), at the index (texel key XOR angular
-    key) mod 2**log2."""
+    key) mod 2**log2.
+
+    count_law=1 counts with the Zirr-Kaplanyan baseline (zk_count per texel,
+    outputs mixed with the node weights); its debug planes then hold: n_open
+    the counts on the Gaussian branch, n_live the Bernoulli trials drawn,
+    count_sum the sum of the integer counts, lit the lights with a count > 0."""
     L = lib()
     s, keep, H, W = _gbuf(gb)
     mats, lts = _mats(materials), _lights(lights)
     log2, seed = (0, 0) if rng_table is None else (int(rng_table[0]), int(rng_table[1]) & 0xFFFFFFFF)
     if rng_table is not None and not 1 <= log2 <= 32:
         raise ValueError("rng_table log2 must be in 1..32")
-    prm = _Params(k_max, n_probe_max, rounding, log2, seed)
+    prm = _Params(k_max, n_probe_max, rounding, log2, seed, count_law)
     out = np.zeros((3, H, W), np.float64)
     dbg = None
     planes = {}
@@ -277,3 +284,11 @@ def simplex(cx, cy, l, k, m):
 
 def gated_count(n, p, theta0, theta1, rounding=0):
     return lib().og_gated_count(float(n), float(p), float(theta0), float(theta1), int(rounding))
+
+
+def zk_count(n, p, h0):
+    """One count of the Zirr-Kaplanyan baseline from n trials, probability p and
+    the texel's slot-0 word h0: (count, gaussian branch taken, trials drawn)."""
+    g, t = C.c_int(), C.c_int()
+    c = lib().og_zk_count(float(n), float(p), h0 & 0xFFFFFFFF, C.byref(g), C.byref(t))
+    return c, g.value, t.value

@@ -28,6 +28,7 @@
  *   uniforms from a precomputed table (variant) Sec. 6.3 (small texture of random numbers)
  *   distributed sum over grids                  Sec. 4.2, Eq. 10; Sec. 5.2
  *   glint NDF, BRDF, radiance                   Sec. 3, Eqs. 1-3
+ *   baseline: Zirr-Kaplanyan counting (A/B)     Sec. 2, Eq. 7; Sec. 6.3, Eq. 15; Sec. 7
  *
  * Parity pins (tests that hold this file to the paper and to mathematics,
  * not to itself): footprint vs numpy SVD; NDF normalisation and Smith
@@ -75,8 +76,11 @@ typedef struct { float dir[3]; float radiance[3]; } og_light;
 
 /* rng_log2 = 0: gate uniforms hashed from their keys; 1..32: read from a
  * table of 2^rng_log2 words whose entry i is H(rng_seed, i) (Sec. 6.3, the
- * small precomputed texture of random numbers) */
-typedef struct { int32_t k_max, n_probe_max, rounding, rng_log2; uint32_t rng_seed; } og_params;
+ * small precomputed texture of random numbers).
+ * count_law 0: the distributed gated binomial (the method); 1: the counting
+ * law of Zirr and Kaplanyan, an A/B baseline (see zk_count; integer counts,
+ * so rounding must be 0). */
+typedef struct { int32_t k_max, n_probe_max, rounding, rng_log2; uint32_t rng_seed; int32_t count_law; } og_params;
 
 typedef struct {                  /* every plane is [height*stride] or NULL */
     uint32_t *flags;
@@ -101,7 +105,7 @@ typedef struct {                  /* every plane is [height*stride] or NULL */
 
 /* margin kinds (which discrete decision came closest to its boundary) */
 enum { MK_NONE = 0, MK_NPROBE, MK_RATIO, MK_ORIENT, MK_TRIANGLE, MK_TETRA,
-       MK_LATTICE, MK_ANGULAR, MK_GATE, MK_COUNT, MK_LIGHT, MK_VIEW };
+       MK_LATTICE, MK_ANGULAR, MK_GATE, MK_COUNT, MK_LIGHT, MK_VIEW, MK_ZK_SWITCH };
 
 /* ------------------------------------------------------------------ */
 /* Decision tape: records every light-dependent discrete decision of a */
@@ -511,6 +515,58 @@ double og_gated_count(double n, double p, double theta0, double theta1, int roun
 }
 
 /* ------------------------------------------------------------------ */
+/* Counting law of Zirr and Kaplanyan, the prior art the method        */
+/* replaces (Sec. 2, Eq. 7; Sec. 6.3, Eq. 15), kept as an A/B baseline. */
+/* Every grid node counts the flakes of its whole cell, n = N A_g      */
+/* trials, and the node outputs are mixed with the interpolation       */
+/* weights w_g (Eq. 7: a linear mix of binomial outputs, here over the */
+/* nodes of the grid family instead of two LOD levels).  One count:    */
+/*   n p > 5, or n above the Bernoulli loop limit 16 (Sec. 7):          */
+/*       c = max(0, floor(n p + sqrt(n p (1-p)) Phi^-1(theta_0)))       */
+/*   otherwise t = floor(n + 1/2) Bernoulli trials:                     */
+/*       c = #{k = 1..t : theta_k < p},  theta_k the uniform of H(h0, k) */
+/* with h0 the texel's slot-0 word and theta_0 its uniform; a trial     */
+/* succeeds when theta < p, as the gates do (the paper's X_i < p).      */
+/* *gauss: 1 on the Gaussian branch; *trials: Bernoulli trials drawn.   */
+/* ------------------------------------------------------------------ */
+#define OG_ZK_LOOP_MAX 16.0
+static double zk_count(double n, double p, uint32_t h0, double *mg, int *mk, int *gauss, int *trials)
+{
+    const double mu = n * p;
+    upd_margin(mg, mk, fabs(mu - 5.0) / 5.0, MK_ZK_SWITCH);
+    upd_margin(mg, mk, fabs(n - OG_ZK_LOOP_MAX) / OG_ZK_LOOP_MAX, MK_ZK_SWITCH);
+    if (mu > 5.0 || n > OG_ZK_LOOP_MAX) {
+        *gauss = 1;
+        *trials = 0;
+        const double sd = sqrt(mu * (1.0 - p));
+        const double z = og_ndtri(uniform_of(h0));
+        const double x = mu + sd * z;
+        if (x >= 0.5)   /* floor(x) decides the count; its error scale is mu + sd |z| */
+            upd_margin(mg, mk, fabs(x - floor(x + 0.5)) / (mu + sd * fabs(z) + 1.0), MK_COUNT);
+        const double c = floor(x);
+        return c > 0.0 ? c : 0.0;
+    }
+    *gauss = 0;
+    upd_margin(mg, mk, fabs(n + 0.5 - floor(n + 1.0)) / (n > 1.0 ? n : 1.0), MK_ZK_SWITCH);
+    const int t = (int)floor(n + 0.5);
+    *trials = t;
+    double c = 0.0;
+    for (int k = 1; k <= t; ++k) {
+        const double th = uniform_of(og_hash_step(h0, (uint32_t)k));
+        upd_margin(mg, mk, fabs(th - p) / (p > 0x1p-24 ? p : 0x1p-24), MK_GATE);
+        if (th < p) c += 1.0;
+    }
+    return c;
+}
+
+double og_zk_count(double n, double p, uint32_t h0, int *gauss, int *trials)
+{
+    double mg[2] = {INFINITY, INFINITY};
+    int mk[2] = {MK_NONE, MK_NONE};
+    return zk_count(n, p, h0, mg, mk, gauss, trials);
+}
+
+/* ------------------------------------------------------------------ */
 /* One pixel.                                                          */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -656,6 +712,25 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
             if (!lv[li]) continue;
             double p = pl[li];
             for (int g = 0; g < nodes.n; ++g) {
+                if (prm->count_law == 1) {
+                    /* Eq. 7 baseline: node g counts its whole cell (N A_g
+                     * trials) and its output enters with weight w_g */
+                    const double nz = N * ldexp(1.0, nodes.l[g]);
+                    for (int e = 0; e < 3; ++e)
+                        for (int a = 0; a < 4; ++a) {
+                            uint32_t h0 = gate_word(prm, pre[g][e], akey[li][a][0]);
+                            o->theta_sum += h0;
+                            o->n_gate++;
+                            int gauss, trials;
+                            double c = zk_count(nz, p, h0, mg, mk, &gauss, &trials);
+                            o->n_open += (uint32_t)gauss;
+                            o->n_live += (uint32_t)trials;
+                            o->count_sum += (uint32_t)c;
+                            if (c > 0.0 && li < 32) o->lit |= 1u << li;
+                            bsum[li] += nodes.w[g] * beta[g][e] * vw[li][a] * c;
+                        }
+                    continue;
+                }
                 /* Eq. 10: node g receives w_g N A_g trials */
                 double ng = nodes.w[g] * N * ldexp(1.0, nodes.l[g]);
                 double pg;
@@ -752,6 +827,7 @@ int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_
     if (!gb || !mats || n_mat <= 0 || n_light < 0 || n_light > 64 || !prm || !out_rgb) return -1;
     if (prm->k_max < 0 || prm->k_max > 4 || prm->n_probe_max < 1) return -1;
     if (prm->rng_log2 < 0 || prm->rng_log2 > 32) return -1;
+    if (prm->count_law != 0 && !(prm->count_law == 1 && prm->rounding == 0)) return -1;
     if (row0 < 0) row0 = 0;
     if (row1 > gb->height) row1 = gb->height;
     const int64_t npx = (int64_t)gb->height * gb->stride;
@@ -823,6 +899,7 @@ int og_grad(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_l
             int n_threads)
 {
     if (!gb || !mats || n_mat <= 0 || n_light <= 0 || n_light > 64 || !grad_out || !(step > 0.0)) return -1;
+    if (prm_in->count_law != 0) return -1;          /* the adjoint is the method's only */
     og_params prm = *prm_in;
     prm.rounding = 1;
     const int64_t npx = (int64_t)gb->height * gb->stride;
