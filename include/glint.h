@@ -99,11 +99,25 @@ typedef struct {
  * are split into ceil(r / 2^k_max) sub-footprints, at most n_probe_max.
  * rounding: 0 = counts floor(1 + mu + sigma z) (Eq. 18); 1 = relaxed counts
  * max(1, 1 + mu + sigma z) (the function the backward differentiates).
- * flags: reserved, must be 0. */
+ * flags: 0, or (glint_shade only) GLINT_FLAG_ZK_COUNT; every other entry
+ * point rejects a nonzero value with EINVAL. */
 typedef struct {
     int32_t k_max, n_probe_max, rounding;
     uint32_t flags;
 } glint_params;
+
+/* glint_params.flags bit: count with the prior-art law the method replaces
+ * (Zirr and Kaplanyan; Sec. 2, Eq. 7 and Sec. 6.3, Eq. 15), an A/B baseline
+ * on the same grids, texels and uniforms.  Grid node g counts its whole
+ * cell, n = N 2^l_g trials: when n p > 5 or n > 16 the count of a texel is
+ * max(0, floor(n p + sqrt(n p (1 - p)) Phi^-1(theta_0))), otherwise the
+ * number of k in 1..floor(n + 1/2) whose uniform of H(h0, k) is below p
+ * (h0 the texel's slot-0 word, theta_0 its uniform); the per-node outputs
+ * are summed with the node weights w_g (a mix of outputs, Eq. 7, instead of
+ * the distribution of trials, Eq. 10).  Requires rounding = 0.  Debug
+ * planes then count: n_open the texels on the Gaussian branch, n_live the
+ * Bernoulli trials drawn, count_sum the sum of the counts. */
+#define GLINT_FLAG_ZK_COUNT 1u
 
 /* Optional per-pixel debug planes of glint_shade (each [height*stride] or
  * NULL).  They hold exact integer fingerprints of every discrete decision, so
@@ -154,6 +168,8 @@ size_t glint_shade_workspace_bytes(int32_t width, int32_t height);
 /* Forward shading of one view: out_rgb[3][height*stride] <- radiance
  * L = sum_l E_l F G D_P / (4 <w,n>) with D_P = D(n) b / (R N P)
  * (Eqs. 1-4, 10, 14, 16-18).  n_mat in [1, 32], n_light in [0, 16].
+ * With params->flags = GLINT_FLAG_ZK_COUNT b is the baseline's mixed count
+ * instead (Eqs. 7 and 15; see that flag).
  * dbg may be NULL.
  * workspace: device memory of at least glint_shade_workspace_bytes(width,
  * height) bytes, 4-byte aligned, owned by the caller and used by this call

@@ -78,6 +78,19 @@ struct TileSmem {
 // numbers precomputed once).
 enum : int { kRngHash = 0, kRngTable = 1, kRngTableLds = 2 };
 
+// Counting law of the kernel:
+//   kLawDistributed  the method: distributed gated binomials (Eqs. 10, 16-18)
+//   kLawZk           the baseline it replaces (Zirr and Kaplanyan): every
+//                    node counts its whole cell, n = N 2^l trials, with the
+//                    classical approximation of Eq. 15 (a floored Gaussian
+//                    when n p > 5 or n > 16, else n Bernoulli trials), and
+//                    the node outputs are mixed with the weights w (Eq. 7)
+enum : int { kLawDistributed = 0, kLawZk = 1 };
+// an upper bound of every ndtri_bits value (the largest, for the uniform
+// 1 - 2^-24, is 5.33): a floored Gaussian count fma(sd, z, mu) is 0 for
+// every uniform when fma(sd, kZmaxBound, mu) < 1
+constexpr float kZmaxBound = 5.5f;
+
 template <int RNG>
 __device__ __forceinline__ uint32_t rng_word(uint32_t pre, uint32_t ak, const Shared &sh, const uint32_t *ltbl)
 {
@@ -97,10 +110,10 @@ __device__ __forceinline__ uint32_t rng_word(uint32_t pre, uint32_t ak, const Sh
 // Either way the chain is o.rgb = fma(E_l, f_l, o.rgb) over l = 0, 1, ...
 // with f_l = +0 for a light without an open gate, so the image has the same
 // bits.
-template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LK = 1>
+template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LK = 1, int LAW = kLawDistributed>
 __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v, const double n[3],
                                            const double wi[3], int kp, const Shared &sh, TileSmem<DEBUG> &sm,
-                                           ItemOut &o, const uint32_t *ltbl)
+                                           ItemOut &o, const uint32_t *ltbl, float zN = 0.0f)
 {
     static_assert(LK == 1 || (LK == 2 && !DEBUG), "two lanes per item only in the production kernels");
     const int lane = threadIdx.x;
@@ -127,6 +140,65 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
             LightEval le;
             if (!eval_light(n, wi, R.alpha, L, M, fr, le)) break;
             const float p = le.p;
+            if constexpr (LAW == kLawZk) {
+                // baseline counting law; R.ng holds the node weights w and zN
+                // the pixel's flake density N
+                uint32_t ak0[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
+                // a Bernoulli trial succeeds when (2k + 1) 2^-24 < p, k = h >> 9,
+                // i.e. k < ceil((p 2^24 - 1) / 2): exact in FP32
+                const float kf = ceilf((p * 16777216.0f - 1.0f) * 0.5f);
+                const uint32_t KB = kf >= 8388608.0f ? 8388608u : (kf > 0.0f ? (uint32_t)kf : 0u);
+                float bsum = 0.0f;
+                for (int g = 0; g < nn; ++g) {
+                    const float nz = ldexpf(zN, (int)(rec_node_word(R, g) & 0x7ffu) - 1024);   // N 2^l
+                    const float w = R.ng[g];
+                    const float mu = nz * p;
+                    if (mu > 5.0f || nz > 16.0f) {
+                        const float sd = __builtin_amdgcn_sqrtf(mu * (1.0f - p));
+                        if (!DEBUG && fmaf(sd, kZmaxBound, mu) < 1.0f) continue;
+                        for (int e = 0; e < 3; ++e) {
+                            const int ge = g * 3 + e;
+                            const float wb = w * sm.beta[ge][lane];
+                            const uint32_t pk = sm.pre[ge][lane];
+#pragma unroll
+                            for (int a = 0; a < 4; ++a) {
+                                const uint32_t h0 = hstep(pk, ak0[a]);
+                                const float c = fmaxf(floorf(fmaf(sd, ndtri_bits(h0), mu)), 0.0f);
+                                const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);
+                                bsum = fmaf(wb * va, c, bsum);
+                                if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_open += 1; o.count_sum += (uint32_t)c; }
+                            }
+                        }
+                    } else {
+                        const int t = (int)floorf(nz + 0.5f);
+                        if (!DEBUG && (t == 0 || KB == 0u)) continue;
+                        for (int e = 0; e < 3; ++e) {
+                            const int ge = g * 3 + e;
+                            const float wb = w * sm.beta[ge][lane];
+                            const uint32_t pk = sm.pre[ge][lane];
+#pragma unroll
+                            for (int a = 0; a < 4; ++a) {
+                                const uint32_t h0 = hstep(pk, ak0[a]);
+                                uint32_t c = 0u;
+                                for (int k = 1; k <= t; ++k) c += ((hstep(h0, (uint32_t)k) >> 9) < KB) ? 1u : 0u;
+                                const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);
+                                bsum = fmaf(wb * va, (float)c, bsum);
+                                if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_live += (uint32_t)t; o.count_sum += c; }
+                            }
+                        }
+                    }
+                }
+                if (DEBUG) o.b[li] = bsum;
+                if (!(bsum > 0.0f)) break;   // no count: the light adds exactly +0
+                if (DEBUG) o.n_lit += 1;
+                light_brdf(M, R.alpha, le);
+                const float G = 1.0f / ((1.0f + R.lam_i) * (1.0f + le.lam_o));
+                f = le.F * G * R.kpx * bsum;
+                break;
+            }
             const float lp = log1m(p);
             uint32_t K[4], anyK = 0u;
 #pragma unroll
@@ -246,10 +318,10 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 // ---------------------------------------------------------------------------
 // One tile of 64 pixels (tile_w x 64/tile_w) at (x0, y0) of a view.
 // ---------------------------------------------------------------------------
-template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false>
+template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LAW = kLawDistributed>
 __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
                            int lw, TileSmem<DEBUG> &sm, const uint32_t *ltbl = nullptr, uint16_t *lit = nullptr,
-                           uint32_t *lit_probes = nullptr)
+                           uint32_t *lit_probes = nullptr, float *zden = nullptr)
 {
     const int lane = threadIdx.x;
     const int tmask = (1 << lw) - 1;
@@ -267,6 +339,12 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
         if (px.flags & F_SHADED) {
             npr = px.npr;
             sm.rec[lane] = make_rec(px, sh);
+            if constexpr (LAW == kLawZk) {
+                // the baseline needs the node weights and N, not their products
+#pragma unroll
+                for (int g = 0; g < 4; ++g) sm.rec[lane].ng[g] = px.nw[g];
+                zden[lane] = px.N;
+            }
         }
         if (DEBUG) {
             dflags = px.flags;
@@ -305,12 +383,14 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             ItemOut o;
+            const float zN = LAW == kLawZk ? zden[p] : 0.0f;
             if (DEBUG || lk == 1)
-                shade_item<DEBUG, HEAD, RNG, LIT, 1>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi, kp,
-                                                     sh, sm, o, ltbl);
+                shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi,
+                                                          kp, sh, sm, o, ltbl, zN);
             else
-                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx],
-                                                                 n, wi, kp, sh, sm, o, ltbl);
+                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2, LAW>(sm.rec[p], (double)vw.u[pidx],
+                                                                      (double)vw.v[pidx], n, wi, kp, sh, sm, o,
+                                                                      ltbl, zN);
             if constexpr (DEBUG) {
                 sm.dslot[lane] = o;
             } else {
@@ -387,7 +467,9 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
 // opened a gate in any of the pixel's probes (lit[y * stride + x]) and, if
 // lit_probes is given, the bit mask of the probes that opened one (bit k:
 // probe k, bit 31: probe 31 or a later one).
-template <bool DEBUG, int RNG = kRngHash, bool LIT = false>
+// With LAW = kLawZk the dynamic LDS holds the tile's flake densities
+// (64 floats).
+template <bool DEBUG, int RNG = kRngHash, bool LIT = false, int LAW = kLawDistributed>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 4))) void glint_fwd_kernel(
     ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles,
     uint16_t *__restrict__ lit, uint32_t *__restrict__ lit_probes)
@@ -405,8 +487,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 
         __syncthreads();
         ltbl = reinterpret_cast<const uint32_t *>(glint_rng_lds);
     }
-    shade_tile<DEBUG, RNG == kRngHash, RNG, LIT>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, ltbl, lit,
-                                                lit_probes);
+    float *zden = LAW == kLawZk ? reinterpret_cast<float *>(glint_rng_lds) : nullptr;
+    shade_tile<DEBUG, RNG == kRngHash, RNG, LIT, LAW>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, ltbl, lit,
+                                                     lit_probes, zden);
 }
 
 // Random-number table: t[i] = H(seed, i) for i < n.
@@ -817,11 +900,13 @@ size_t glint_shade_workspace_bytes(int32_t width, int32_t height) { return tile_
 }  // extern "C"
 
 // Shared body of glint_shade and glint_shade_rng_table: tile order, then one
-// launch of the shading kernel with the uniforms' source RNG.
+// launch of the shading kernel with the uniforms' source RNG and the counting
+// law (kLawZk only with hashed uniforms and without lit masks).
 static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb, const glint_debug *dbg,
                           void *workspace, size_t workspace_bytes, int rng, size_t lds_bytes, uint16_t *lit,
-                          uint32_t *lit_probes, void *stream)
+                          uint32_t *lit_probes, void *stream, int law = kLawDistributed)
 {
+    if (law == kLawZk && (rng != kRngHash || lit)) return GLINT_EUNSUPPORTED;
     ViewDesc vw;
     int rc = make_view(gbuf, out_rgb, vw);
     if (rc) return rc;
@@ -841,7 +926,10 @@ static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb,
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light,
                           dbg->n_live_small, dbg->n_lit};
-        if (rng == kRngHash)
+        if (law == kLawZk)
+            hipLaunchKernelGGL((glint_fwd_kernel<true, kRngHash, false, kLawZk>), grid, block, kWave * sizeof(float),
+                               st, vw, sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
+        else if (rng == kRngHash)
             hipLaunchKernelGGL(glint_fwd_kernel<true>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
                                (int32_t)nt, nullptr, nullptr);
         else
@@ -849,7 +937,10 @@ static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb,
                                tiles_x, order, (int32_t)nt, nullptr, nullptr);
     } else {
         DebugPlanes dp = {};
-        if (rng == kRngHash && lit)
+        if (law == kLawZk)
+            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngHash, false, kLawZk>), grid, block, kWave * sizeof(float),
+                               st, vw, sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
+        else if (rng == kRngHash && lit)
             hipLaunchKernelGGL((glint_fwd_kernel<false, kRngHash, true>), grid, block, 0, st, vw, sh, dp, kTileLw,
                                tiles_x, order, (int32_t)nt, lit, lit_probes);
         else if (rng == kRngHash)
@@ -873,9 +964,11 @@ int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n
                 void *workspace, size_t workspace_bytes, void *stream)
 {
     Shared sh;
-    int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh);
+    int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh, GLINT_FLAG_ZK_COUNT);
     if (rc) return rc;
-    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, kRngHash, 0, nullptr, nullptr, stream);
+    const int law = (params->flags & GLINT_FLAG_ZK_COUNT) ? kLawZk : kLawDistributed;
+    return launch_forward(gbuf, sh, out_rgb, dbg, workspace, workspace_bytes, kRngHash, 0, nullptr, nullptr, stream,
+                          law);
 }
 
 int glint_shade_lit(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat, const glint_light *lights,

@@ -38,14 +38,17 @@ int enqueue_tile_order(const ViewDesc &vw, const Shared &sh, void *ws, size_t ws
 inline bool finite_host(float x) { return std::isfinite(x); }
 
 // Validates materials / lights / params and fills the kernel-argument block.
+// allowed_flags: the params.flags bits the calling entry point accepts.
 inline int prepare_shared(const glint_material *mats, int32_t n_mat, const glint_light *lights,
-                          int32_t n_light, const glint_params *prm, Shared &sh)
+                          int32_t n_light, const glint_params *prm, Shared &sh, uint32_t allowed_flags = 0u)
 {
     if (!mats || !prm || (n_light > 0 && !lights)) return GLINT_ENULL;
     if (n_mat < 1 || n_mat > kMaxMat || n_light < 0 || n_light > kMaxLight) return GLINT_EINVAL;
     if (prm->k_max < 0 || prm->k_max > GLINT_MAX_K || prm->n_probe_max < 1 ||
-        prm->n_probe_max > GLINT_MAX_PROBES || (prm->rounding != 0 && prm->rounding != 1) || prm->flags != 0)
+        prm->n_probe_max > GLINT_MAX_PROBES || (prm->rounding != 0 && prm->rounding != 1) ||
+        (prm->flags & ~allowed_flags) != 0u)
         return GLINT_EINVAL;
+    if ((prm->flags & GLINT_FLAG_ZK_COUNT) && prm->rounding != 0) return GLINT_EINVAL;   // integer counts
     std::memset(&sh, 0, sizeof(sh));
     for (int i = 0; i < n_mat; ++i) {
         const glint_material &m = mats[i];

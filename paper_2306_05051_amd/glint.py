@@ -26,6 +26,8 @@ GLINT_EHIP, GLINT_EUNSUPPORTED, GLINT_ENOMEM = -4, -5, -6
 GLINT_MAX_MATERIALS, GLINT_MAX_LIGHTS, GLINT_MAX_K, GLINT_MAX_PROBES = 32, 16, 4, 64
 GLINT_RNG_TABLE_MIN_LOG2, GLINT_RNG_TABLE_MAX_LOG2, GLINT_RNG_LDS_MAX_LOG2 = 8, 32, 13
 GLINT_RNG_CACHED, GLINT_RNG_LDS = 0, 1
+GLINT_FLAG_ZK_COUNT = 1
+LAW_DISTRIBUTED, LAW_ZK = 0, 1      # counting laws of glint_shade (count_law=)
 MAX_MATERIALS, MAX_LIGHTS = 32, 16
 
 
@@ -167,8 +169,10 @@ def make_lights(lights):
     return arr
 
 
-def make_params(k_max=4, n_probe_max=21, rounding=0):
-    return _Params(int(k_max), int(n_probe_max), int(rounding), 0)
+def make_params(k_max=4, n_probe_max=21, rounding=0, count_law=LAW_DISTRIBUTED):
+    if count_law not in (LAW_DISTRIBUTED, LAW_ZK):
+        raise ValueError("count_law must be LAW_DISTRIBUTED or LAW_ZK")
+    return _Params(int(k_max), int(n_probe_max), int(rounding), GLINT_FLAG_ZK_COUNT if count_law == LAW_ZK else 0)
 
 
 def to_device(gb_np, device="cuda"):
@@ -186,13 +190,16 @@ def glint_shade_workspace_bytes(width, height):
 
 
 def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, out=None, debug=False,
-                workspace=None, stream=None):
+                workspace=None, stream=None, count_law=LAW_DISTRIBUTED):
     """Radiance [3, H, W] float32 (and a dict of debug planes when debug=True).
 
     workspace: None allocates the tile-order workspace (heaviest tiles first),
     False shades the tiles in row-major order without one, a uint8 CUDA tensor
-    of at least glint_shade_workspace_bytes(W, H) bytes is used as given."""
-    return _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, None)
+    of at least glint_shade_workspace_bytes(W, H) bytes is used as given.
+    count_law: LAW_DISTRIBUTED (the method) or LAW_ZK (the Zirr-Kaplanyan
+    baseline, GLINT_FLAG_ZK_COUNT; rounding must be 0)."""
+    return _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, None,
+                  count_law)
 
 
 RNG_CACHED, RNG_LDS = GLINT_RNG_CACHED, GLINT_RNG_LDS
@@ -223,7 +230,8 @@ def glint_shade_rng_table(gbuf, materials, lights, table, log2_words, placement=
     return _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, rng)
 
 
-def _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, rng):
+def _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, rng,
+           count_law=LAW_DISTRIBUTED):
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
@@ -249,7 +257,7 @@ def _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, wo
         for n in WORK_FIELDS:
             planes[n] = torch.zeros((H, W), dtype=torch.int32, device=dev)
             setattr(dbg, n, planes[n].data_ptr())
-    prm = make_params(k_max, n_probe_max, rounding)
+    prm = make_params(k_max, n_probe_max, rounding, count_law)
     if rng is None:
         st = glint_shade_raw(g, make_materials(materials), len(materials), make_lights(lights), len(lights),
                              prm, _dev_ptr(out, torch.float32, "out"), dbg, _stream(stream), ws_ptr, ws_bytes)

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2306_05051_amd import scenes
-from parity_util import compare, dbg_to_numpy
+from parity_util import MARGIN, compare, dbg_to_numpy
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -200,6 +200,65 @@ def test_no_lights_and_empty(glint):
     empty = {k: v[:0] for k, v in dgb.items()}
     out = glint.glint_shade(empty, mats, lights)
     assert out.numel() == 0
+
+
+@pytest.mark.parametrize("case", ["sphere", "four_k", "plane25_sparse", "plane25", "four_k_K0"])
+def test_zk_baseline_law(glint, case):
+    """The Zirr-Kaplanyan baseline (GLINT_FLAG_ZK_COUNT: Eq. 15 per texel on
+    the node's whole cell, node outputs mixed as in Eq. 7) against the
+    oracle's count_law=1: flags, keys, per-texel uniforms, Gaussian draws
+    (n_open) and every integer count (count_sum) bit-exact, radiance within
+    the bar; the production kernel (which skips nodes whose counts are all
+    zero) gives the instrumented kernel's bits."""
+    kw = {}
+    if case == "sphere":
+        gb, mats, lights = scenes.sphere_forward(256, 144, seed=4)
+    elif case == "four_k":
+        gb, mats, lights = scenes.four_k(192, 108, seed=6)
+    elif case == "plane25_sparse":
+        gb, mats, lights = scenes.paper_setting(192, 108, view="plane25", log10_density=3.0, seed=2)
+    elif case == "plane25":
+        gb, mats, lights = scenes.paper_setting(192, 108, view="plane25", log10_density=5.0, seed=2)
+    else:
+        gb, mats, lights = scenes.four_k(128, 96, seed=9, n_light=3)
+        kw = dict(k_max=0)
+    grgb, gdbg = _run(glint, gb, mats, lights, count_law=glint.LAW_ZK, **kw)
+    rrgb, rdbg = oracle.shade(gb, mats, lights, debug=True, count_law=1, **kw)
+    st = compare(grgb, gdbg, rrgb, rdbg, label=f"zk {case}")
+    shaded = (rdbg["flags"] & 1) > 0
+    trials = int(gdbg["n_live"][shaded].astype(np.int64).sum())
+    gauss = int(gdbg["n_open"][shaded].astype(np.int64).sum())
+    print(f"  zk {case}: {st}; Bernoulli trials {trials}, Gaussian draws {gauss}", flush=True)
+    assert st["checked"] > 0.9 * st["shaded"] and st["nonzero"] > 1000
+    # both branches of Eq. 15 run (trials are compared through count_sum)
+    assert trials > 0 and gauss > 0
+    # and so do the trials drawn, on every compared pixel
+    m = shaded & (rdbg["margin_pos"] >= MARGIN)
+    assert np.array_equal(gdbg["n_live"][m].astype(np.int64) & 0xFFFFFFFF, rdbg["n_live"][m].astype(np.int64))
+
+
+def test_zk_baseline_differs_from_the_method(glint):
+    """Same grids, texels and uniforms, other counting law: the images differ
+    while both match their oracle (guards against a flag that is ignored)."""
+    gb, mats, lights = scenes.four_k(96, 64, seed=11)
+    dgb = glint.to_device(gb)
+    a = glint.glint_shade(dgb, mats, lights)
+    b = glint.glint_shade(dgb, mats, lights, count_law=glint.LAW_ZK)
+    torch.cuda.synchronize()
+    assert not torch.equal(a, b)
+
+
+def test_zk_baseline_rejected_where_unsupported(glint):
+    gb, mats, lights = scenes.ragged_plane(8, 8, seed=3)
+    dgb = glint.to_device(gb)
+    with pytest.raises(glint.GlintError) as e:
+        glint.glint_shade(dgb, mats, lights, rounding=1, count_law=glint.LAW_ZK)
+    assert e.value.status == glint.GLINT_EINVAL
+    table = glint.glint_rng_table_fill(8, 1)
+    with pytest.raises(glint.GlintError) as e:
+        glint._shade(dgb, mats, lights, 4, 21, 0, None, False, None, None,
+                     (table.data_ptr(), 8, glint.RNG_CACHED), glint.LAW_ZK)
+    assert e.value.status == glint.GLINT_EINVAL
 
 
 def test_bad_arguments_rejected(glint):
