@@ -15,7 +15,9 @@ footprint (Sec. 2, Eq. 7).  Pinned here against what mathematics fixes:
   sum_g w_g^2 Var[c_g]: with the isotropic family (k_max = 0) the nodes are
   the two LOD levels of Eq. 7, and at mid-blend the variance falls to about
   half of the flake model's N P p (1 - p), the incorrect statistics Sec. 2
-  predicts for this interpolation, while the distributed law keeps it.
+  predicts for this interpolation, while the distributed law keeps it;
+* ghost flakes: at a lattice point the method counts whole flakes at every
+  footprint area, the baseline shows half-intensity flakes at mid-blend.
 """
 import math
 
@@ -171,3 +173,22 @@ def test_baseline_needs_integer_counts():
         oracle.shade(g, mats, lights, rounding=1, count_law=1)
     with pytest.raises(ValueError):
         oracle.shade(g, mats, lights, count_law=2)
+
+
+def test_ghost_flakes_at_mid_blend():
+    """Sec. 2's ghosting: mixing the outputs of two LOD levels shows flakes at
+    fractional intensity.  At a lattice-aligned point (one texel per node) the
+    method's count is a whole number of flakes at every footprint area; the
+    baseline's is (1 - t) c_lo + t c_hi, half-integers at mid-blend whenever
+    the two levels disagree in parity."""
+    S = 2000
+    P = 1.5 * 2.0**-20
+    dbg0, _, _, _, _ = _pixel_sample(S, P, 9.0, 0, 0)
+    b0 = dbg0["b_light"][0, 0]
+    # one angular texel carries (almost) all the weight: distance to the nearest integer is tiny
+    assert np.max(np.abs(b0 - np.round(b0))) < 1e-3 * np.max(b0)
+    dbg1, _, _, _, _ = _pixel_sample(S, P, 9.0, 1, 0)
+    b1 = dbg1["b_light"][0, 0]
+    frac = np.abs(b1 - np.round(b1))
+    ghost = np.mean(frac > 0.25)
+    assert 0.35 < ghost < 0.65, ghost       # about half the pixels show a half-intensity flake
