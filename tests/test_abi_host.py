@@ -38,7 +38,7 @@ def test_limits_match_header():
     txt = open(HEADER).read()
     for name in ("GLINT_MAX_MATERIALS", "GLINT_MAX_LIGHTS", "GLINT_MAX_K", "GLINT_MAX_PROBES",
                  "GLINT_RNG_TABLE_MIN_LOG2", "GLINT_RNG_TABLE_MAX_LOG2", "GLINT_RNG_LDS_MAX_LOG2",
-                 "GLINT_RNG_CACHED", "GLINT_RNG_LDS"):
+                 "GLINT_RNG_CACHED", "GLINT_RNG_LDS", "GLINT_FLAG_ZK_COUNT"):
         m = re.search(r"#define " + name + r"\s+(\d+)", txt)
         assert m and int(m.group(1)) == getattr(glint, name), name
 
@@ -102,6 +102,22 @@ def test_host_validation_without_device(lib):
     assert L.glint_rng_table_fill(tbl, 7, 0, None) == glint.GLINT_EINVAL
     assert L.glint_rng_table_fill(tbl, 33, 0, None) == glint.GLINT_EINVAL
     assert L.glint_rng_table_fill(C.c_void_p((1 << 20) + 8), 12, 0, None) == glint.GLINT_EINVAL
+    # the baseline counting law: glint_shade only, integer counts only, no unknown flag bits
+    zk = glint.make_params(count_law=glint.LAW_ZK)
+    assert zk.flags == glint.GLINT_FLAG_ZK_COUNT
+    zk_relaxed = glint.make_params(rounding=1, count_law=glint.LAW_ZK)
+    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(zk_relaxed), fake_out, None, None, 0,
+                         None) == glint.GLINT_EINVAL
+    unknown = glint.make_params()
+    unknown.flags = 2
+    assert L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(unknown), fake_out, None, None, 0,
+                         None) == glint.GLINT_EINVAL
+    assert shade_t(C.byref(g), mats, 1, lts, 1, C.byref(zk), tbl, 12, 0, fake_out, None, None, 0,
+                   None) == glint.GLINT_EINVAL
+    assert L.glint_shade_lit(C.byref(g), mats, 1, lts, 1, C.byref(zk), fake_out, C.c_void_p(4096), None, None, 0,
+                             None) == glint.GLINT_EINVAL
+    with pytest.raises(ValueError):
+        glint.make_params(count_law=2)
     # lit-light mask: NULL and misaligned planes
     lit_args = lambda l, pr: (C.byref(g), mats, 1, lts, 1, C.byref(prm), fake_out, l, pr, None, 0, None)
     assert L.glint_shade_lit(*lit_args(None, None)) == glint.GLINT_ENULL
