@@ -113,6 +113,9 @@ def lib():
                                  C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.og_gated_count.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]
         L.og_gated_count.restype = C.c_double
+        L.og_onb.argtypes = [C.c_double * 3, C.c_double * 3, C.c_double * 3]
+        L.og_probe_centre.argtypes = [C.c_double] * 4 + [C.c_int, C.c_int, C.POINTER(C.c_double),
+                                                         C.POINTER(C.c_double)]
         L.og_zk_count.argtypes = [C.c_double, C.c_double, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.og_zk_count.restype = C.c_double
         _lib = L
@@ -292,3 +295,18 @@ def zk_count(n, p, h0):
     g, t = C.c_int(), C.c_int()
     c = lib().og_zk_count(float(n), float(p), h0 & 0xFFFFFFFF, C.byref(g), C.byref(t))
     return c, g.value, t.value
+
+
+def tangent_frame(n):
+    """(t, b) of the unit normal n: the frame whose axes index the angular grid."""
+    t, b = (C.c_double * 3)(), (C.c_double * 3)()
+    lib().og_onb((C.c_double * 3)(*[float(x) for x in n]), t, b)
+    return list(t), list(b)
+
+
+def probe_centre(u, v, phi, sigma0, n_pr, kp):
+    """Centre of sub-footprint kp of n_pr along the footprint's major axis."""
+    cx, cy = C.c_double(), C.c_double()
+    lib().og_probe_centre(float(u), float(v), float(phi), float(sigma0), int(n_pr), int(kp),
+                          C.byref(cx), C.byref(cy))
+    return cx.value, cy.value

@@ -38,9 +38,13 @@
  * simulation for mean and variance of the distributed count; convergence
  * of the seed-averaged glint NDF to D(h); continuity across level, ratio,
  * orientation and lattice boundaries; frozen-branch finite differences
- * against free finite differences.  The hash and the angular cell size are
- * definitions of this implementation: parity unpinned beyond their
- * statistical tests (uniformity, independence) and the bit-exact match.
+ * against free finite differences; the tangent frame orthonormal and
+ * right-handed; the probe centres splitting the major axis into equal
+ * segments; the Zirr-Kaplanyan baseline's branches against the binomial
+ * and the floored-Gaussian closed forms, and its variance deficit.  The
+ * hash and the angular cell size are definitions of this implementation:
+ * parity unpinned beyond their statistical tests (uniformity,
+ * independence) and the bit-exact match.
  */
 #include <math.h>
 #include <stdint.h>
@@ -269,6 +273,22 @@ static void onb(const double n[3], double t[3], double b[3])
     double bb = n[0] * n[1] * a;
     t[0] = 1.0 + sgn * n[0] * n[0] * a; t[1] = sgn * bb; t[2] = -sgn * n[0];
     b[0] = bb; b[1] = sgn + n[1] * n[1] * a; b[2] = -n[1];
+}
+
+void og_onb(const double n[3], double t[3], double b[3]) { onb(n, t, b); }   /* for the pin tests */
+
+/* centre of sub-footprint kp of n_pr (Sec. 4.2, reading S25): uniform along
+ * the major axis (angle phi) over the major-axis length sigma0 */
+static void probe_centre(double u, double v, double phi, double sigma0, int n_pr, int kp, double *cx, double *cy)
+{
+    double off = ((kp + 0.5) / n_pr - 0.5) * sigma0;
+    *cx = u + off * cos(phi);
+    *cy = v + off * sin(phi);
+}
+
+void og_probe_centre(double u, double v, double phi, double sigma0, int n_pr, int kp, double *cx, double *cy)
+{
+    probe_centre(u, v, phi, sigma0, n_pr, kp, cx, cy);
 }
 
 static double dot3(const double a[3], const double b[3]) { return a[0]*b[0] + a[1]*b[1] + a[2]*b[2]; }
@@ -694,9 +714,8 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
     for (int li = 0; li < NL; ++li) bsum[li] = 0.0;
 
     for (int kp = 0; kp < n_pr; ++kp) {
-        /* probe centre: uniform along the major axis over length sigma0 */
-        double off = ((kp + 0.5) / n_pr - 0.5) * sigma0;
-        double cx = in->u + off * cos(phi), cy = in->v + off * sin(phi);
+        double cx, cy;
+        probe_centre(in->u, in->v, phi, sigma0, n_pr, kp, &cx, &cy);
         int vi[OG_MAX_NODES][3], vj[OG_MAX_NODES][3];
         double beta[OG_MAX_NODES][3];
         uint32_t pre[OG_MAX_NODES][3];

@@ -359,3 +359,51 @@ def test_simplex_reconstruction():
         (x0, y0), (x1, y1), (x2, y2) = pts
         tri = 0.5 * abs((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0))
         assert tri == pytest.approx(0.5 * 2.0**l, rel=1e-9)
+
+
+def test_tangent_frame_orthonormal_right_handed():
+    """The frame that indexes the angular grid (Duff et al.'s branchless ONB,
+    a choice) must be an orthonormal right-handed basis with n as third axis,
+    so that the projected half vector (<h,t>, <h,b>) keeps |.|^2 = 1 - <h,n>^2
+    and h = n lands on the grid origin."""
+    rng = np.random.default_rng(5)
+    ns = rng.normal(size=(3000, 3))
+    ns = np.concatenate([ns, [[0, 0, 1], [0, 0, -1], [1, 0, 0], [0, 1, 1e-12], [1e-9, 0, -1],
+                              [0.3, -0.2, -1e-15]]])
+    ns /= np.linalg.norm(ns, axis=1, keepdims=True)
+    for n in ns:
+        t, b = (np.array(x) for x in oracle.tangent_frame(n))
+        M = np.stack([t, b, n])
+        assert np.allclose(M @ M.T, np.eye(3), atol=1e-12), n
+        assert np.allclose(np.cross(t, b), n, atol=1e-12), n
+        h = rng.normal(size=3)
+        h /= np.linalg.norm(h)
+        assert np.dot(h, t) ** 2 + np.dot(h, b) ** 2 == pytest.approx(1.0 - np.dot(h, n) ** 2, abs=1e-12)
+
+
+def test_probe_centres_partition_the_major_axis():
+    """Sec. 4.2 with reading S25: the n_pr sub-footprints of an over-long
+    footprint sit on its major axis (the leading singular vector of J) and
+    split the ellipse's major-axis extent [-sigma0/2, sigma0/2] into equal,
+    contiguous segments centred on the pixel."""
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        J = rng.normal(size=(2, 2)) * 10.0 ** rng.uniform(-4, -1)
+        fp = oracle.footprint(J[0, 0], J[1, 0], J[0, 1], J[1, 1])
+        if fp is None:
+            continue
+        P, r, phi, s0 = fp
+        U, S, Vt = np.linalg.svd(J)
+        axis = np.array([math.cos(phi), math.sin(phi)])
+        assert abs(abs(np.dot(axis, U[:, 0])) - 1.0) < 1e-9
+        assert s0 == pytest.approx(S[0], rel=1e-12)
+        u, v = rng.uniform(-3, 3, size=2)
+        for n_pr in (1, 2, 3, 7, 21):
+            c = np.array([oracle.probe_centre(u, v, phi, s0, n_pr, k) for k in range(n_pr)])
+            d = (c - [u, v]) @ axis                          # along the major axis
+            perp = (c - [u, v]) @ np.array([-axis[1], axis[0]])
+            assert np.allclose(perp, 0.0, atol=1e-12 * (abs(u) + abs(v) + s0))
+            assert np.mean(d) == pytest.approx(0.0, abs=1e-12 * (abs(u) + abs(v) + s0))
+            lo, hi = d - s0 / (2 * n_pr), d + s0 / (2 * n_pr)
+            assert lo[0] == pytest.approx(-s0 / 2, rel=1e-9) and hi[-1] == pytest.approx(s0 / 2, rel=1e-9)
+            assert np.allclose(lo[1:], hi[:-1], rtol=0, atol=1e-9 * s0)
