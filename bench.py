@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-count", action="store_true", help="skip the instrumented unit-count run")
     ap.add_argument("--batched", action="store_true", help="also time the batched multi-view path")
+    ap.add_argument("--batched-tune", default=None,
+                    help="tile_w,tile_h,blocks_per_cu for the batched path instead of autotuning it")
     ap.add_argument("--no-backward", action="store_true", help="skip the forward+backward timing")
     ap.add_argument("--scene-cache", default=None, help="npz file to load the 4K scene from / save it to")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -239,9 +241,13 @@ def main():
         views, bm, bl = scenes.batched_views(n_views=64, seed=4)
         dviews = [glint.to_device(v) for v in views]
         outs = [torch.empty((3,) + v["u"].shape, device="cuda") for v in dviews]
-        from paper_2306_05051_amd.autotune import autotune
-        best, tt = autotune(dviews, outs, bm, bl, reps=1)
-        log("autotuned batched shape", best, {k: round(v, 3) for k, v in tt.items()})
+        if args.batched_tune:
+            best = tuple(int(x) for x in args.batched_tune.split(","))
+            log("batched shape (given)", best)
+        else:
+            from paper_2306_05051_amd.autotune import autotune
+            best, tt = autotune(dviews, outs, bm, bl, reps=1)
+            log("autotuned batched shape", best, {k: round(v, 3) for k, v in tt.items()})
         plan = glint.GlintPlan(dviews, outs, bm, bl, tune=best)
         plan.run(use_graph=True)
         torch.cuda.synchronize()

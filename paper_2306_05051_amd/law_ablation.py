@@ -46,6 +46,7 @@ def main():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--no-4k", action="store_true")
+    ap.add_argument("--only-4k", action="store_true")
     args = ap.parse_args()
 
     import torch
@@ -90,7 +91,7 @@ def main():
         gb, mats, lights = scenes.four_k()
         frames.append(("4k", None, None, gb, mats, lights, (4,)))
     W, H = args.width, args.height
-    for view in scenes.PAPER_VIEWS:
+    for view in (() if args.only_4k else scenes.PAPER_VIEWS):
         gb, _, lights = scenes.paper_setting(W, H, view=view, log10_density=5.0)
         for d in DENSITIES:
             _, mats, _ = scenes.paper_setting(16, 16, view=view, log10_density=d)
@@ -118,7 +119,7 @@ def main():
                   f"(tile max {row['zk_tile_max_trials']:.1f}, max {row['zk_trials_max']}); "
                   f"radiance zk/dist {row['radiance_zk_vs_distributed']:.4f}", file=sys.stderr, flush=True)
     summary = []
-    for view in scenes.PAPER_VIEWS:
+    for view in (() if args.only_4k else scenes.PAPER_VIEWS):
         for k in K_LEVELS:
             rs = [x for x in result["rows"] if x["view"] == view and x["k_max"] == k]
             e = {}
