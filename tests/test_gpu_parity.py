@@ -323,19 +323,21 @@ def test_tile_order_is_a_heaviest_first_permutation(glint):
         assert np.mean(np.diff(idx) > 0) > 0.99
 
 
-def test_full_4k_sampled_rows(glint):
-    """Full-size 3840x2160 frame in the benchmark's launch configuration;
-    the oracle recomputes sampled rows."""
+@pytest.mark.parametrize("count_law", [0, 1], ids=["method", "zk_baseline"])
+def test_full_4k_sampled_rows(glint, count_law):
+    """Full-size 3840x2160 frame in the benchmark's launch configuration (and
+    the same frame under the Zirr-Kaplanyan baseline); the oracle recomputes
+    sampled rows."""
     gb, mats, lights = scenes.four_k(3840, 2160, seed=3)
     dgb = glint.to_device(gb)
-    print("  full 4K frame", flush=True)
-    rgb = glint.glint_shade(dgb, mats, lights)
+    print(f"  full 4K frame, count law {count_law}", flush=True)
+    rgb = glint.glint_shade(dgb, mats, lights, count_law=count_law)
     torch.cuda.synchronize()
     rgb = rgb.cpu().numpy()
     rows = [0, 7, 8, 500, 1079, 1080, 1501, 2159]
     for r in rows:
         sub = {k: v[r:r + 1] for k, v in gb.items()}
-        rrgb, rdbg = oracle.shade(sub, mats, lights, debug=True)
+        rrgb, rdbg = oracle.shade(sub, mats, lights, debug=True, count_law=count_law)
         ok = ((rdbg["flags"] & 1) > 0) & (rdbg["margin_pos"] >= 1e-5)
         g = rgb[:, r:r + 1].astype(np.float64)
         err = np.abs(g - rrgb)[:, ok]
