@@ -8,7 +8,8 @@ the product: the two implementations share no code.  See the header of
 
 Inputs are the same FP32 G-buffer planes the GPU reads, given as a dict of
 numpy arrays of shape (H, W): u, v, dudx, dvdx, dudy, dvdy, nx, ny, nz,
-wx, wy, wz, optional material_id (int32), alpha_px, log10_density_px.
+wx, wy, wz, optional material_id (int32), alpha_px, log10_density_px and
+tangent planes tx, ty, tz (all three or none).
 Materials are dicts with keys ndf, alpha, R, log10_density,
 micro_roughness, F0, seed; lights are dicts with keys dir, radiance.
 """
@@ -30,7 +31,7 @@ PLANES = ("u", "v", "dudx", "dvdx", "dudy", "dvdy", "nx", "ny", "nz", "wx", "wy"
 FLAG_SHADED, FLAG_CLAMP_RATIO, FLAG_CLAMP_P, FLAG_BAD_INPUT = 1, 2, 4, 8
 FLAG_BACKFACING, FLAG_SKIPPED, FLAG_BAD_MAT = 16, 32, 64
 MARGIN_KINDS = ("none", "nprobe", "ratio", "orient", "triangle", "tetra", "lattice",
-                "angular", "gate", "count", "light", "view", "zk_switch")
+                "angular", "gate", "count", "light", "view", "zk_switch", "pclamp", "tangent")
 
 
 def build(force: bool = False) -> str:
@@ -46,7 +47,8 @@ def build(force: bool = False) -> str:
 class _GBuf(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("stride", C.c_int64)] + \
                [(n, C.c_void_p) for n in PLANES] + \
-               [("material_id", C.c_void_p), ("alpha_px", C.c_void_p), ("log10_density_px", C.c_void_p)]
+               [("material_id", C.c_void_p), ("alpha_px", C.c_void_p), ("log10_density_px", C.c_void_p),
+                ("tx", C.c_void_p), ("ty", C.c_void_p), ("tz", C.c_void_p)]
 
 
 class _Mat(C.Structure):
@@ -114,6 +116,10 @@ def lib():
         L.og_gated_count.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]
         L.og_gated_count.restype = C.c_double
         L.og_onb.argtypes = [C.c_double * 3, C.c_double * 3, C.c_double * 3]
+        L.og_tangent_frame.argtypes = [C.c_double * 3] * 4
+        L.og_tangent_frame.restype = C.c_int
+        L.og_angular_texels.argtypes = [C.c_double * 3, C.c_double * 3, C.c_double * 3, C.c_double,
+                                        C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_double * 4]
         L.og_probe_centre.argtypes = [C.c_double] * 4 + [C.c_int, C.c_int, C.POINTER(C.c_double),
                                                          C.POINTER(C.c_double)]
         L.og_zk_count.argtypes = [C.c_double, C.c_double, C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -135,7 +141,8 @@ def _gbuf(gb):
         a = np.ascontiguousarray(gb[n], dtype=np.float32)
         keep[n] = a
         setattr(s, n, a.ctypes.data)
-    for n, dt in (("material_id", np.int32), ("alpha_px", np.float32), ("log10_density_px", np.float32)):
+    for n, dt in (("material_id", np.int32), ("alpha_px", np.float32), ("log10_density_px", np.float32),
+                  ("tx", np.float32), ("ty", np.float32), ("tz", np.float32)):
         if gb.get(n) is not None:
             a = np.ascontiguousarray(gb[n], dtype=dt)
             keep[n] = a
@@ -302,6 +309,25 @@ def tangent_frame(n):
     t, b = (C.c_double * 3)(), (C.c_double * 3)()
     lib().og_onb((C.c_double * 3)(*[float(x) for x in n]), t, b)
     return list(t), list(b)
+
+
+def frame_of_tangent(n, t):
+    """(t, b) of the unit normal n and a supplied tangent t (made orthogonal to
+    n, b = n x t), or None when t is (nearly) parallel to n."""
+    to, bo = (C.c_double * 3)(), (C.c_double * 3)()
+    ok = lib().og_tangent_frame((C.c_double * 3)(*[float(x) for x in n]),
+                                (C.c_double * 3)(*[float(x) for x in t]), to, bo)
+    return (list(to), list(bo)) if ok else None
+
+
+def angular_texels(h, t, b, micro):
+    """Lower-left angular texel (ai, aj) of the half vector h in the frame
+    (t, b) with cells of size micro, and the bilinear weights v[a] of texels
+    (ai + (a & 1), aj + (a >> 1)) (Eq. 14)."""
+    ai, aj, v = C.c_int(), C.c_int(), (C.c_double * 4)()
+    d3 = lambda x: (C.c_double * 3)(*[float(c) for c in x])
+    lib().og_angular_texels(d3(h), d3(t), d3(b), float(micro), C.byref(ai), C.byref(aj), v)
+    return ai.value, aj.value, list(v)
 
 
 def probe_centre(u, v, phi, sigma0, n_pr, kp):

@@ -22,6 +22,7 @@
  *   anisotropic grid transform                  Sec. 5.1, Eq. 12 (rotate then scale)
  *   simplex surface lattice                     Sec. 6.2, Fig. 6
  *   success probability p = R D(h)/D(n)         Sec. 3, Eq. 4
+ *   tangent frame of the angular grid           Sec. 5.2, Eq. 14 (supplied tangent, else a basis of n)
  *   angular bilinear grid over projected h      Sec. 5.2, Eq. 14
  *   per-texel random numbers                    Sec. 3 (seeds on spatial / angular grids)
  *   gated Gaussian binomial                     Sec. 6.3, Eqs. 16-18
@@ -37,7 +38,10 @@
  * conservation of the distributed weights; brute-force stratified flake
  * simulation for mean and variance of the distributed count; convergence
  * of the seed-averaged glint NDF to D(h); continuity across level, ratio,
- * orientation and lattice boundaries; frozen-branch finite differences
+ * orientation, lattice and angular-cell boundaries; the angular texels'
+ * bilinear weights reconstructing the projected half vector, and the
+ * distributed count as the bilinear blend of its values at the angular
+ * texel centres (Eq. 14); frozen-branch finite differences
  * against free finite differences; the tangent frame orthonormal and
  * right-handed; the probe centres splitting the major axis into equal
  * segments; the Zirr-Kaplanyan baseline's branches against the binomial
@@ -68,6 +72,7 @@ typedef struct {
     const int32_t *material_id;   /* NULL: every pixel uses material 0 */
     const float *alpha_px;        /* NULL or per-pixel roughness */
     const float *log10_density_px;/* NULL or per-pixel log10 flake density */
+    const float *tx, *ty, *tz;    /* NULL or per-pixel tangent (indexes the angular grid) */
 } og_gbuffer;
 
 typedef struct {
@@ -109,7 +114,8 @@ typedef struct {                  /* every plane is [height*stride] or NULL */
 
 /* margin kinds (which discrete decision came closest to its boundary) */
 enum { MK_NONE = 0, MK_NPROBE, MK_RATIO, MK_ORIENT, MK_TRIANGLE, MK_TETRA,
-       MK_LATTICE, MK_ANGULAR, MK_GATE, MK_COUNT, MK_LIGHT, MK_VIEW, MK_ZK_SWITCH };
+       MK_LATTICE, MK_ANGULAR, MK_GATE, MK_COUNT, MK_LIGHT, MK_VIEW, MK_ZK_SWITCH,
+       MK_PCLAMP, MK_TANGENT };
 
 /* ------------------------------------------------------------------ */
 /* Decision tape: records every light-dependent discrete decision of a */
@@ -277,6 +283,73 @@ static void onb(const double n[3], double t[3], double b[3])
 
 void og_onb(const double n[3], double t[3], double b[3]) { onb(n, t, b); }   /* for the pin tests */
 
+static double dot3(const double a[3], const double b[3]) { return a[0]*b[0] + a[1]*b[1] + a[2]*b[2]; }
+
+/* Tangent frame (t, b, n) whose first two axes index the angular grid
+ * (Sec. 5.2, Eq. 14).  Reading: a supplied tangent is made orthogonal to the
+ * unit normal (Gram-Schmidt) and normalised, and b = n x t (right-handed);
+ * without one, the orthonormal basis of n above.  A supplied tangent within
+ * about 1e-3 rad of n (sin^2 of their angle below 1e-6) defines no frame:
+ * returns 0.  The margin of that decision is relative to the threshold. */
+#define OG_TANGENT_MIN_SIN2 1e-6
+static void upd_margin(double *mg, int *mk, double value, int kind);
+static int tangent_frame(const double n[3], const double *tin, double t[3], double b[3],
+                         double *mg, int *mk)
+{
+    if (!tin) { onb(n, t, b); return 1; }
+    double tt = dot3(tin, tin);
+    if (!(tt > 0.0)) return 0;
+    double tn = dot3(tin, n);
+    double tp[3] = {tin[0] - tn * n[0], tin[1] - tn * n[1], tin[2] - tn * n[2]};
+    double s2 = dot3(tp, tp) / tt;                  /* sin^2 of the angle between t and n */
+    if (mg) upd_margin(mg, mk, fabs(s2 - OG_TANGENT_MIN_SIN2) / OG_TANGENT_MIN_SIN2, MK_TANGENT);
+    if (!(s2 >= OG_TANGENT_MIN_SIN2)) return 0;
+    double l = sqrt(dot3(tp, tp));
+    t[0] = tp[0] / l; t[1] = tp[1] / l; t[2] = tp[2] / l;
+    b[0] = n[1] * t[2] - n[2] * t[1];
+    b[1] = n[2] * t[0] - n[0] * t[2];
+    b[2] = n[0] * t[1] - n[1] * t[0];
+    return 1;
+}
+
+int og_tangent_frame(const double n[3], const double tin[3], double t[3], double b[3])
+{
+    return tangent_frame(n, tin, t, b, NULL, NULL);
+}
+
+/* Angular grid of Eq. 14: cells of size mr over the orthographic projection
+ * (<h,t>, <h,b>) of the half vector, texel (i, j) centred at
+ * ((i + 1/2) mr, (j + 1/2) mr).  Cell coordinates of h, measured from the
+ * centre of texel (0, 0): */
+static void angular_coords(const double h[3], const double t[3], const double b[3], double mr,
+                           double *ax, double *ay)
+{
+    *ax = dot3(h, t) / mr - 0.5;
+    *ay = dot3(h, b) / mr - 0.5;
+}
+
+/* bilinear weights of the four texels around (ax, ay), given the lower-left
+ * texel (ai, aj): texel a is (ai + (a & 1), aj + (a >> 1)) and gets v[a] */
+static void angular_weights(double ax, double ay, int ai, int aj, double v[4])
+{
+    double fx = ax - ai, fy = ay - aj;
+    v[0] = (1.0 - fx) * (1.0 - fy);
+    v[1] = fx * (1.0 - fy);
+    v[2] = (1.0 - fx) * fy;
+    v[3] = fx * fy;
+}
+
+/* the four angular texels of h and their weights (for the pin tests) */
+void og_angular_texels(const double h[3], const double t[3], const double b[3], double mr,
+                       int *ai, int *aj, double v[4])
+{
+    double ax, ay;
+    angular_coords(h, t, b, mr, &ax, &ay);
+    *ai = (int)floor(ax);
+    *aj = (int)floor(ay);
+    angular_weights(ax, ay, *ai, *aj, v);
+}
+
 /* centre of sub-footprint kp of n_pr (Sec. 4.2, reading S25): uniform along
  * the major axis (angle phi) over the major-axis length sigma0 */
 static void probe_centre(double u, double v, double phi, double sigma0, int n_pr, int kp, double *cx, double *cy)
@@ -290,8 +363,6 @@ void og_probe_centre(double u, double v, double phi, double sigma0, int n_pr, in
 {
     probe_centre(u, v, phi, sigma0, n_pr, kp, cx, cy);
 }
-
-static double dot3(const double a[3], const double b[3]) { return a[0]*b[0] + a[1]*b[1] + a[2]*b[2]; }
 
 static int normalize3(double a[3])
 {
@@ -593,6 +664,8 @@ typedef struct {
     double u, v, dudx, dvdx, dudy, dvdy, n[3], wi[3];
     int mat;
     double alpha, log10N;          /* effective values (material or per-pixel) */
+    int has_t;                     /* a tangent t[] was supplied */
+    double t[3];
 } og_px_in;
 
 typedef struct {
@@ -629,6 +702,9 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
     double nrm[3] = {in->n[0], in->n[1], in->n[2]};
     double wi[3] = {in->wi[0], in->wi[1], in->wi[2]};
     if (!normalize3(nrm) || !normalize3(wi)) { o->flags |= OGF_BAD_INPUT; return; }
+    /* the frame of the angular grid (Eq. 14) */
+    double tt[3], bb[3];
+    if (!tangent_frame(nrm, in->has_t ? in->t : NULL, tt, bb, mg, mk)) { o->flags |= OGF_BAD_INPUT; return; }
 
     double P, r, phi, sigma0;
     if (!og_footprint(in->dudx, in->dvdx, in->dudy, in->dvdy, &P, &r, &phi, &sigma0)) {
@@ -658,8 +734,6 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
               | ((uint32_t)nodes.pivot << 11) | ((uint32_t)nodes.D << 13) | ((uint32_t)nodes.n << 15);
 
     /* per-light quantities that do not depend on the probe */
-    double tt[3], bb[3];
-    onb(nrm, tt, bb);
     const double mr = mat->micro_roughness;
     const double Dn = 1.0 / (OG_PI * alpha * alpha);  /* D(n) for GGX and Beckmann */
     const uint32_t s0 = og_hash_step(0x243F6A88u, mat->seed);
@@ -682,21 +756,19 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
         double cos_h = dot3(nrm, h);
         /* Eq. 4: p = R D(h)/D(n), clamped to a probability */
         double praw = R * og_ndf(mat->ndf, alpha, cos_h) / Dn;
+        upd_margin(mg, mk, fabs(praw - 1.0), MK_PCLAMP);
         int pc = tape_dec(T, praw > 1.0);
         if (pc) o->flags |= OGF_CLAMP_P;
         pl[li] = pc ? 1.0 : praw;
         /* Eq. 14: bilinear over the 4 nearest texels of the angular grid,
          * indexed by the orthographic projection of h, cell size mr */
-        double ax = dot3(h, tt) / mr - 0.5, ay = dot3(h, bb) / mr - 0.5;
+        double ax, ay;
+        angular_coords(h, tt, bb, mr, &ax, &ay);
         upd_margin(mg, mk, fabs(ax - floor(ax + 0.5)), MK_ANGULAR);
         upd_margin(mg, mk, fabs(ay - floor(ay + 0.5)), MK_ANGULAR);
         ai[li] = tape_dec(T, (int32_t)floor(ax));
         aj[li] = tape_dec(T, (int32_t)floor(ay));
-        double fx = ax - ai[li], fy = ay - aj[li];
-        vw[li][0] = (1.0 - fx) * (1.0 - fy);
-        vw[li][1] = fx * (1.0 - fy);
-        vw[li][2] = (1.0 - fx) * fy;
-        vw[li][3] = fx * fy;
+        angular_weights(ax, ay, ai[li], aj[li], vw[li]);
         for (int a = 0; a < 4; ++a)
             for (int s = 0; s < 2; ++s) {
                 akey[li][a][s] = og_hash_step(0x13198A2Eu, angular_word(ai[li] + (a & 1), aj[li] + (a >> 1), s));
@@ -821,9 +893,14 @@ static int load_pixel(const og_gbuffer *gb, const og_material *mats, int n_mat, 
     in->wi[0] = gb->wx[idx]; in->wi[1] = gb->wy[idx]; in->wi[2] = gb->wz[idx];
     in->alpha = gb->alpha_px ? (double)gb->alpha_px[idx] : (double)mats[mat].alpha;
     in->log10N = gb->log10_density_px ? (double)gb->log10_density_px[idx] : (double)mats[mat].log10_density;
-    double vals[14] = {in->u, in->v, in->dudx, in->dvdx, in->dudy, in->dvdy, in->n[0], in->n[1],
-                       in->n[2], in->wi[0], in->wi[1], in->wi[2], in->alpha, in->log10N};
-    for (int i = 0; i < 14; ++i)
+    in->has_t = gb->tx != NULL;
+    in->t[0] = in->has_t ? gb->tx[idx] : 0.0;
+    in->t[1] = in->has_t ? gb->ty[idx] : 0.0;
+    in->t[2] = in->has_t ? gb->tz[idx] : 0.0;
+    double vals[17] = {in->u, in->v, in->dudx, in->dvdx, in->dudy, in->dvdy, in->n[0], in->n[1],
+                       in->n[2], in->wi[0], in->wi[1], in->wi[2], in->alpha, in->log10N,
+                       in->t[0], in->t[1], in->t[2]};
+    for (int i = 0; i < 17; ++i)
         if (!isfinite(vals[i])) { *flags = OGF_BAD_INPUT; return 0; }
     if (!(in->alpha > 0.0)) { *flags = OGF_BAD_INPUT; return 0; }
     return 1;
@@ -847,6 +924,7 @@ int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_
     if (prm->k_max < 0 || prm->k_max > 4 || prm->n_probe_max < 1) return -1;
     if (prm->rng_log2 < 0 || prm->rng_log2 > 32) return -1;
     if (prm->count_law != 0 && !(prm->count_law == 1 && prm->rounding == 0)) return -1;
+    if (gb->tx && (!gb->ty || !gb->tz)) return -1;
     if (row0 < 0) row0 = 0;
     if (row1 > gb->height) row1 = gb->height;
     const int64_t npx = (int64_t)gb->height * gb->stride;

@@ -8,7 +8,9 @@
 * convergence of the glint BRDF to the smooth microfacet BRDF as the flake
   density grows (Sec. 3, Eqs. 5-6).
 * continuity of the relaxed count across area levels, ratio / orientation
-  cells and lattice edges, and identical floor counts (coherence, Sec. 1).
+  cells and the orientation wrap, and identical floor counts (coherence,
+  Sec. 1); lattice and angular cell edges are crossed in
+  test_oracle_angular.py.
 * evaluation count: 4 grids x 3 simplex vertices x 4 angular texels = 48
   gated binomials per probe and light (Sec. 6.2).
 * gradients: frozen-branch differences equal free differences wherever no
