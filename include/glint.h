@@ -24,8 +24,9 @@
  *    hipError_t of the failing call (per thread).
  *  - Planes are row-major [height][stride] with stride >= width (elements).
  *    out_rgb is SoA: three planes [3][height*stride] (R, G, B).
- *  - The library keeps no mutable global state; it allocates device memory
- *    only inside glint_plan objects.
+ *  - The library keeps no mutable global state except the static workspace
+ *    of glint_shade_noalloc (one per GPU); it allocates device memory only
+ *    inside glint_plan objects.
  */
 #ifndef GLINT_H
 #define GLINT_H
@@ -44,7 +45,8 @@ enum {
     GLINT_ESHAPE = -3,        /* width/height/stride/count inconsistent             */
     GLINT_EHIP = -4,          /* a HIP runtime call failed (glint_last_hip_error)  */
     GLINT_EUNSUPPORTED = -5,  /* valid request this build does not implement       */
-    GLINT_ENOMEM = -6         /* device allocation inside a plan failed            */
+    GLINT_ENOMEM = -6,        /* device allocation inside a plan failed            */
+    GLINT_ELIMIT = -7         /* view larger than glint_shade_noalloc's static workspace */
 };
 
 #define GLINT_MAX_MATERIALS 32
@@ -56,6 +58,7 @@ enum {
 #define GLINT_RNG_LDS_MAX_LOG2 13    /* LDS placement: at most 2^13 words (32 KiB)     */
 #define GLINT_RNG_CACHED 0           /* table read from device memory through L1/L2    */
 #define GLINT_RNG_LDS 1              /* each tile's wave copies the table into LDS     */
+#define GLINT_NOALLOC_WORKSPACE_BYTES 2097152  /* static workspace of glint_shade_noalloc, per GPU */
 
 /* G-buffer of one view (Sec. 5.1 reads footprints from screen derivatives).
  * u, v: texture coordinates; dudx..dvdy: their screen-space derivatives
@@ -204,6 +207,26 @@ int glint_shade_lit(const glint_gbuffer *gbuf, const glint_material *mats, int32
                     const glint_light *lights, int32_t n_light, const glint_params *params,
                     float *out_rgb, uint16_t *lit_lights, uint32_t *lit_probes, void *workspace,
                     size_t workspace_bytes, void *stream);
+
+/* glint_shade for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same heaviest-first shading as glint_shade with a workspace, the
+ * same image bit for bit, but the tile-order workspace is a static device
+ * array of the library (GLINT_NOALLOC_WORKSPACE_BYTES = 2 MiB on every GPU
+ * the library runs on, held until the process ends).  The call allocates
+ * nothing and takes no debug planes; the caller still owns gbuf and out_rgb.
+ * Every call on one GPU uses that GPU's single array: calls that overlap on
+ * one device (two streams, two host threads) race and must be serialised by
+ * the caller; consecutive calls on one stream are safe (each rewrites what it
+ * reads).  The first call on a device looks up the array's address on that
+ * device (hipGetSymbolAddress) and caches it.
+ * Errors as glint_shade, plus ELIMIT when glint_shade_workspace_bytes(width,
+ * height) exceeds GLINT_NOALLOC_WORKSPACE_BYTES (about 22 million pixels,
+ * e.g. 5120 x 4096 fits, 8192 x 4096 does not), EUNSUPPORTED when the current
+ * device index is 64 or above. */
+int glint_shade_noalloc(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
+                        const glint_light *lights, int32_t n_light, const glint_params *params,
+                        float *out_rgb, void *stream);
 
 /* Random-number table for glint_shade_rng_table (Sec. 6.3: the two uniforms
  * of a gated binomial may be read from a small texture of random numbers

@@ -17,8 +17,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -891,6 +893,7 @@ const char *glint_status_string(int s)
     case GLINT_EHIP: return "HIP runtime error (see glint_last_hip_error)";
     case GLINT_EUNSUPPORTED: return "unsupported request";
     case GLINT_ENOMEM: return "device allocation failed";
+    case GLINT_ELIMIT: return "view exceeds the static workspace of glint_shade_noalloc";
     default: return "unknown status";
     }
 }
@@ -983,6 +986,66 @@ int glint_shade_lit(const glint_gbuffer *gbuf, const glint_material *mats, int32
         return GLINT_EINVAL;
     return launch_forward(gbuf, sh, out_rgb, nullptr, workspace, workspace_bytes, kRngHash, 0, lit_lights, lit_probes,
                           stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward (glint_shade_noalloc): the tile-order workspace is
+// a file-scope device array, one copy per GPU that loads the library, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy: on the first call on each device (with that device
+// current) hipGetSymbolAddress gives that device's address of the array,
+// which is kept per device and used from then on.  Nothing in the array has
+// to start at zero: the order pass writes every byte it later reads (class
+// bytes, per-block class counts, their offsets, the order) before reading it.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[GLINT_NOALLOC_WORKSPACE_BYTES];
+static std::atomic<void *> g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_hip_error(e);
+    if (dev < 0 || dev >= kMaxDevices) return GLINT_EUNSUPPORTED;
+    void *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return set_hip_error(e);
+            if (!p) return GLINT_EUNSUPPORTED;
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return GLINT_OK;
+}
+
+extern "C" {
+
+int glint_shade_noalloc(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
+                        const glint_light *lights, int32_t n_light, const glint_params *params, float *out_rgb,
+                        void *stream)
+{
+    Shared sh;
+    int rc = prepare_shared(mats, n_mat, lights, n_light, params, sh, GLINT_FLAG_ZK_COUNT);
+    if (rc) return rc;
+    if (!gbuf) return GLINT_ENULL;
+    if (gbuf->width < 0 || gbuf->height < 0) return GLINT_ESHAPE;
+    const size_t need = tile_order_bytes(gbuf->width, gbuf->height);
+    if (need > GLINT_NOALLOC_WORKSPACE_BYTES) return GLINT_ELIMIT;
+    void *ws = nullptr;
+    if (need > 0) {
+        rc = scratch_of_current_device(&ws);
+        if (rc) return rc;
+    }
+    const int law = (params->flags & GLINT_FLAG_ZK_COUNT) ? kLawZk : kLawDistributed;
+    return launch_forward(gbuf, sh, out_rgb, nullptr, ws, need, kRngHash, 0, nullptr, nullptr, stream, law);
 }
 
 int glint_rng_table_fill(uint32_t *table, int32_t log2_words, uint32_t seed, void *stream)

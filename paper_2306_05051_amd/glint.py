@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libglint.so")
 PLANES = ("u", "v", "dudx", "dvdx", "dudy", "dvdy", "nx", "ny", "nz", "wx", "wy", "wz")
 
 GLINT_OK, GLINT_EINVAL, GLINT_ENULL, GLINT_ESHAPE = 0, -1, -2, -3
-GLINT_EHIP, GLINT_EUNSUPPORTED, GLINT_ENOMEM = -4, -5, -6
+GLINT_EHIP, GLINT_EUNSUPPORTED, GLINT_ENOMEM, GLINT_ELIMIT = -4, -5, -6, -7
+GLINT_NOALLOC_WORKSPACE_BYTES = 2097152
 GLINT_MAX_MATERIALS, GLINT_MAX_LIGHTS, GLINT_MAX_K, GLINT_MAX_PROBES = 32, 16, 4, 64
 GLINT_RNG_TABLE_MIN_LOG2, GLINT_RNG_TABLE_MAX_LOG2, GLINT_RNG_LDS_MAX_LOG2 = 8, 32, 13
 GLINT_RNG_CACHED, GLINT_RNG_LDS = 0, 1
@@ -91,6 +92,8 @@ def lib():
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.glint_shade.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
                                   C.POINTER(_Params), vp, C.POINTER(_Debug), vp, C.c_size_t, vp]
+        L.glint_shade_noalloc.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
+                                          C.POINTER(_Params), vp, vp]
         L.glint_rng_table_fill.argtypes = [vp, i32, C.c_uint32, vp]
         L.glint_shade_rng_table.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), i32, C.POINTER(_Light), i32,
                                             C.POINTER(_Params), vp, i32, i32, vp, C.POINTER(_Debug), vp,
@@ -200,6 +203,23 @@ def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, ou
     baseline, GLINT_FLAG_ZK_COUNT; rounding must be 0)."""
     return _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, None,
                   count_law)
+
+
+def glint_shade_noalloc(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, out=None, stream=None,
+                        count_law=LAW_DISTRIBUTED):
+    """glint_shade (heaviest tiles first, same image) through the entry point
+    that allocates nothing: its tile-order workspace is the library's static
+    device array.  out: a float32 CUDA tensor [3, H, W] (allocated here when
+    None, which the C call itself never does)."""
+    g = make_gbuffer(gbuf)
+    H, W = gbuf["u"].shape
+    if out is None:
+        out = torch.empty((3, H, W), dtype=torch.float32, device=gbuf["u"].device)
+    st = lib().glint_shade_noalloc(C.byref(g), make_materials(materials), len(materials), make_lights(lights),
+                                   len(lights), C.byref(make_params(k_max, n_probe_max, rounding, count_law)),
+                                   _dev_ptr(out, torch.float32, "out"), _stream(stream))
+    _check(st, "glint_shade_noalloc")
+    return out
 
 
 RNG_CACHED, RNG_LDS = GLINT_RNG_CACHED, GLINT_RNG_LDS

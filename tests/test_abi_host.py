@@ -38,14 +38,14 @@ def test_limits_match_header():
     txt = open(HEADER).read()
     for name in ("GLINT_MAX_MATERIALS", "GLINT_MAX_LIGHTS", "GLINT_MAX_K", "GLINT_MAX_PROBES",
                  "GLINT_RNG_TABLE_MIN_LOG2", "GLINT_RNG_TABLE_MAX_LOG2", "GLINT_RNG_LDS_MAX_LOG2",
-                 "GLINT_RNG_CACHED", "GLINT_RNG_LDS", "GLINT_FLAG_ZK_COUNT"):
+                 "GLINT_RNG_CACHED", "GLINT_RNG_LDS", "GLINT_FLAG_ZK_COUNT", "GLINT_NOALLOC_WORKSPACE_BYTES"):
         m = re.search(r"#define " + name + r"\s+(\d+)", txt)
         assert m and int(m.group(1)) == getattr(glint, name), name
 
 
 def test_status_strings_and_version(lib):
     lib.glint_status_string.restype = C.c_char_p
-    for s in range(0, -7, -1):
+    for s in range(0, -8, -1):
         assert lib.glint_status_string(s)
     assert lib.glint_status_string(-99) == b"unknown status"
     assert lib.glint_version() >= 10000
@@ -128,6 +128,16 @@ def test_host_validation_without_device(lib):
                                   fake, fake, fake, 1 << 20, None) == glint.GLINT_EINVAL
     assert L.glint_shade_backward(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake, fake, C.c_void_p(4098), fake,
                                   fake, fake, fake, 1 << 20, None) == glint.GLINT_EINVAL
+    # allocation-free forward: arguments and its size limit are checked before any device call
+    na = L.glint_shade_noalloc
+    assert na(None, mats, 1, lts, 1, C.byref(prm), fake_out, None) == glint.GLINT_ENULL
+    assert na(C.byref(g), mats, 1, lts, 1, C.byref(bad), fake_out, None) == glint.GLINT_EINVAL
+    assert na(C.byref(g), mats, 1, lts, 1, C.byref(zk_relaxed), fake_out, None) == glint.GLINT_EINVAL
+    big = glint._GBuf()
+    big.width, big.height, big.stride = 8192, 4096, 8192
+    assert L.glint_shade_workspace_bytes(8192, 4096) > glint.GLINT_NOALLOC_WORKSPACE_BYTES
+    assert na(C.byref(big), mats, 1, lts, 1, C.byref(prm), fake_out, None) == glint.GLINT_ELIMIT
+    assert L.glint_shade_workspace_bytes(5120, 4096) <= glint.GLINT_NOALLOC_WORKSPACE_BYTES
     # utilities: negative sizes and NULL pointers
     assert L.glint_texel_hash(None, -1, None, None) == glint.GLINT_ESHAPE
     assert L.glint_texel_hash(None, 5, None, None) == glint.GLINT_ENULL
