@@ -39,33 +39,40 @@ keys and gates):
       CDF (bits to x, 1-x, 1+x 7, log 6, select 1, polynomial 9, scale 2) 25,
       node mean/sigma 11, Gaussian 1, count 2, bilinear weight and
       accumulate 5 = 65
-  item-light (one pixel, probe, light; the unit half vector enters through
-      dot products: |wi + wo|^2 = 2 (1 + <wi,wo>) and so on): <n,wo> and its
-      sign 8, <wi,wo> 6, |wi + wo|^2 and guard 4, 1/|wi + wo| 16, <n,h> 4,
-      cos^2/sin^2 8, GGX ratio p 12, angular coordinates, cell and bilinear
-      fractions 46 (the frame projections <t,wo>, <b,wo> through the implicit
-      frame: 4 FP64 operations), log(1-p) 21, 4 gate set-ups (trials x log,
-      1-exp, guards, threshold, shift) 4 x 28 = 112, 4 slot-0 angular keys
-      4 x 12 = 48 = 285
-  lit item-light (extra, when at least one of its gates opened; otherwise it
-      adds exactly nothing): Fresnel 13, Smith Lambda(wo) 20, radiance 13 = 46
-  item (one pixel, probe): probe centre 28, FP64 tangent frame of n in
-      implicit form (sign s, a = -1/(s + n_z), s n_x) 17, <n,wi> 6 and
-      <wi,t>, <wi,b> from it 8, 4 x (key unpack 5, trig table index 3, rotation 8,
+  pixel-light (one pixel and one light: everything here depends on the
+      pixel and the light only, never on the probe, so it is credited once
+      per valid (pixel, light) pair however many probes the pixel has; the
+      unit half vector enters through dot products: |wi + wo|^2 = 2 (1 +
+      <wi,wo>) and so on): <n,wo> and its sign 8, <wi,wo> 6, |wi + wo|^2 and
+      guard 4, 1/|wi + wo| 16, <n,h> 4, cos^2/sin^2 8, GGX ratio p 12,
+      angular coordinates, cell and bilinear fractions 46 (the frame
+      projections <t,wo>, <b,wo>: 4 FP64 operations), log(1-p) 21, 4 gate
+      set-ups (the node's trials are per pixel: trials x log, 1-exp, guards,
+      threshold, shift) 4 x 28 = 112, 4 slot-0 angular keys 4 x 12 = 48 = 285
+  lit pixel-light (extra, when at least one gate of the light opened in
+      some probe of the pixel; otherwise the light adds exactly nothing):
+      Fresnel 13, Smith Lambda(wo) 20, radiance factor and RGB 13 = 46
+  item (one pixel, probe: only what depends on the probe's centre): probe
+      centre 28, 4 x (key unpack 5, trig table index 3, rotation 8,
       anisotropic scales 14, lattice shear/floor/fractions 18, triangle 2,
-      vertex selects 6, barycentrics 10, node hash 9, texel keys H(H(node, i),
-      j) of the three vertices, which span two lattice columns: 2 + 3 hashes
-      45 and the column select 2) = 4 x 122 = 488, probe sum 3 = 550
+      vertex selects 6, barycentrics 10, texel keys H(H(node, i), j) of the
+      three vertices, which span two lattice columns: 2 + 3 hashes 45 and the
+      column select 2) = 4 x 113 = 452, probe sum 3 = 483
   pixel: density 5, FP64 normalisation of n and w 68, footprint moments 24,
       <n,wi> 6, eigenvalue and ratio 60, atan2 80, sigma0 times the major-axis
       eigenvector 58, probe split 50, area level 6, ratio/orientation cell,
       triangle, merge, sort, tetrahedron and node words 180,
-      D(n)/(R N P 4<wi,n>) and Lambda(wi) 56 = 593
+      D(n)/(R N P 4<wi,n>) and Lambda(wi) 56, FP64 tangent frame of n in
+      implicit form (sign s, a = -1/(s + n_z), s n_x) 17, <n,wi> and <wi,t>,
+      <wi,b> from it 14, the 4 nodes' base hashes H(material, node) 36 = 660
 
 Units are counted exactly by the library's instrumented kernel (debug
-planes).  Loop control, address arithmetic, LDS traffic, recomputation,
-scheduling and idle lanes are not credited, so the achieved rate is a lower
-bound on the issue rate the kernel sustains.
+planes): pixel-lights from the gated binomials each light evaluates per
+probe, lit pixel-lights from the per-light count sums.  Loop control,
+address arithmetic, LDS traffic, recomputation (a pixel's light set-up or its
+node hashes done again for each of its probes), scheduling and idle lanes are
+not credited, so the achieved rate is a lower bound on the issue rate the
+kernel sustains.
 """
 from __future__ import annotations
 
@@ -81,33 +88,45 @@ COST = {
     "live_gate": HASH + 1 + 2,
     "live_gate_small": HASH - 1 + 1 + 2,
     "open_gate": (3 + HASH) + HASH + 25 + 11 + 1 + 2 + 5,
-    "item_light": 8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 46 + 21 + 4 * 28 + 4 * (3 + HASH),
-    "item_light_lit": 13 + 20 + 13,
-    "item": (8 + FP64_RCP + 8) + (5 + FP64_RCP) + 6 + 8
-            + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + HASH + 5 * HASH + 2) + 3,
+    "pixel_light": 8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 46 + 21 + 4 * 28 + 4 * (3 + HASH),
+    "pixel_light_lit": 13 + 20 + 13,
+    "item": (8 + FP64_RCP + 8) + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + 5 * HASH + 2) + 3,
     "pixel": (5 + 2 * (12 + FP64_RSQ + 6) + 24 + 6 + (12 + FP64_SQRT + 2 + FP64_DIV + 2) + 80
-              + (26 + 2 * FP64_RSQ) + (8 + 2 * FP64_DIV + 2) + 6 + 180 + 56),
+              + (26 + 2 * FP64_RSQ) + (8 + 2 * FP64_DIV + 2) + 6 + 180 + 56
+              + (5 + FP64_RCP) + 6 + 8 + 4 * HASH),
 }
 
 
 def units_from_debug(dbg):
-    """Unit counts from the debug planes of one launch (numpy arrays)."""
+    """Unit counts from the debug planes of one launch (numpy arrays).
+
+    Every probe of a pixel evaluates the same lights, each with 12 gated
+    binomials per grid node, so a pixel's valid lights number
+    n_gate / (12 n_nodes n_probe); a light is lit in a pixel when its count
+    sum b (b_light) is positive, which needs an open gate."""
     import numpy as np
     flags = dbg["flags"].astype(np.int64) & 0xFFFFFFFF
     shaded = (flags & 1) > 0
     n_nodes = (dbg["cell"].astype(np.int64) >> 15) & 7
+    n_probe = dbg["n_probe"].astype(np.int64)
     n_gate = dbg["n_gate"].astype(np.int64) & 0xFFFFFFFF
-    pairs = np.where(shaded & (n_nodes > 0), n_gate // np.maximum(12 * n_nodes, 1), 0)
+    ok = shaded & (n_nodes > 0)
+    item_lights = np.where(ok, n_gate // np.maximum(12 * n_nodes, 1), 0)
+    pixel_lights = np.where(ok, n_gate // np.maximum(12 * n_nodes * n_probe, 1), 0)
     live = int((dbg["n_live"].astype(np.int64) & 0xFFFFFFFF).sum())
     small = int((dbg["n_live_small"].astype(np.int64) & 0xFFFFFFFF).sum()) if "n_live_small" in dbg else 0
+    lit_pl = int(((dbg["b_light"] > 0) & shaded[None]).sum()) if "b_light" in dbg else 0
     return {
         "pixel": int(shaded.sum()),
-        "item": int(dbg["n_probe"][shaded].astype(np.int64).sum()),
-        "item_light": int(pairs.sum()),
-        "item_light_lit": int((dbg["n_lit"].astype(np.int64) & 0xFFFFFFFF).sum()) if "n_lit" in dbg else 0,
+        "item": int(n_probe[shaded].sum()),
+        "pixel_light": int(pixel_lights.sum()),
+        "pixel_light_lit": lit_pl,
         "live_gate": live - small,
         "live_gate_small": small,
         "open_gate": int((dbg["n_open"].astype(np.int64) & 0xFFFFFFFF).sum()),
+        # not priced (reported for the record): item-lights and all gates
+        "item_light": int(item_lights.sum()),
+        "item_light_lit": int((dbg["n_lit"].astype(np.int64) & 0xFFFFFFFF).sum()) if "n_lit" in dbg else 0,
         "gate": int(n_gate.sum()),
     }
 

@@ -50,18 +50,20 @@ struct Shared {
 };
 
 // The pixel that owns item q of a tile: the last p in 0..63 with off[p] <= q,
-// for the non-decreasing item offsets off[] of the tile's pixels (off[0] = 0).
-// Two rounds of independent LDS reads (the 8-pixel block, then the pixel in
-// it) instead of a six-step chain of dependent ones.
-__device__ __forceinline__ int item_pixel(const int *off, int q)
+// for the non-decreasing item offsets of the tile's pixels (off[0] = 0),
+// where `off` is this lane's offset (lane = pixel).  Two rounds of
+// independent cross-lane reads (the 8-pixel block, then the pixel in it)
+// instead of a six-step chain of dependent ones.  Every lane of the wave must
+// be active.
+__device__ __forceinline__ int item_pixel(int off, int q)
 {
     int c = 0;
 #pragma unroll
-    for (int k = 1; k < 8; ++k) c += (off[8 * k] <= q) ? 1 : 0;
+    for (int k = 1; k < 8; ++k) c += (__builtin_amdgcn_readlane(off, 8 * k) <= q) ? 1 : 0;
     const int b = 8 * c;
     int p = b;
 #pragma unroll
-    for (int i = 1; i < 8; ++i) p += (off[b + i] <= q) ? 1 : 0;
+    for (int i = 1; i < 8; ++i) p += (__shfl(off, b + i) <= q) ? 1 : 0;
     return p;
 }
 
@@ -710,39 +712,63 @@ __device__ __forceinline__ PixelRec make_rec(const Pixel &px, const Shared &sh)
     return r;
 }
 
-// texel keys and barycentric weights of one probe's simplex texels (Sec. 6.2)
-template <typename SM>
-__device__ __forceinline__ void probe_texels(const PixelRec &R, double u, double v, int kp, const DevMaterial &M,
-                                             const Shared &sh, uint32_t pre[4][3], SM &sm, uint32_t *key_sum)
+// Centre of sub-footprint kp of npr (Sec. 4.2: the distributed law over
+// more areas): uniform along the major axis (ex, ey) = sigma0 e0 over length
+// sigma0, centred on the pixel's uv.
+__device__ __forceinline__ void probe_centre(double u, double v, double ex, double ey, int kp, int npr, double &cx,
+                                             double &cy)
 {
-    const int lane = threadIdx.x;
-    const int npr = rec_npr(R), nn = rec_nodes(R);
-    // probe centre, uniform along the major axis over length sigma0
     const double off = ((double)kp + 0.5) * rcp_d((double)npr) - 0.5;
-    const double cx = u + off * R.ex, cy = v + off * R.ey;
-    // all four nodes without branching (almost every pixel has four, and
-    // straight-line code lets the nodes' FP64 and hash chains interleave);
-    // slots of nodes g >= nn are never read
+    cx = u + off * ex;
+    cy = v + off * ey;
+}
+
+// Texel keys and barycentric weights of the simplex texels under a probe
+// centred at (cx, cy) (Eq. 12, Sec. 6.2), for the four grid nodes whose key
+// words (l + 1024) | k << 11 | m << 14 are w[g], under the material's hash
+// root.  All four nodes are computed without branching (almost every pixel has
+// four, and straight-line code lets the nodes' FP64 and hash chains
+// interleave); the keys of nodes past the pixel's node count are never used.
+__device__ __forceinline__ void texel_keys(double cx, double cy, const uint32_t w[4], uint32_t root, const Shared &sh,
+                                           uint32_t pre[4][3], float beta[4][3])
+{
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        const uint32_t w = rec_node_word(R, g);
-        const int l = (int)(w & 0x7ffu) - 1024, k = (w >> 11) & 7, m = w >> 14;
+        const int l = (int)(w[g] & 0x7ffu) - 1024, k = (w[g] >> 11) & 7, m = w[g] >> 14;
         int vi[3], vj[3];
-        float beta[3];
-        simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta);
-        const uint32_t base = hstep(M.root, w);
+        simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta[g]);
+        const uint32_t base = hstep(root, w[g]);
         // vertex keys H(H(base, i), j): the triangle's vertices span two
         // columns i0 = vi[0] and i0 + 1 = vi[2], so two inner steps serve all three
         const uint32_t h0 = hstep(base, (uint32_t)vi[0]), h1 = hstep(base, (uint32_t)vi[2]);
         pre[g][0] = hstep(h0, (uint32_t)vj[0]);
         pre[g][1] = hstep(vi[1] == vi[0] ? h0 : h1, (uint32_t)vj[1]);
         pre[g][2] = hstep(h1, (uint32_t)vj[2]);
+    }
+}
+
+// texel keys and barycentric weights of one probe's simplex texels (Sec. 6.2),
+// staged in the caller's LDS columns ([node*3 + vertex][lane])
+template <typename SM>
+__device__ __forceinline__ void probe_texels(const PixelRec &R, double u, double v, int kp, const DevMaterial &M,
+                                             const Shared &sh, uint32_t pre[4][3], SM &sm, uint32_t *key_sum)
+{
+    const int lane = threadIdx.x;
+    const int npr = rec_npr(R), nn = rec_nodes(R);
+    double cx, cy;
+    probe_centre(u, v, R.ex, R.ey, kp, npr, cx, cy);
+    uint32_t w[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) w[g] = rec_node_word(R, g);
+    float beta[4][3];
+    texel_keys(cx, cy, w, M.root, sh, pre, beta);
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             sm.pre[g * 3 + e][lane] = pre[g][e];
-            sm.beta[g * 3 + e][lane] = beta[e];
+            sm.beta[g * 3 + e][lane] = beta[g][e];
             if (key_sum && g < nn) *key_sum += pre[g][e];
         }
-    }
 }
 }  // namespace glint

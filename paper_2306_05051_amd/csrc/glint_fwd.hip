@@ -45,20 +45,107 @@ struct ItemOut {
     float b[kMaxLight];
 };
 
-// Per-wave LDS (9984 bytes without the debug slots: 16 workgroups per CU).
-// Values the open-gate loop reads with a per-lane index live here
-// ([slot][lane], conflict-free) rather than in registers, which cannot be
-// indexed per lane.  Column `lane` of pre[][] is private to that lane while
-// its item runs; afterwards rows 0-2 of the column hold the item's RGB for
-// the pixel lanes' sums.
-template <bool DEBUG>
-struct TileSmem {
-    int off[kWave];
-    PixelRec rec[kWave];
-    uint32_t pre[12][kWave];   // texel key hashes of each lane's item, [node*3 + vertex][lane]
-    float beta[12][kWave];     // their barycentric weights
-    ItemOut dslot[DEBUG ? kWave : 1];
+// Per-wave LDS.  Static part (2048 bytes): per pixel of the tile, what its
+// items need that depends neither on the probe nor on the light
+// ([field][pixel], conflict-free): sigma0 e0, the probe step direction, in
+// FP32 (its rounding moves a probe centre by at most 2^-25 sigma0, a few 1e-6
+// lattice cells, inside every decision margin; the centre itself is FP64);
+// the packed counts and node codes; the trials per node.  The instrumented
+// kernel adds one result slot per lane.  Dynamic part: the per-(pixel,
+// light) records (LightRec) of the tile, 2 KB per light,
+// [light][word][pixel].  Item offsets stay in the pixel lanes' registers
+// (cross-lane reads), so 4 lights fit in 10 KB: 16 waves per CU.
+//   pk   n_pr (bits 0-6) | node count (7-9) | material (10-14) | l + 1024
+//        (15-25) | node codes bits 0-5 (26-31)
+//   nd   node codes bits 6-35; node g's 9-bit code (top level | k << 1 |
+//        m << 4) is bits 9g..9g+8 of the 36-bit code string
+struct TileSmemBase {
+    float ex[kWave], ey[kWave];
+    uint32_t pk[kWave];
+    uint32_t nd[kWave];
+    float ng[4][kWave];        // trials per node w N 2^l (Eq. 10); the baseline law keeps the weights w here
 };
+template <bool DEBUG>
+struct TileSmem : TileSmemBase {
+    ItemOut dslot[kWave];
+};
+template <>
+struct TileSmem<false> : TileSmemBase {};
+
+// Per-(pixel, light) record: everything a light needs at a pixel that does not
+// depend on the probe, computed once by the pixel's lane before the items run
+// (8 words, LDS [light][word][pixel]):
+//   w0..w3  gate threshold K_g of node g (Eqs. 10, 16: the uniform's index
+//           k = h >> 9 opens the gate iff k < K_g; K_g <= 2^23, bits 0-23) and,
+//           in bits 24-31 of the four words, the 31-bit code
+//           A | B << 15 | valid << 30 with A = (ai + 16384) mod 2^15,
+//           B = (aj + 16384) mod 2^15 the lower-left angular texel (Eq. 14)
+//   w4      p (Eq. 4)
+//   w5, w6  the bilinear fractions of Eq. 14 along x and y: the smaller of
+//           (f, 1 - f), stored as f when f <= 1/2 and as -(1 - f) otherwise
+//           (the other one is 1 minus it, within 2^-24)
+//   w7      F G D(n)/(R N P 4 <wi,n>) (Eqs. 1-3 without the count b)
+// valid = 0 (all words 0): the light is below the horizon at this pixel (or
+// zero), so it adds nothing.
+constexpr int kLightRecWords = 8;
+constexpr size_t kLightRecBytes = kLightRecWords * kWave * sizeof(uint32_t);   // per light
+
+__device__ __forceinline__ void make_light_rec(const Pixel &px, const PixelRec &r, const DevMaterial &M,
+                                               const DevLight &L, const ViewFrame &fr, uint32_t w[kLightRecWords],
+                                               bool &pclamp)
+{
+#pragma unroll
+    for (int k = 0; k < kLightRecWords; ++k) w[k] = 0u;
+    pclamp = false;
+    LightEval le;
+    if (!eval_light(px.n, px.wi, px.alpha, L, M, fr, le)) return;
+    pclamp = le.pclamp;
+    const float lp = log1m(le.p);
+    const uint32_t code = ((uint32_t)(le.ai + 16384) & 0x7FFFu) | (((uint32_t)(le.aj + 16384) & 0x7FFFu) << 15) |
+                          (1u << 30);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) w[g] = gate_K(r.ng[g], le.p, lp) | (((code >> (8 * g)) & 0xFFu) << 24);
+    light_brdf(M, px.alpha, le);
+    const float G = 1.0f / ((1.0f + r.lam_i) * (1.0f + le.lam_o));
+    w[4] = __float_as_uint(le.p);
+    w[5] = __float_as_uint(le.fx <= 0.5f ? le.fx : -le.gx);
+    w[6] = __float_as_uint(le.fy <= 0.5f ? le.fy : -le.gy);
+    w[7] = __float_as_uint(le.F * G * r.kpx);
+}
+
+// the fraction f and its complement 1 - f from a stored smaller one
+__device__ __forceinline__ void unpack_frac(uint32_t bits, float &f, float &g)
+{
+    const float s = __uint_as_float(bits);
+    const bool neg = (bits >> 31) != 0u;
+    f = neg ? 1.0f - (-s) : s;
+    g = neg ? -s : 1.0f - s;
+}
+
+// element (g, e) of a per-lane [4][3] register array for a per-lane (g, e):
+// a tree of selects (registers cannot be indexed per lane).  Each element
+// passes through an empty register constraint first, so that the compiler
+// cannot fold the selects into one load from a per-lane address (which would
+// move the array to scratch memory).
+template <typename T>
+__device__ __forceinline__ T pick43(const T (&a)[4][3], int g, int e)
+{
+    T v[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[i][k] = a[i][k];
+            asm("" : "+v"(v[i][k]));
+        }
+    const bool e1 = e == 1, e2 = e == 2;
+    const T x0 = e2 ? v[0][2] : (e1 ? v[0][1] : v[0][0]);
+    const T x1 = e2 ? v[1][2] : (e1 ? v[1][1] : v[1][0]);
+    const T x2 = e2 ? v[2][2] : (e1 ? v[2][1] : v[2][0]);
+    const T x3 = e2 ? v[3][2] : (e1 ? v[3][1] : v[3][0]);
+    const bool g0 = (g & 1) != 0;
+    return (g & 2) ? (g0 ? x3 : x2) : (g0 ? x1 : x0);
+}
 
 // ---------------------------------------------------------------------------
 // One (pixel, probe) item: simplex texels of every grid node, then per light
@@ -105,17 +192,24 @@ __device__ __forceinline__ uint32_t rng_word(uint32_t pre, uint32_t ak, const Sh
     }
 }
 
+// angular key H(salt, angular word) of texel (ai + dx, aj + dy), slot s, from
+// the record's A = (ai + 16384) mod 2^15 and B = (aj + 16384) mod 2^15
+__device__ __forceinline__ uint32_t angular_key(uint32_t A, uint32_t B, int dx, int dy, int s)
+{
+    return hstep(kAngularSalt, ((A + (uint32_t)dx) & 0x7FFFu) | (((B + (uint32_t)dy) & 0x7FFFu) << 15) |
+                                   ((uint32_t)s << 30));
+}
+
 // LK = 2 shades one item on two lanes: the even lane takes the even lights,
 // the odd lane the odd ones, and after every pair of lights the even lane
 // (the item's owner) receives its partner's factor and extends the radiance
 // chain with both, in light order.  With LK = 1 one lane takes every light.
 // Either way the chain is o.rgb = fma(E_l, f_l, o.rgb) over l = 0, 1, ...
 // with f_l = +0 for a light without an open gate, so the image has the same
-// bits.
+// bits.  p: the item's pixel in the tile, kp: its probe, (u, v): the pixel's uv.
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LK = 1, int LAW = kLawDistributed>
-__device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v, const double n[3],
-                                           const double wi[3], int kp, const Shared &sh, TileSmem<DEBUG> &sm,
-                                           ItemOut &o, const uint32_t *ltbl, float zN = 0.0f)
+__device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint32_t *lrec, int ip, double u, double v,
+                                           int kp, const Shared &sh, ItemOut &o, const uint32_t *ltbl, float zN = 0.0f)
 {
     static_assert(LK == 1 || (LK == 2 && !DEBUG), "two lanes per item only in the production kernels");
     const int lane = threadIdx.x;
@@ -125,12 +219,28 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
         o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = o.n_live_small = o.n_lit = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
     }
-    const int nn = rec_nodes(R);
-    const DevMaterial &M = sh.mats[rec_mat(R)];
+    const uint32_t pk = sm.pk[ip];
+    const int npr = (int)(pk & 0x7fu), nn = (int)((pk >> 7) & 7u);
+    const DevMaterial &M = sh.mats[(pk >> 10) & 31u];
+    uint32_t wd[4];
+    {
+        const uint32_t lb = (pk >> 15) & 0x7ffu;
+        const uint64_t D = (uint64_t)(pk >> 26) | ((uint64_t)sm.nd[ip] << 6);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const uint32_t d = (uint32_t)(D >> (9 * g)) & 0x1ffu;
+            wd[g] = (lb + (d & 1u)) | (((d >> 1) & 7u) << 11) | ((d >> 4) << 14);
+        }
+    }
+    double cx, cy;
+    probe_centre(u, v, (double)sm.ex[ip], (double)sm.ey[ip], kp, npr, cx, cy);
     uint32_t pre[4][3];
-    probe_texels(R, u, v, kp, M, sh, pre, sm, DEBUG ? &o.key_sum : (uint32_t *)nullptr);
-    ViewFrame fr;
-    view_frame(n, wi, fr);
+    float beta[4][3];
+    texel_keys(cx, cy, wd, M.root, sh, pre, beta);
+    if (DEBUG) {
+        for (int g = 0; g < nn; ++g)
+            for (int e = 0; e < 3; ++e) o.key_sum += pre[g][e];
+    }
     const int n_light = sh.n_light;
     const int trips = LK == 1 ? n_light : (n_light + 1) >> 1;
     for (int j = 0; j < trips; ++j) {
@@ -138,38 +248,47 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
         float f = 0.0f;                        // this light's radiance factor F G D_P / (4 <wi,n>)
         do {
             if (LK == 2 && li >= n_light) break;
-            const DevLight &L = sh.lights[li];
-            LightEval le;
-            if (!eval_light(n, wi, R.alpha, L, M, fr, le)) break;
-            const float p = le.p;
+            const uint32_t *lw = lrec + (size_t)li * kLightRecWords * kWave + ip;
+            uint32_t K[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) K[g] = lw[g * kWave];
+            const uint32_t code = (K[0] >> 24) | ((K[1] >> 24) << 8) | ((K[2] >> 24) << 16) | ((K[3] >> 24) << 24);
+            if (!(code & (1u << 30))) break;   // below the horizon: the light adds nothing
+#pragma unroll
+            for (int g = 0; g < 4; ++g) K[g] &= 0xFFFFFFu;
+            const uint32_t A = code & 0x7FFFu, B = (code >> 15) & 0x7FFFu;
             if constexpr (LAW == kLawZk) {
-                // baseline counting law; R.ng holds the node weights w and zN
+                // baseline counting law; sm.ng holds the node weights w and zN
                 // the pixel's flake density N
+                const float p = __uint_as_float(lw[4 * kWave]);
+                float fx, gx, fy, gy;
+                unpack_frac(lw[5 * kWave], fx, gx);
+                unpack_frac(lw[6 * kWave], fy, gy);
                 uint32_t ak0[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
-                    ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
+                for (int a = 0; a < 4; ++a) ak0[a] = angular_key(A, B, a & 1, a >> 1, 0);
                 // a Bernoulli trial succeeds when (2k + 1) 2^-24 < p, k = h >> 9,
                 // i.e. k < ceil((p 2^24 - 1) / 2): exact in FP32
                 const float kf = ceilf((p * 16777216.0f - 1.0f) * 0.5f);
                 const uint32_t KB = kf >= 8388608.0f ? 8388608u : (kf > 0.0f ? (uint32_t)kf : 0u);
                 float bsum = 0.0f;
-                for (int g = 0; g < nn; ++g) {
-                    const float nz = ldexpf(zN, (int)(rec_node_word(R, g) & 0x7ffu) - 1024);   // N 2^l
-                    const float w = R.ng[g];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    if (g >= nn) break;
+                    const float nz = ldexpf(zN, (int)(wd[g] & 0x7ffu) - 1024);   // N 2^l
+                    const float w = sm.ng[g][ip];
                     const float mu = nz * p;
                     if (mu > 5.0f || nz > 16.0f) {
                         const float sd = __builtin_amdgcn_sqrtf(mu * (1.0f - p));
                         if (!DEBUG && fmaf(sd, kZmaxBound, mu) < 1.0f) continue;
+#pragma unroll
                         for (int e = 0; e < 3; ++e) {
-                            const int ge = g * 3 + e;
-                            const float wb = w * sm.beta[ge][lane];
-                            const uint32_t pk = sm.pre[ge][lane];
+                            const float wb = w * beta[g][e];
 #pragma unroll
                             for (int a = 0; a < 4; ++a) {
-                                const uint32_t h0 = hstep(pk, ak0[a]);
+                                const uint32_t h0 = hstep(pre[g][e], ak0[a]);
                                 const float c = fmaxf(floorf(fmaf(sd, ndtri_bits(h0), mu)), 0.0f);
-                                const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);
+                                const float va = ((a & 1) ? fx : gx) * ((a & 2) ? fy : gy);
                                 bsum = fmaf(wb * va, c, bsum);
                                 if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_open += 1; o.count_sum += (uint32_t)c; }
                             }
@@ -177,16 +296,15 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
                     } else {
                         const int t = (int)floorf(nz + 0.5f);
                         if (!DEBUG && (t == 0 || KB == 0u)) continue;
+#pragma unroll
                         for (int e = 0; e < 3; ++e) {
-                            const int ge = g * 3 + e;
-                            const float wb = w * sm.beta[ge][lane];
-                            const uint32_t pk = sm.pre[ge][lane];
+                            const float wb = w * beta[g][e];
 #pragma unroll
                             for (int a = 0; a < 4; ++a) {
-                                const uint32_t h0 = hstep(pk, ak0[a]);
+                                const uint32_t h0 = hstep(pre[g][e], ak0[a]);
                                 uint32_t c = 0u;
                                 for (int k = 1; k <= t; ++k) c += ((hstep(h0, (uint32_t)k) >> 9) < KB) ? 1u : 0u;
-                                const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);
+                                const float va = ((a & 1) ? fx : gx) * ((a & 2) ? fy : gy);
                                 bsum = fmaf(wb * va, (float)c, bsum);
                                 if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_live += (uint32_t)t; o.count_sum += c; }
                             }
@@ -196,23 +314,17 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
                 if (DEBUG) o.b[li] = bsum;
                 if (!(bsum > 0.0f)) break;   // no count: the light adds exactly +0
                 if (DEBUG) o.n_lit += 1;
-                light_brdf(M, R.alpha, le);
-                const float G = 1.0f / ((1.0f + R.lam_i) * (1.0f + le.lam_o));
-                f = le.F * G * R.kpx * bsum;
+                f = __uint_as_float(lw[7 * kWave]) * bsum;
                 break;
             }
-            const float lp = log1m(p);
-            uint32_t K[4], anyK = 0u;
+            uint32_t anyK = 0u;
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                K[g] = gate_K(R.ng[g], p, lp);
+            for (int g = 0; g < 4; ++g)
                 if (g < nn) anyK |= K[g];
-            }
             if (!DEBUG && anyK == 0u) break;   // no gate of this light can open
             uint32_t ak0[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-                ak0[a] = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 0));
+            for (int a = 0; a < 4; ++a) ak0[a] = angular_key(A, B, a & 1, a >> 1, 0);
             uint32_t mlo = 0u, mhi = 0u;       // open gates: bit g*16 + e*4 + a (g < 2 in mlo)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
@@ -260,27 +372,28 @@ __device__ __forceinline__ void shade_item(const PixelRec &R, double u, double v
             if ((mlo | mhi) == 0u) break;
             if (DEBUG) o.n_lit += 1;
             if (LIT) o.lit |= 1u << li;
-            light_brdf(M, R.alpha, le);
+            const float p = __uint_as_float(lw[4 * kWave]);
+            float fx, gx, fy, gy;
+            unpack_frac(lw[5 * kWave], fx, gx);
+            unpack_frac(lw[6 * kWave], fy, gy);
             float bsum = 0.0f;
             while (mlo | mhi) {
                 int idx;
                 if (mlo) { idx = __builtin_ctz(mlo); mlo &= mlo - 1u; }
                 else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
                 const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
-                const int ge = g * 3 + e;
-                const uint32_t ak1 = hstep(kAngularSalt, angular_word(le.ai + (a & 1), le.aj + (a >> 1), 1));
-                const uint32_t h1 = rng_word<RNG>(sm.pre[ge][lane], ak1, sh, ltbl);
+                const uint32_t ak1 = angular_key(A, B, a & 1, a >> 1, 1);
+                const uint32_t h1 = rng_word<RNG>(pick43(pre, g, e), ak1, sh, ltbl);
                 // Eq. 17 for node g: m = max(n - 1, 0), 1 + mu, sigma (the adjoint repeats this arithmetic)
-                const float ng = R.ng[g];
+                const float ng = sm.ng[g][ip];
                 const float m = fmaxf(ng - 1.0f, 0.0f);
                 const float x = fmaf(__builtin_amdgcn_sqrtf(m * p * (1.0f - p)), ndtri_bits(h1), 1.0f + m * p);
                 const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
-                const float va = ((a & 1) ? le.fx : le.gx) * ((a & 2) ? le.fy : le.gy);   // bilinear weight (Eq. 14)
-                bsum = fmaf(sm.beta[ge][lane] * va, c, bsum);
+                const float va = ((a & 1) ? fx : gx) * ((a & 2) ? fy : gy);   // bilinear weight (Eq. 14)
+                bsum = fmaf(pick43(beta, g, e) * va, c, bsum);
                 if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
             }
-            const float G = 1.0f / ((1.0f + R.lam_i) * (1.0f + le.lam_o));
-            f = le.F * G * R.kpx * bsum;
+            f = __uint_as_float(lw[7 * kWave]) * bsum;
             if (DEBUG) o.b[li] = bsum;
         } while (false);
         if constexpr (LK == 1) {
@@ -319,11 +432,18 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 
 // ---------------------------------------------------------------------------
 // One tile of 64 pixels (tile_w x 64/tile_w) at (x0, y0) of a view.
+//  1. lane = pixel: footprint, probes, grid nodes (setup_pixel), the pixel's
+//     LDS fields, and one record per light (make_light_rec).
+//  2. a wave prefix sum flattens the tile's (pixel, probe) items; lanes take
+//     them 64 at a time (two lanes per item in a last batch of at most 32).
+//  3. each pixel lane sums its own items' RGB in probe order, read from the
+//     item lanes' registers (cross-lane reads in a loop every lane runs).
+// lrec: the tile's dynamic LDS, n_light * kLightRecBytes.
 // ---------------------------------------------------------------------------
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LAW = kLawDistributed>
 __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
-                           int lw, TileSmem<DEBUG> &sm, const uint32_t *ltbl = nullptr, uint16_t *lit = nullptr,
-                           uint32_t *lit_probes = nullptr, float *zden = nullptr)
+                           int lw, TileSmem<DEBUG> &sm, uint32_t *lrec, const uint32_t *ltbl = nullptr,
+                           uint16_t *lit = nullptr, uint32_t *lit_probes = nullptr, float *zden = nullptr)
 {
     const int lane = threadIdx.x;
     const int tmask = (1 << lw) - 1;
@@ -340,12 +460,29 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
         if (inb) setup_pixel<DEBUG>(vw, idx, sh, px);
         if (px.flags & F_SHADED) {
             npr = px.npr;
-            sm.rec[lane] = make_rec(px, sh);
-            if constexpr (LAW == kLawZk) {
-                // the baseline needs the node weights and N, not their products
+            const PixelRec r = make_rec(px, sh);
+            sm.ex[lane] = (float)r.ex;
+            sm.ey[lane] = (float)r.ey;
+            {
+                // node codes of PixelRec (two per word, at bits 0 and 16) as one 36-bit string
+                const uint64_t D = (uint64_t)(r.nd[0] & 0x1ffu) | ((uint64_t)((r.nd[0] >> 16) & 0x1ffu) << 9) |
+                                   ((uint64_t)(r.nd[1] & 0x1ffu) << 18) | ((uint64_t)((r.nd[1] >> 16) & 0x1ffu) << 27);
+                sm.pk[lane] = r.pk | ((uint32_t)(D & 0x3fu) << 26);
+                sm.nd[lane] = (uint32_t)(D >> 6);
+            }
 #pragma unroll
-                for (int g = 0; g < 4; ++g) sm.rec[lane].ng[g] = px.nw[g];
-                zden[lane] = px.N;
+            for (int g = 0; g < 4; ++g) sm.ng[g][lane] = LAW == kLawZk ? px.nw[g] : r.ng[g];
+            if constexpr (LAW == kLawZk) zden[lane] = px.N;   // the baseline needs the weights and N
+            const DevMaterial &M = sh.mats[px.mat];
+            ViewFrame fr;
+            view_frame(px.n, px.wi, fr);
+            for (int li = 0; li < sh.n_light; ++li) {
+                uint32_t w[kLightRecWords];
+                bool pclamp;
+                make_light_rec(px, r, M, sh.lights[li], fr, w, pclamp);
+                if (pclamp) px.flags |= F_CLAMP_P;
+#pragma unroll
+                for (int k = 0; k < kLightRecWords; ++k) lrec[((size_t)li * kLightRecWords + k) * kWave + lane] = w[k];
             }
         }
         if (DEBUG) {
@@ -363,7 +500,6 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     }
     const int off = incl - npr;
     const int S = __shfl(incl, kWave - 1);
-    sm.off[lane] = off;
     __syncthreads();
     float acc[3] = {0.0f, 0.0f, 0.0f};
     uint32_t litacc = 0u, probeacc = 0u;
@@ -377,59 +513,64 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
         // result is on its even lane
         const int lk = (!DEBUG && S - base <= kWave / 2 && sh.n_light > 1) ? 2 : 1;
         const int q = base + (lk == 2 ? lane >> 1 : lane);
+        float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f;
+        uint32_t ol = 0u;
+        // the item's pixel and probe, with every lane active (cross-lane reads)
+        const int qc = q < S ? q : S - 1;
+        const int p = item_pixel(off, qc);
+        const int kp = qc - __shfl(off, p);
         if (q < S) {
-            const int p = item_pixel(sm.off, q);
-            const int kp = q - sm.off[p];
             const int64_t pidx = (int64_t)(y0 + (p >> lw)) * vw.stride + (x0 + (p & tmask));
-            double n[3], wi[3];
-            normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
-            normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
             ItemOut o;
             const float zN = LAW == kLawZk ? zden[p] : 0.0f;
+            const double pu = (double)vw.u[pidx], pv = (double)vw.v[pidx];
             if (DEBUG || lk == 1)
-                shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm.rec[p], (double)vw.u[pidx], (double)vw.v[pidx], n, wi,
-                                                          kp, sh, sm, o, ltbl, zN);
+                shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
             else
-                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2, LAW>(sm.rec[p], (double)vw.u[pidx],
-                                                                      (double)vw.v[pidx], n, wi, kp, sh, sm, o,
-                                                                      ltbl, zN);
+                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
             if constexpr (DEBUG) {
                 sm.dslot[lane] = o;
             } else {
-                sm.pre[0][lane] = __float_as_uint(o.rgb[0]);
-                sm.pre[1][lane] = __float_as_uint(o.rgb[1]);
-                sm.pre[2][lane] = __float_as_uint(o.rgb[2]);
-                if (LIT) sm.pre[3][lane] = o.lit;
+                o0 = o.rgb[0];
+                o1 = o.rgb[1];
+                o2 = o.rgb[2];
+                if (LIT) ol = o.lit;
             }
         }
-        __syncthreads();
-        if (npr > 0) {
-            const int i0 = max(off, base), i1 = min(off + npr, base + kWave);
+        const int i0 = max(off, base), i1 = min(off + npr, base + kWave);
+        if constexpr (DEBUG) {
+            __syncthreads();
             for (int i = i0; i < i1; ++i) {
-                if constexpr (DEBUG) {
-                    const ItemOut &s = sm.dslot[i - base];
-                    acc[0] += s.rgb[0];
-                    acc[1] += s.rgb[1];
-                    acc[2] += s.rgb[2];
-                    dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
-                    dnl += s.n_live;
-                    dns += s.n_live_small;
-                    dlt += s.n_lit;
-                    for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
-                } else {
-                    const int slot = (i - base) * lk;      // the item's owner lane
-                    acc[0] += __uint_as_float(sm.pre[0][slot]);
-                    acc[1] += __uint_as_float(sm.pre[1][slot]);
-                    acc[2] += __uint_as_float(sm.pre[2][slot]);
+                const ItemOut &s = sm.dslot[i - base];
+                acc[0] += s.rgb[0];
+                acc[1] += s.rgb[1];
+                acc[2] += s.rgb[2];
+                dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
+                dnl += s.n_live;
+                dns += s.n_live_small;
+                dlt += s.n_lit;
+                for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
+            }
+            __syncthreads();
+        } else {
+            // every lane runs the loop (the reads need all lanes); lane k of a
+            // pixel's range reads the item's owner lane
+            const int cnt = i1 > i0 ? i1 - i0 : 0;
+            for (int k = 0; __ballot(k < cnt) != 0ull; ++k) {
+                const int src = k < cnt ? (i0 + k - base) * lk : lane;
+                const float r0 = __shfl(o0, src), r1 = __shfl(o1, src), r2 = __shfl(o2, src);
+                const uint32_t rl = LIT ? (uint32_t)__shfl((int)ol, src) : 0u;
+                if (k < cnt) {
+                    acc[0] += r0;
+                    acc[1] += r1;
+                    acc[2] += r2;
                     if (LIT) {
-                        const uint32_t m = sm.pre[3][slot];
-                        litacc |= m;
-                        probeacc |= m ? 1u << min(i - off, 31) : 0u;   // bit 31: probe 31 or a later one
+                        litacc |= rl;
+                        probeacc |= rl ? 1u << min(i0 + k - off, 31) : 0u;   // bit 31: probe 31 or a later one
                     }
                 }
             }
         }
-        __syncthreads();
     }
     if (inb) {
         const int64_t npx = (int64_t)vw.height * vw.stride;
@@ -462,35 +603,38 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
 
 // One workgroup per tile.  With a tile order (cost classes, heaviest first)
 // workgroup b shades tile order[b]; without one, tiles go in row-major order.
-// RNG selects the source of the gate uniforms (rng_word); with kRngTableLds
-// the wave first copies the table (rng_mask + 1 words, a multiple of 4,
-// 16-byte aligned) into its dynamic LDS.
+// Dynamic LDS: the tile's light records (n_light * kLightRecBytes), then,
+// with RNG = kRngTableLds, the wave's copy of the random-number table
+// (rng_mask + 1 words, a multiple of 4, 16-byte aligned), or with
+// LAW = kLawZk the tile's flake densities (64 floats).
+// RNG selects the source of the gate uniforms (rng_word).
 // With LIT the kernel also writes, per pixel, the bit mask of the lights that
 // opened a gate in any of the pixel's probes (lit[y * stride + x]) and, if
 // lit_probes is given, the bit mask of the probes that opened one (bit k:
 // probe k, bit 31: probe 31 or a later one).
-// With LAW = kLawZk the dynamic LDS holds the tile's flake densities
-// (64 floats).
 template <bool DEBUG, int RNG = kRngHash, bool LIT = false, int LAW = kLawDistributed>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DEBUG ? 1 : 4))) void glint_fwd_kernel(
     ViewDesc vw, Shared sh, DebugPlanes dp, int lw, int tiles_x, const int32_t *__restrict__ order, int32_t n_tiles,
     uint16_t *__restrict__ lit, uint32_t *__restrict__ lit_probes)
 {
     __shared__ TileSmem<DEBUG> sm;
-    extern __shared__ uint4 glint_rng_lds[];
+    extern __shared__ uint4 glint_dyn_lds[];
     const int t = order ? __builtin_amdgcn_readfirstlane(order[blockIdx.x]) : (int)blockIdx.x;
     if ((unsigned)t >= (unsigned)n_tiles) return;
     const int tx = t % tiles_x, ty = t / tiles_x;
+    uint32_t *lrec = reinterpret_cast<uint32_t *>(glint_dyn_lds);
+    uint32_t *tail = lrec + (size_t)sh.n_light * kLightRecWords * kWave;
     const uint32_t *ltbl = nullptr;
     if constexpr (RNG == kRngTableLds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(sh.rng_tbl);
+        uint4 *dst = reinterpret_cast<uint4 *>(tail);
         const int n4 = (int)((sh.rng_mask + 1u) >> 2);
-        for (int i = threadIdx.x; i < n4; i += kWave) glint_rng_lds[i] = src[i];
+        for (int i = threadIdx.x; i < n4; i += kWave) dst[i] = src[i];
         __syncthreads();
-        ltbl = reinterpret_cast<const uint32_t *>(glint_rng_lds);
+        ltbl = tail;
     }
-    float *zden = LAW == kLawZk ? reinterpret_cast<float *>(glint_rng_lds) : nullptr;
-    shade_tile<DEBUG, RNG == kRngHash, RNG, LIT, LAW>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, ltbl, lit,
+    float *zden = LAW == kLawZk ? reinterpret_cast<float *>(tail) : nullptr;
+    shade_tile<DEBUG, RNG == kRngHash, RNG, LIT, LAW>(vw, sh, dp, tx << lw, ty << (6 - lw), lw, sm, lrec, ltbl, lit,
                                                      lit_probes, zden);
 }
 
@@ -769,6 +913,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void gl
 {
     __shared__ TileSmem<false> sm;
     __shared__ int s_t0;
+    extern __shared__ uint4 glint_dyn_lds[];
+    uint32_t *lrec = reinterpret_cast<uint32_t *>(glint_dyn_lds);
     DebugPlanes dp = {};
     for (;;) {
         if (threadIdx.x == 0) s_t0 = (int)atomicAdd(counter, (unsigned int)chunk);
@@ -793,7 +939,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void gl
             // in registers across every tile and halve the occupancy)
             const Shared *sp = shp;
             asm volatile("" : "+s"(sp));
-            shade_tile<false, false>(vw, *sp, dp, tx << lw, ty << (6 - lw), lw, sm);
+            shade_tile<false, false>(vw, *sp, dp, tx << lw, ty << (6 - lw), lw, sm, lrec);
         }
     }
 }
@@ -808,6 +954,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
     int lw, const Shared *__restrict__ shp)
 {
     __shared__ TileSmem<false> sm;
+    extern __shared__ uint4 glint_dyn_lds[];
     const int t = (int)blockIdx.x;
     if (t >= n_tiles) return;
     int lo = 0, hi = n_views;
@@ -821,7 +968,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
     const int tiles_x = (vw.width + (1 << lw) - 1) >> lw;
     const int tx = local % tiles_x, ty = local / tiles_x;
     DebugPlanes dp = {};
-    shade_tile<false>(vw, *shp, dp, tx << lw, ty << (6 - lw), lw, sm);
+    shade_tile<false>(vw, *shp, dp, tx << lw, ty << (6 - lw), lw, sm, reinterpret_cast<uint32_t *>(glint_dyn_lds));
 }
 
 // bit-exactness utilities ----------------------------------------------------
@@ -924,37 +1071,40 @@ static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb,
         if (rc) return rc;
     }
     const dim3 grid((unsigned)nt), block(kWave);
+    // dynamic LDS: the light records, then the table copy or the flake densities
+    const unsigned rec_b = (unsigned)(sh.n_light * kLightRecBytes);
+    const unsigned zk_b = rec_b + kWave * sizeof(float);
     if (dbg) {
         // the instrumented kernel reads a table through the caches: same words as from LDS
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light,
                           dbg->n_live_small, dbg->n_lit};
         if (law == kLawZk)
-            hipLaunchKernelGGL((glint_fwd_kernel<true, kRngHash, false, kLawZk>), grid, block, kWave * sizeof(float),
-                               st, vw, sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
+            hipLaunchKernelGGL((glint_fwd_kernel<true, kRngHash, false, kLawZk>), grid, block, zk_b, st, vw, sh, dp,
+                               kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
         else if (rng == kRngHash)
-            hipLaunchKernelGGL(glint_fwd_kernel<true>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
+            hipLaunchKernelGGL(glint_fwd_kernel<true>, grid, block, rec_b, st, vw, sh, dp, kTileLw, tiles_x, order,
                                (int32_t)nt, nullptr, nullptr);
         else
-            hipLaunchKernelGGL((glint_fwd_kernel<true, kRngTable>), grid, block, 0, st, vw, sh, dp, kTileLw,
+            hipLaunchKernelGGL((glint_fwd_kernel<true, kRngTable>), grid, block, rec_b, st, vw, sh, dp, kTileLw,
                                tiles_x, order, (int32_t)nt, nullptr, nullptr);
     } else {
         DebugPlanes dp = {};
         if (law == kLawZk)
-            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngHash, false, kLawZk>), grid, block, kWave * sizeof(float),
-                               st, vw, sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
+            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngHash, false, kLawZk>), grid, block, zk_b, st, vw, sh, dp,
+                               kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
         else if (rng == kRngHash && lit)
-            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngHash, true>), grid, block, 0, st, vw, sh, dp, kTileLw,
+            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngHash, true>), grid, block, rec_b, st, vw, sh, dp, kTileLw,
                                tiles_x, order, (int32_t)nt, lit, lit_probes);
         else if (rng == kRngHash)
-            hipLaunchKernelGGL(glint_fwd_kernel<false>, grid, block, 0, st, vw, sh, dp, kTileLw, tiles_x, order,
+            hipLaunchKernelGGL(glint_fwd_kernel<false>, grid, block, rec_b, st, vw, sh, dp, kTileLw, tiles_x, order,
                                (int32_t)nt, nullptr, nullptr);
         else if (rng == kRngTable)
-            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTable>), grid, block, 0, st, vw, sh, dp, kTileLw,
+            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTable>), grid, block, rec_b, st, vw, sh, dp, kTileLw,
                                tiles_x, order, (int32_t)nt, nullptr, nullptr);
         else
-            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTableLds>), grid, block, (unsigned)lds_bytes, st, vw,
-                               sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
+            hipLaunchKernelGGL((glint_fwd_kernel<false, kRngTableLds>), grid, block, rec_b + (unsigned)lds_bytes, st,
+                               vw, sh, dp, kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLINT_OK : set_hip_error(e);
@@ -1154,13 +1304,15 @@ int glint_plan_create(const glint_gbuffer *gbufs, float *const *out_rgb, int32_t
 static int enqueue_batched(glint_plan *P, hipStream_t st)
 {
     if (P->per_tile) {
-        hipLaunchKernelGGL(glint_batched_grid_kernel, dim3((unsigned)P->n_tiles), dim3(kWave), 0, st, P->d_views,
+        hipLaunchKernelGGL(glint_batched_grid_kernel, dim3((unsigned)P->n_tiles), dim3(kWave),
+                           (unsigned)(P->sh.n_light * kLightRecBytes), st, P->d_views,
                            P->d_tile_start, P->n_views, (int32_t)P->n_tiles, log2_tile(P->tile_w), P->d_sh);
         hipError_t e = hipGetLastError();
         return e == hipSuccess ? GLINT_OK : set_hip_error(e);
     }
     hipLaunchKernelGGL(glint_reset_counter, dim3(1), dim3(1), 0, st, P->d_counter);
-    hipLaunchKernelGGL(glint_batched_kernel, dim3((unsigned)P->n_blocks), dim3(kWave), 0, st, P->d_views,
+    hipLaunchKernelGGL(glint_batched_kernel, dim3((unsigned)P->n_blocks), dim3(kWave),
+                       (unsigned)(P->sh.n_light * kLightRecBytes), st, P->d_views,
                        P->d_tile_start, P->n_views, (int32_t)P->n_tiles, log2_tile(P->tile_w), P->chunk,
                        P->d_counter, P->d_sh);
     hipError_t e = hipGetLastError();
