@@ -67,8 +67,13 @@ enum {
  * the pixel (output 0); material_id >= n_mat marks it invalid (output 0);
  * NULL material_id means material 0 everywhere.  alpha_px and
  * log10_density_px, when non-NULL, override the material's roughness and
- * flake density per pixel.  Non-finite inputs, det J = 0 or a view below
- * the surface give output 0. */
+ * flake density per pixel.  tx, ty, tz (all three or none; NULL: the
+ * orthonormal basis of n of Duff et al. 2017) give a tangent per pixel whose
+ * component orthogonal to n, normalised, is the first axis t of the angular
+ * grid, with b = n x t (Sec. 5.2, Eq. 14); it need not be unit length.
+ * Non-finite inputs, det J = 0, a view below the surface or a supplied
+ * tangent within about 1e-3 rad of n (sin^2 of the angle below 1e-6) or of
+ * zero length give output 0 (flag bit 3). */
 typedef struct {
     int32_t width, height;
     int64_t stride;
@@ -77,6 +82,7 @@ typedef struct {
     const int32_t *material_id;
     const float *alpha_px;
     const float *log10_density_px;
+    const float *tx, *ty, *tz;
 } glint_gbuffer;
 
 /* Glint material (Sec. 3).  ndf: 0 GGX, 1 Beckmann.  alpha > 0: roughness of

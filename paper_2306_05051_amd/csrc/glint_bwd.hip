@@ -197,8 +197,8 @@ __device__ __forceinline__ bool light_grad(const PixelRec &R, const double n[3],
 // Lights whose bit in litm is clear are skipped: the forward opened none of
 // their gates in this pixel, so they contribute exactly zero.
 __device__ void grad_item(bool live, const PixelRec &R, double u, double v, const double n[3], const double wi[3],
-                          int kp, const Shared &sh, const float gout[3], uint32_t litm, float &da, float &dn,
-                          BwdSmem &sm)
+                          double rc, double rs, int kp, const Shared &sh, const float gout[3], uint32_t litm,
+                          float &da, float &dn, BwdSmem &sm)
 {
     da = 0.0f;
     dn = 0.0f;
@@ -208,7 +208,7 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
     uint32_t pre[4][3];
     if (live) probe_texels(R, u, v, kp, M, sh, pre, sm, (uint32_t *)nullptr);
     ViewFrame fr = {};
-    if (live) view_frame(n, wi, fr);
+    if (live) view_frame(n, wi, rc, rs, fr);
     const float alpha = live ? R.alpha : 1.0f;
     const float kpx = live ? R.kpx : 0.0f, lam_i = live ? R.lam_i : 0.0f;
     float dli_da = 0.0f, dl_dc;                 // d Lambda(view) / d alpha
@@ -241,8 +241,8 @@ __device__ void grad_item(bool live, const PixelRec &R, double u, double v, cons
 // lane's own: d/d alpha and d/d ln N of the pixel's material (da, dn) and
 // d/d dir of light li (gd).  Lanes with live = false return zeros.
 __device__ __forceinline__ void grad_item_light(bool live, const PixelRec &R, double u, double v, const double n[3],
-                                const double wi[3], int kp, int li, const Shared &sh, const float gout[3], float &da,
-                                float &dn, float gd[3], BwdSmem &sm)
+                                const double wi[3], double rc, double rs, int kp, int li, const Shared &sh,
+                                const float gout[3], float &da, float &dn, float gd[3], BwdSmem &sm)
 {
     da = 0.0f;
     dn = 0.0f;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void grad_item_light(bool live, const PixelRec &R, do
     uint32_t pre[4][3];
     probe_texels(R, u, v, kp, M, sh, pre, sm, (uint32_t *)nullptr);
     ViewFrame fr;
-    view_frame(n, wi, fr);
+    view_frame(n, wi, rc, rs, fr);
     float dli_da, dl_dc;                          // d Lambda(view) / d alpha
     smith_lambda_grad(M.ndf, R.alpha, (float)fr.cos_i, (float)(1.0 - fr.cos_i * fr.cos_i), dl_dc, dli_da);
     light_grad(R, n, wi, M, fr, pre, nn, R.alpha, R.kpx, R.lam_i, dli_da, (float)M.inv_micro, sh.lights[li], gout,
@@ -352,12 +352,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         const uint32_t pm = __shfl(pmask, p);
         float g3[3] = {0.0f, 0.0f, 0.0f};
         uint32_t litm = 0u;
-        double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, u = 0.0, v = 0.0;
+        double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, u = 0.0, v = 0.0, rc = 1.0, rs = 0.0;
         if (live) {
             kp = q - sm.off[p];
             if (pm != 0xffffffffu) kp = nth_bit(pm, kp);
             normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
             normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
+            if (vw.tx) tangent_rotation(n, vw.tx[pidx], vw.ty[pidx], vw.tz[pidx], rc, rs);
             u = vw.u[pidx];
             v = vw.v[pidx];
             g3[0] = gout[pidx];
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
             litm = lit ? (uint32_t)lit[pidx] : 0xffffffffu;
         }
         float da, dn;
-        grad_item(live, sm.rec[p], u, v, n, wi, kp, sh, g3, litm, da, dn, sm);
+        grad_item(live, sm.rec[p], u, v, n, wi, rc, rs, kp, sh, g3, litm, da, dn, sm);
         sm.pre[0][lane] = live ? (uint32_t)rec_mat(sm.rec[p]) : 0xffffffffu;
         sm.pre[1][lane] = __float_as_uint(da);
         sm.pre[2][lane] = __float_as_uint(dn);
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
             const bool live = r < S && rec_npr(sm.rec[p]) > 0;
             int kp = 0, li = 0;
             float g3[3] = {0.0f, 0.0f, 0.0f};
-            double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, uu = 0.0, vv = 0.0;
+            double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, uu = 0.0, vv = 0.0, rc = 1.0, rs = 0.0;
             if (live) {
                 const uint32_t pidx = list[c * kWave + (uint32_t)p];
                 const uint32_t pm = lit_probes[pidx], litm = (uint32_t)lit[pidx] & lmask;
@@ -541,6 +542,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
                 li = nth_bit(litm, lr);
                 normalize_in(vw.nx[pidx], vw.ny[pidx], vw.nz[pidx], n);
                 normalize_in(vw.wx[pidx], vw.wy[pidx], vw.wz[pidx], wi);
+                if (vw.tx) tangent_rotation(n, vw.tx[pidx], vw.ty[pidx], vw.tz[pidx], rc, rs);
                 uu = vw.u[pidx];
                 vv = vw.v[pidx];
                 g3[0] = gout[pidx];
@@ -548,7 +550,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
                 g3[2] = gout[2 * npx + pidx];
             }
             float da, dn, gd[3];
-            grad_item_light(live, sm.rec[p], uu, vv, n, wi, kp, li, sh, g3, da, dn, gd, sm);
+            grad_item_light(live, sm.rec[p], uu, vv, n, wi, rc, rs, kp, li, sh, g3, da, dn, gd, sm);
             // per material and per light, a wave sum over the lanes of that
             // material or light (fixed order); lane m keeps material m's sums
             const int mat = live ? rec_mat(sm.rec[p]) : -1;

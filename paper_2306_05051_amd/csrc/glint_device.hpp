@@ -74,6 +74,7 @@ struct ViewDesc {
     const int32_t *mat;
     const float *alpha_px, *log10N_px;
     float *out;
+    const float *tx, *ty, *tz;   // optional supplied tangent (all three or none)
 };
 
 struct DebugPlanes {
@@ -197,6 +198,7 @@ struct Pixel {
     int mat;
     float alpha, N;            // roughness, flakes per unit UV area
     double n[3], wi[3];
+    double rc, rs;             // tangent frame: rotation of the basis of n (1, 0 without a tangent)
     double cos_i;
     double u, v, P;            // uv and |det J|
     double ex, ey;             // sigma0 * major axis direction
@@ -264,6 +266,85 @@ __device__ __forceinline__ double log2_ratio(double x)
     return (double)e + (2.88539008177792681472 * s) * t;
 }
 
+// The tangent frame (t, b, n) of the angular grid (Eq. 14).  The orthonormal
+// basis (t0, b0, n) of n after Duff et al. (2017) is kept in implicit form:
+// with s = sign(n_z) and a = -1/(s + n_z) its axes are
+// t0 = (1 + s a nx^2, s a nx ny, -s nx) and b0 = (a nx ny, s + a ny^2, -ny),
+// so for any w, with d = a (nx wx + ny wy) - wz:
+//   <t0, w> = wx + s nx d,   <b0, w> = s wy + ny d.
+// A supplied tangent (reading of Sec. 5.2: made orthogonal to n and
+// normalised, b = n x t) lies in the span of t0 and b0, so the frame is t0, b0
+// turned about n by the unit rotation (rc, rs): t = rc t0 + rs b0 and
+// b = n x t = -rs t0 + rc b0 (the basis is right-handed).  Without a tangent
+// (rc, rs) = (1, 0), and the rotation reproduces <t0, w>, <b0, w> exactly.
+struct ViewFrame {
+    double a, s, snx;          // a, s = sign(n_z), s n_x
+    double rc, rs;             // rotation of (t0, b0) into (t, b)
+    double cos_i, wt, wb;      // <n, wi>, <wi, t>, <wi, b>
+};
+
+// <t, w> and <b, w> from nw = nx wx + ny wy
+__device__ __forceinline__ void frame_dots(const double n[3], const ViewFrame &f, const double w[3], double nw,
+                                           double &tw, double &bw)
+{
+    const double d = f.a * nw - w[2];
+    const double t0 = fma(f.snx, d, w[0]);
+    const double b0 = fma(n[1], d, f.s * w[1]);
+    tw = fma(f.rs, b0, f.rc * t0);
+    bw = fma(f.rc, b0, -(f.rs * t0));
+}
+
+// the axes themselves (the adjoint's light-direction gradient)
+__device__ __forceinline__ void frame_axes(const double n[3], const ViewFrame &f, double t[3], double b[3])
+{
+    const double bb = n[0] * n[1] * f.a;
+    const double t0[3] = {1.0 + f.snx * n[0] * f.a, f.s * bb, -f.snx};
+    const double b0[3] = {bb, f.s + n[1] * n[1] * f.a, -n[1]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        t[c] = fma(f.rs, b0[c], f.rc * t0[c]);
+        b[c] = fma(f.rc, b0[c], -(f.rs * t0[c]));
+    }
+}
+
+__device__ __forceinline__ void view_frame(const double n[3], const double wi[3], double rc, double rs, ViewFrame &f)
+{
+    f.s = copysign(1.0, n[2]);
+    f.a = -rcp_d(f.s + n[2]);                      // |s + n_z| >= 1
+    f.snx = f.s * n[0];
+    f.rc = rc;
+    f.rs = rs;
+    f.cos_i = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
+    frame_dots(n, f, wi, n[0] * wi[0] + n[1] * wi[1], f.wt, f.wb);
+}
+
+// The rotation (rc, rs) of a supplied tangent (FP32 inputs tin) about the unit
+// normal n: rc = <tin, t0>/q, rs = <tin, b0>/q with q the length of tin's
+// component in the tangent plane.  A tangent within about 1e-3 rad of n
+// (sin^2 of the angle below 1e-6, the reading's threshold) or of zero length
+// defines no frame: returns false (invalid input).
+constexpr double kTangentMinSin2 = 1e-6;
+__device__ __forceinline__ bool tangent_rotation(const double n[3], float tx, float ty, float tz, double &rc,
+                                                 double &rs)
+{
+    ViewFrame f;
+    f.s = copysign(1.0, n[2]);
+    f.a = -rcp_d(f.s + n[2]);
+    f.snx = f.s * n[0];
+    f.rc = 1.0;
+    f.rs = 0.0;
+    const double t[3] = {tx, ty, tz};
+    double c, sn;
+    frame_dots(n, f, t, n[0] * t[0] + n[1] * t[1], c, sn);
+    const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];   // exact: products of FP32 values
+    const double q2 = c * c + sn * sn;
+    if (!(tt > 0.0) || !(q2 >= kTangentMinSin2 * tt)) return false;
+    const double iq = rsqrt_d(q2);
+    rc = c * iq;
+    rs = sn * iq;
+    return true;
+}
+
 template <bool DEBUG>
 __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, const Shared &sh, Pixel &px)
 {
@@ -283,15 +364,24 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
     const float fwx = vw.wx[idx], fwy = vw.wy[idx], fwz = vw.wz[idx];
     const float alpha = vw.alpha_px ? vw.alpha_px[idx] : M.alpha;
     const float l10 = vw.log10N_px ? vw.log10N_px[idx] : M.log10N;
+    const float ftx = vw.tx ? vw.tx[idx] : 0.0f, fty = vw.tx ? vw.ty[idx] : 0.0f, ftz = vw.tx ? vw.tz[idx] : 0.0f;
     const int fin = (int)finitef(fu) & (int)finitef(fv) & (int)finitef(dux) & (int)finitef(dvx) &
                     (int)finitef(duy) & (int)finitef(dvy) & (int)finitef(fnx) & (int)finitef(fny) &
                     (int)finitef(fnz) & (int)finitef(fwx) & (int)finitef(fwy) & (int)finitef(fwz) &
-                    (int)finitef(alpha) & (int)finitef(l10);
+                    (int)finitef(alpha) & (int)finitef(l10) & (int)finitef(ftx) & (int)finitef(fty) &
+                    (int)finitef(ftz);
     if (!fin || !(alpha > 0.0f)) { px.flags = F_BAD_INPUT; return; }
     px.alpha = alpha;
     px.N = exp10f(l10);
     // normal and view, FP64 normalised
     if (!normalize_in(fnx, fny, fnz, px.n) || !normalize_in(fwx, fwy, fwz, px.wi)) {
+        px.flags = F_BAD_INPUT;
+        return;
+    }
+    // the angular grid's frame (Eq. 14): the supplied tangent, else the basis of n
+    px.rc = 1.0;
+    px.rs = 0.0;
+    if (vw.tx && !tangent_rotation(px.n, ftx, fty, ftz, px.rc, px.rs)) {
         px.flags = F_BAD_INPUT;
         return;
     }
@@ -559,42 +649,6 @@ __device__ __forceinline__ float success_prob(int ndf, float alpha, float R, flo
     float p = R * ratio;
     clamped = p > 1.0f;
     return clamped ? 1.0f : p;
-}
-
-// Per item: the tangent frame of n (Duff et al. 2017) in implicit form and
-// the view's projections on it.  With s = sign(n_z) and a = -1/(s + n_z) the
-// axes are t = (1 + s a nx^2, s a nx ny, -s nx) and b = (a nx ny, s + a ny^2,
-// -ny), so for any w, with d = a (nx wx + ny wy) - wz:
-//   <t, w> = wx + s nx d,   <b, w> = s wy + ny d.
-struct ViewFrame {
-    double a, s, snx;          // a, s = sign(n_z), s n_x
-    double cos_i, wt, wb;      // <n, wi>, <wi, t>, <wi, b>
-};
-
-// <t, w> and <b, w> from nw = nx wx + ny wy
-__device__ __forceinline__ void frame_dots(const double n[3], const ViewFrame &f, const double w[3], double nw,
-                                           double &tw, double &bw)
-{
-    const double d = f.a * nw - w[2];
-    tw = fma(f.snx, d, w[0]);
-    bw = fma(n[1], d, f.s * w[1]);
-}
-
-// the axes themselves (the adjoint's light-direction gradient)
-__device__ __forceinline__ void frame_axes(const double n[3], const ViewFrame &f, double t[3], double b[3])
-{
-    const double bb = n[0] * n[1] * f.a;
-    t[0] = 1.0 + f.snx * n[0] * f.a; t[1] = f.s * bb; t[2] = -f.snx;
-    b[0] = bb; b[1] = f.s + n[1] * n[1] * f.a; b[2] = -n[1];
-}
-
-__device__ __forceinline__ void view_frame(const double n[3], const double wi[3], ViewFrame &f)
-{
-    f.s = copysign(1.0, n[2]);
-    f.a = -rcp_d(f.s + n[2]);                      // |s + n_z| >= 1
-    f.snx = f.s * n[0];
-    f.cos_i = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
-    frame_dots(n, f, wi, n[0] * wi[0] + n[1] * wi[1], f.wt, f.wb);
 }
 
 // Everything one light needs at one pixel (shared by the forward and the

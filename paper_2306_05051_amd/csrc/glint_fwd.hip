@@ -420,7 +420,7 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 {
     const DevMaterial &M = sh.mats[px.mat];
     ViewFrame fr;
-    view_frame(px.n, px.wi, fr);
+    view_frame(px.n, px.wi, px.rc, px.rs, fr);
     uint32_t s = 0;
     for (int li = 0; li < sh.n_light; ++li) {
         LightEval le;
@@ -475,7 +475,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             if constexpr (LAW == kLawZk) zden[lane] = px.N;   // the baseline needs the weights and N
             const DevMaterial &M = sh.mats[px.mat];
             ViewFrame fr;
-            view_frame(px.n, px.wi, fr);
+            view_frame(px.n, px.wi, px.rc, px.rs, fr);
             for (int li = 0; li < sh.n_light; ++li) {
                 uint32_t w[kLightRecWords];
                 bool pclamp;
@@ -898,6 +898,9 @@ __device__ __forceinline__ ViewDesc uniform_view(const ViewDesc &v)
     u.alpha_px = uniptr(v.alpha_px);
     u.log10N_px = uniptr(v.log10N_px);
     u.out = uniptr(v.out);
+    u.tx = uniptr(v.tx);
+    u.ty = uniptr(v.ty);
+    u.tz = uniptr(v.tz);
     return u;
 }
 

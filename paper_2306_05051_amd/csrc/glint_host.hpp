@@ -111,6 +111,11 @@ inline int make_view(const glint_gbuffer *g, float *out, ViewDesc &v)
     v.alpha_px = g->alpha_px;
     v.log10N_px = g->log10_density_px;
     v.out = out;
+    // tangent planes: all three or none
+    if ((g->tx || g->ty || g->tz) && !(g->tx && g->ty && g->tz)) return GLINT_ENULL;
+    v.tx = g->tx;
+    v.ty = g->ty;
+    v.tz = g->tz;
     return GLINT_OK;
 }
 

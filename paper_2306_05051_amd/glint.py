@@ -6,7 +6,11 @@ binding refuses to run when the library is missing; there is no CPU path.
 
 A G-buffer is a dict of CUDA tensors of shape (H, W), dtype float32
 (u, v, dudx, dvdx, dudy, dvdy, nx, ny, nz, wx, wy, wz), an optional int32
-``material_id`` and optional float32 ``alpha_px`` / ``log10_density_px``.
+``material_id``, optional float32 ``alpha_px`` / ``log10_density_px`` and
+optional float32 tangent planes ``tx``, ``ty``, ``tz`` (all three or none).
+Planes may be row-padded views (element stride 1 along a row, one common row
+stride >= W for every plane, as ``to_device(..., stride=S)`` makes): the C
+ABI's ``stride``.  Outputs then come back as views of the same row stride.
 Materials are dicts (ndf, alpha, R, log10_density, micro_roughness, F0,
 seed) and lights are dicts (dir, radiance), as in ``include/glint.h``.
 """
@@ -44,7 +48,8 @@ class GlintError(RuntimeError):
 class _GBuf(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("stride", C.c_int64)] + \
                [(n, C.c_void_p) for n in PLANES] + \
-               [("material_id", C.c_void_p), ("alpha_px", C.c_void_p), ("log10_density_px", C.c_void_p)]
+               [("material_id", C.c_void_p), ("alpha_px", C.c_void_p), ("log10_density_px", C.c_void_p),
+                ("tx", C.c_void_p), ("ty", C.c_void_p), ("tz", C.c_void_p)]
 
 
 class _Mat(C.Structure):
@@ -139,20 +144,60 @@ def _dev_ptr(t, dtype, name):
     return t.data_ptr()
 
 
+TANGENT_PLANES = ("tx", "ty", "tz")
+
+
+def row_stride(gb):
+    """The common row stride (elements) of a G-buffer's planes."""
+    return gb["u"].stride(0) if gb["u"].dim() == 2 and gb["u"].shape[0] > 1 else gb["u"].shape[-1]
+
+
+def _plane_ptr(t, dtype, name, H, W, S):
+    if not (t.is_cuda and t.dtype == dtype and tuple(t.shape) == (H, W)):
+        raise ValueError(f"plane {name} must be a CUDA {dtype} tensor of shape {(H, W)}")
+    if W > 0 and H > 0 and (t.stride(1) != 1 or (H > 1 and t.stride(0) != S)):
+        raise ValueError(f"plane {name} must have element stride 1 and row stride {S}")
+    return t.data_ptr()
+
+
 def make_gbuffer(gb):
-    """ctypes G-buffer descriptor for a dict of CUDA tensors of shape (H, W)."""
+    """ctypes G-buffer descriptor for a dict of CUDA tensors of shape (H, W)
+    sharing one row stride."""
     H, W = gb["u"].shape
+    S = row_stride(gb)
     g = _GBuf()
-    g.width, g.height, g.stride = W, H, W
+    g.width, g.height, g.stride = W, H, S
     for n in PLANES:
-        if gb[n].shape != (H, W):
-            raise ValueError(f"plane {n} has shape {tuple(gb[n].shape)}, expected {(H, W)}")
-        setattr(g, n, _dev_ptr(gb[n], torch.float32, n))
-    g.material_id = _dev_ptr(gb["material_id"], torch.int32, "material_id") \
+        setattr(g, n, _plane_ptr(gb[n], torch.float32, n, H, W, S))
+    g.material_id = _plane_ptr(gb["material_id"], torch.int32, "material_id", H, W, S) \
         if gb.get("material_id") is not None else None
     for n in ("alpha_px", "log10_density_px"):
-        setattr(g, n, _dev_ptr(gb[n], torch.float32, n) if gb.get(n) is not None else None)
+        setattr(g, n, _plane_ptr(gb[n], torch.float32, n, H, W, S) if gb.get(n) is not None else None)
+    have = [gb.get(n) is not None for n in TANGENT_PLANES]
+    if any(have) and not all(have):
+        raise ValueError("tangent planes tx, ty, tz: give all three or none")
+    for n in TANGENT_PLANES:
+        setattr(g, n, _plane_ptr(gb[n], torch.float32, n, H, W, S) if gb.get(n) is not None else None)
     return g
+
+
+def _planes(n, H, W, S, dtype, device, fill=None):
+    """n planes [n][H*S] as a tensor view of shape (n, H, W) (or (H, W) for n = 0)."""
+    shape = (H, S) if n == 0 else (n, H, S)
+    t = torch.empty(shape, dtype=dtype, device=device) if fill is None else \
+        torch.full(shape, fill, dtype=dtype, device=device)
+    return t[..., :W]
+
+
+def _out_ptr(t, name, n, H, W, S, dtype=torch.float32):
+    """pointer of an output of n planes [n][H*S] given as a (n, H, W) view (or (H, W) for n = 0)"""
+    shape = (H, W) if n == 0 else (n, H, W)
+    strides = (S, 1) if n == 0 else (H * S, S, 1)
+    if not (t.is_cuda and t.dtype == dtype and tuple(t.shape) == shape):
+        raise ValueError(f"{name} must be a CUDA {dtype} tensor of shape {shape}")
+    if H * W > 0 and any(st != want for st, want, d in zip(t.stride(), strides, shape) if d > 1):
+        raise ValueError(f"{name} must have strides {strides} (row stride {S})")
+    return t.data_ptr()
 
 
 def make_materials(materials):
@@ -178,13 +223,23 @@ def make_params(k_max=4, n_probe_max=21, rounding=0, count_law=LAW_DISTRIBUTED):
     return _Params(int(k_max), int(n_probe_max), int(rounding), GLINT_FLAG_ZK_COUNT if count_law == LAW_ZK else 0)
 
 
-def to_device(gb_np, device="cuda"):
-    """numpy G-buffer dict -> dict of contiguous CUDA tensors."""
+def to_device(gb_np, device="cuda", stride=None):
+    """numpy G-buffer dict -> dict of CUDA tensors of shape (H, W); with
+    stride = S > W each plane is a view of (H, S) storage (padded rows, the
+    padding filled with NaN)."""
     out = {}
     for k, v in gb_np.items():
         if v is None:
             continue
-        out[k] = torch.from_numpy(v).to(device).contiguous()
+        t = torch.from_numpy(v).to(device).contiguous()
+        if stride is not None and stride != t.shape[1]:
+            if stride < t.shape[1]:
+                raise ValueError("stride must be at least the width")
+            fill = -7 if t.dtype == torch.int32 else float("nan")
+            pad = torch.full((t.shape[0], stride), fill, dtype=t.dtype, device=device)
+            pad[:, :t.shape[1]] = t
+            t = pad[:, :t.shape[1]]
+        out[k] = t
     return out
 
 
@@ -213,11 +268,12 @@ def glint_shade_noalloc(gbuf, materials, lights, k_max=4, n_probe_max=21, roundi
     None, which the C call itself never does)."""
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
+    S = g.stride
     if out is None:
-        out = torch.empty((3, H, W), dtype=torch.float32, device=gbuf["u"].device)
+        out = _planes(3, H, W, S, torch.float32, gbuf["u"].device)
     st = lib().glint_shade_noalloc(C.byref(g), make_materials(materials), len(materials), make_lights(lights),
                                    len(lights), C.byref(make_params(k_max, n_probe_max, rounding, count_law)),
-                                   _dev_ptr(out, torch.float32, "out"), _stream(stream))
+                                   _out_ptr(out, "out", 3, H, W, S), _stream(stream))
     _check(st, "glint_shade_noalloc")
     return out
 
@@ -255,9 +311,11 @@ def _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, wo
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
+    S = g.stride
     dev = gbuf["u"].device
     if out is None:
-        out = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        out = _planes(3, H, W, S, torch.float32, dev)
+    out_ptr = _out_ptr(out, "out", 3, H, W, S)
     nbytes = L.glint_shade_workspace_bytes(W, H)
     if workspace is False or nbytes == 0:
         ws_ptr, ws_bytes = None, 0
@@ -270,22 +328,21 @@ def _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, wo
     if debug:
         dbg = _Debug()
         for n, dt in DEBUG_FIELDS:
-            planes[n] = torch.zeros((H, W), dtype=dt, device=dev)
+            planes[n] = _planes(0, H, W, S, dt, dev, fill=0)
             setattr(dbg, n, planes[n].data_ptr())
-        planes["b_light"] = torch.zeros((max(1, len(lights)), H, W), dtype=torch.float32, device=dev)
+        planes["b_light"] = _planes(max(1, len(lights)), H, W, S, torch.float32, dev, fill=0)
         dbg.b_light = planes["b_light"].data_ptr()
         for n in WORK_FIELDS:
-            planes[n] = torch.zeros((H, W), dtype=torch.int32, device=dev)
+            planes[n] = _planes(0, H, W, S, torch.int32, dev, fill=0)
             setattr(dbg, n, planes[n].data_ptr())
     prm = make_params(k_max, n_probe_max, rounding, count_law)
     if rng is None:
         st = glint_shade_raw(g, make_materials(materials), len(materials), make_lights(lights), len(lights),
-                             prm, _dev_ptr(out, torch.float32, "out"), dbg, _stream(stream), ws_ptr, ws_bytes)
+                             prm, out_ptr, dbg, _stream(stream), ws_ptr, ws_bytes)
         _check(st, "glint_shade")
     else:
         st = L.glint_shade_rng_table(C.byref(g), make_materials(materials), len(materials), make_lights(lights),
-                                     len(lights), C.byref(prm), rng[0], rng[1], rng[2],
-                                     _dev_ptr(out, torch.float32, "out"),
+                                     len(lights), C.byref(prm), rng[0], rng[1], rng[2], out_ptr,
                                      C.byref(dbg) if dbg is not None else None, ws_ptr, ws_bytes, _stream(stream))
         _check(st, "glint_shade_rng_table")
     return (out, planes) if debug else out
@@ -308,20 +365,21 @@ def glint_shade_lit(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=1
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
+    S = g.stride
     dev = gbuf["u"].device
     if out is None:
-        out = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        out = _planes(3, H, W, S, torch.float32, dev)
     if lit is None:
-        lit = torch.empty((H, W), dtype=torch.int16, device=dev)
+        lit = _planes(0, H, W, S, torch.int16, dev)
     if probes is None:
-        probes = torch.empty((H, W), dtype=torch.int32, device=dev)
+        probes = _planes(0, H, W, S, torch.int32, dev)
     nbytes = L.glint_shade_workspace_bytes(W, H)
     if workspace is None or workspace is False:
         workspace = torch.empty(max(1, nbytes), dtype=torch.uint8, device=dev)
     st = L.glint_shade_lit(C.byref(g), make_materials(materials), len(materials), make_lights(lights),
                            len(lights), C.byref(make_params(k_max, n_probe_max, rounding)),
-                           _dev_ptr(out, torch.float32, "out"), _dev_ptr(lit, torch.int16, "lit"),
-                           _dev_ptr(probes, torch.int32, "probes"),
+                           _out_ptr(out, "out", 3, H, W, S), _out_ptr(lit, "lit", 0, H, W, S, torch.int16),
+                           _out_ptr(probes, "probes", 0, H, W, S, torch.int32),
                            _dev_ptr(workspace, torch.uint8, "workspace"), nbytes, _stream(stream))
     _check(st, "glint_shade_lit")
     return out, lit, probes
@@ -336,8 +394,18 @@ def glint_shade_backward(gbuf, materials, lights, grad_out, k_max=4, n_probe_max
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
+    S = g.stride
     dev = gbuf["u"].device
     nm, nl = len(materials), len(lights)
+    if grad_out.shape != (3, H, W):
+        raise ValueError(f"grad_out must have shape {(3, H, W)}")
+    try:
+        go_ptr = _out_ptr(grad_out, "grad_out", 3, H, W, S)
+    except ValueError:           # repack into the G-buffer's row stride
+        go = _planes(3, H, W, S, torch.float32, dev, fill=0.0)
+        go.copy_(grad_out)
+        grad_out = go
+        go_ptr = _out_ptr(grad_out, "grad_out", 3, H, W, S)
     ga = torch.empty(nm, dtype=torch.float32, device=dev)
     gn = torch.empty(nm, dtype=torch.float32, device=dev)
     gd = torch.empty((nl, 3), dtype=torch.float32, device=dev)
@@ -346,9 +414,9 @@ def glint_shade_backward(gbuf, materials, lights, grad_out, k_max=4, n_probe_max
         workspace = torch.empty(max(1, nbytes), dtype=torch.uint8, device=dev)
     st = L.glint_shade_backward(C.byref(g), make_materials(materials), nm, make_lights(lights), nl,
                                 C.byref(make_params(k_max, n_probe_max, 1)),
-                                _dev_ptr(grad_out.contiguous(), torch.float32, "grad_out"),
-                                None if lit is None else _dev_ptr(lit, torch.int16, "lit"),
-                                None if probes is None else _dev_ptr(probes, torch.int32, "probes"),
+                                go_ptr,
+                                None if lit is None else _out_ptr(lit, "lit", 0, H, W, S, torch.int16),
+                                None if probes is None else _out_ptr(probes, "probes", 0, H, W, S, torch.int32),
                                 ga.data_ptr(), gn.data_ptr(), gd.data_ptr(), workspace.data_ptr(),
                                 nbytes, _stream(stream))
     _check(st, "glint_shade_backward")
@@ -363,7 +431,8 @@ class GlintPlan:
         L = lib()
         n = len(gbufs)
         self._gb = (_GBuf * n)(*[make_gbuffer(g) for g in gbufs])
-        self._outs = (C.c_void_p * n)(*[_dev_ptr(o, torch.float32, "out") for o in outs])
+        self._outs = (C.c_void_p * n)(*[_out_ptr(o, "out", 3, gb.height, gb.width, gb.stride)
+                                        for o, gb in zip(outs, self._gb)])
         self._keep = (gbufs, outs)
         t = None
         if tune is not None:

@@ -333,20 +333,22 @@ def four_k(W=3840, H=2160, seed=3, n_mat=8, n_light=4, tile=16, grazing_frac=0.3
     return _finish(g), mats, lights
 
 
-def batched_views(n_views=64, seed=4, side_min=128, side_max=2048, max_side=None):
+def batched_views(n_views=64, seed=4, side_min=128, side_max=2048, max_side=None, workers=8):
     """n_views square views, side ~ round(exp U(ln 128, ln 2048)), each a
-    sphere_forward scene from its own random camera."""
+    sphere_forward scene from its own random camera (seed 100 + view index,
+    so the views do not depend on the order they are built in; `workers`
+    threads build them)."""
+    from concurrent.futures import ThreadPoolExecutor
     rng = np.random.Generator(np.random.PCG64(4000 + seed))
     sides = np.round(np.exp(rng.uniform(math.log(side_min), math.log(side_max), n_views))).astype(int)
     if max_side is not None:
         sides = np.minimum(sides, max_side)
-    views = []
-    mats = lights = None
-    for i, s in enumerate(sides):
-        gb, m, l = sphere_forward(int(s), int(s), seed=100 + i)
-        views.append(gb)
-        if mats is None:
-            mats, lights = m, l
+    # largest views first, so that the pool's last tasks are short
+    order = sorted(range(n_views), key=lambda i: -int(sides[i]))
+    with ThreadPoolExecutor(max_workers=max(1, int(workers))) as ex:
+        built = dict(zip(order, ex.map(lambda i: sphere_forward(int(sides[i]), int(sides[i]), seed=100 + i), order)))
+    views = [built[i][0] for i in range(n_views)]
+    mats, lights = built[0][1], built[0][2]
     return views, mats, lights
 
 

@@ -21,10 +21,15 @@ def compare(gpu_rgb, gpu_dbg, ref_rgb, ref_dbg, exact_fields=EXACT, rtol=RTOL, l
     """Returns a dict of statistics; raises AssertionError on a parity failure."""
     gflags = gpu_dbg["flags"].astype(np.uint32)
     rflags = ref_dbg["flags"].astype(np.uint32)
+    # every flag but the p <= 1 clamp (bit 2) is decided exactly on both sides
     assert np.array_equal(gflags & ~np.uint32(4), rflags & ~np.uint32(4)), \
         f"{label}: flags differ on {np.count_nonzero(gflags != rflags)} pixels"
     shaded = (rflags & 1) > 0
     ok = shaded & (ref_dbg["margin_pos"] >= MARGIN)
+    # the clamp (FP32 R D(h)/D(n) > 1 against FP64) wherever no decision, the
+    # clamp's included, is within the margin of its boundary
+    bad = ok & ((gflags & 4) != (rflags & 4))
+    assert not bad.any(), f"{label}: p-clamp flag differs on {bad.sum()} of {ok.sum()} pixels"
     for k in exact_fields:
         a = gpu_dbg[k].astype(np.int64) & 0xFFFFFFFF
         b = ref_dbg[k].astype(np.int64) & 0xFFFFFFFF
@@ -40,7 +45,8 @@ def compare(gpu_rgb, gpu_dbg, ref_rgb, ref_dbg, exact_fields=EXACT, rtol=RTOL, l
     # pixels that are not shaded are exactly zero on both sides
     assert np.all(g[:, ~shaded] == 0.0)
     stats = dict(shaded=int(shaded.sum()), checked=int(ok.sum()), near_boundary=int((shaded & ~ok).sum()),
-                 worst_rel=worst, nonzero=int((ref_rgb[0] > 0).sum()))
+                 worst_rel=worst, nonzero=int((ref_rgb[0] > 0).sum()),
+                 p_clamped=int(((rflags & 4) > 0).sum()))
     kinds = ref_dbg["margin_pos_kind"][shaded & ~ok]
     stats["near_boundary_kinds"] = {int(k): int(c) for k, c in zip(*np.unique(kinds, return_counts=True))}
     return stats

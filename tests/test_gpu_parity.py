@@ -132,6 +132,20 @@ def test_paper_setting_beckmann(glint, view, k_max, log10_density):
     _check(glint, gb, mats, lights, f"{view} K={k_max} logN={log10_density}", min_checked=0.75, k_max=k_max)
 
 
+@pytest.mark.parametrize("view", ["plane90", "plane25"])
+def test_p_clamp_flag(glint, view):
+    """Eq. 4's p = R D(h)/D(n) exceeds 1 for Beckmann alpha = 1 (up to 1.47 R)
+    once R is above 0.68 (reading S15: p clamped to 1, flag bit 2).  With
+    R = 0.8 a band of half-vector angles is clamped (13-52% of the pixels in
+    these views); the flag, compared wherever no decision sits within the
+    margin of its boundary, and the counts (every gate of a clamped light
+    opens) follow the oracle on both sides of the band's edges."""
+    gb, mats, lights = scenes.paper_setting(192, 108, view=view, log10_density=4.0, seed=3)
+    mats = [dict(mats[0], R=0.8)]
+    st = _check(glint, gb, mats, lights, f"p clamp {view}", min_checked=0.6)
+    assert 0.1 * st["shaded"] < st["p_clamped"] < 0.9 * st["shaded"], st
+
+
 def test_maximum_materials_and_lights(glint):
     """The largest parameter blocks the ABI takes: 32 materials, 16 lights."""
     gb, mats, lights = scenes.four_k(160, 96, seed=8, n_mat=32, n_light=16)
