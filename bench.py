@@ -1,6 +1,7 @@
 """Benchmark: glint-shaded Mpixel/s at 4K on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--batched]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-backward] [--no-batched] [--no-c5]
 
 Workload (one step = one forward shading of the whole frame, every step of
 the method): synthetic 3840x2160 G-buffer of a unit sphere over a ground
@@ -14,7 +15,12 @@ Prints ONE JSON line on stdout; progress goes to stderr.  The roofline entry
 prices the launch's algorithmic VALU work (costmodel.py: slots at the FP32
 issue rate, 78.6 T/s) against the time of one glint_shade call (shading
 kernel plus its tile-order pre-pass), measured with HIP events on the launch
-stream; cpu_baseline times the FP64 oracle on the host cores.
+stream; roofline_bwd does the same for the adjoint call of the 4K
+forward+backward step.  Extra keys: the rate over shaded pixels only, the 4K
+forward+backward rate, the batched path on 64 views of 128^2..2048^2 against
+64 glint_shade calls on the same stream, and the 1024^2 forward+backward
+(the adjoint's configuration).  cpu_baseline times the FP64 oracle on the
+host cores (model and thread count stated).
 """
 import argparse
 import json
@@ -103,8 +109,33 @@ def cpu_baseline(gb, mats, lights, target_s=10.0):
     dt1 = time.perf_counter() - t0
     return {"value": round(n_px / 1e6 / dt, 4), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
             "sample": what + "; FP64 C oracle (OpenMP over rows), same G-buffer, materials and lights",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "value_1_thread": round(n1 * W / 1e6 / dt1, 4),
             "sample_1_thread": f"{n1} of {H} rows (evenly spaced), {dt1:.2f} s on one thread"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def timed(stream, fn, reps):
+    """mean ms of fn() over reps calls, HIP events on `stream` around them"""
+    import torch
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(reps):
+        fn()
+    s1.record(stream)
+    torch.cuda.synchronize()
+    return s0.elapsed_time(s1) / reps
 
 
 def main():
@@ -114,10 +145,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-count", action="store_true", help="skip the instrumented unit-count run")
-    ap.add_argument("--batched", action="store_true", help="also time the batched multi-view path")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-view timing")
     ap.add_argument("--batched-tune", default=None,
                     help="tile_w,tile_h,blocks_per_cu for the batched path instead of autotuning it")
-    ap.add_argument("--no-backward", action="store_true", help="skip the forward+backward timing")
+    ap.add_argument("--no-backward", action="store_true", help="skip the forward+backward timings")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 1024^2 forward+backward timing")
     ap.add_argument("--scene-cache", default=None, help="npz file to load the 4K scene from / save it to")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (HBM byte-counter calibration for profiles)")
@@ -159,10 +191,12 @@ def main():
     torch.cuda.synchronize()
 
     units = None
+    dbg_np = None
     if not args.no_count:
         _, dbg = glint.glint_shade(dgb, mats, lights, debug=True)
         torch.cuda.synchronize()
-        units = costmodel.units_from_debug({k: v.cpu().numpy() for k, v in dbg.items()})
+        dbg_np = {k: v.cpu().numpy() for k, v in dbg.items()}
+        units = costmodel.units_from_debug(dbg_np)
         del dbg
         log("units per launch:", units)
 
@@ -185,6 +219,11 @@ def main():
     log(f"forward 4K: {ms_per_step:.3f} ms/step (kernel {kernel_ms:.3f} ms, wall {wall / args.steps * 1e3:.3f} ms)"
         f" -> {value:.1f} Mpixel/s")
 
+    extra = {}
+    n_shaded = int((gb["material_id"] >= 0).sum())
+    extra["shaded_pixels"] = n_shaded
+    extra["shaded_mpix_s"] = round(n_shaded / 1e6 / (ms_per_step / 1e3), 2)
+
     roof = None
     if units is not None:
         slots = costmodel.slots(units)
@@ -195,51 +234,77 @@ def main():
                 "kernel": "glint_fwd_kernel<false> + tile-order pre-pass", "kernel_ms": round(kernel_ms, 4),
                 "slots_per_launch": int(slots), "units_per_launch": units}
 
-    extra = {}
-    # forward + backward on the same frame (relaxed counts): one material set, same lights
-    try:
-        if args.no_backward:
-            raise glint.GlintError(glint.GLINT_EUNSUPPORTED, "skipped (--no-backward)")
+    # forward + backward on the same frame (relaxed counts): the forward records
+    # which lights and probes opened a gate, the adjoint skips the rest
+    roof_bwd = None
+    if not args.no_backward:
         go = torch.randn((3, H, W), device="cuda", dtype=torch.float32)
         wsb = torch.empty(max(1, glint.glint_backward_workspace_bytes(W, H, len(mats), len(lights))),
                           dtype=torch.uint8, device="cuda")
         gbn = {k: v for k, v in dgb.items() if k not in ("alpha_px", "log10_density_px")}
         lit = torch.empty((H, W), dtype=torch.int16, device="cuda")
         probes = torch.empty((H, W), dtype=torch.int32, device="cuda")
-        glint.glint_shade_lit(gbn, mats, lights, out=out, lit=lit, probes=probes, rounding=1, workspace=ws)
-        glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb, lit=lit, probes=probes)
-        glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb)
-        torch.cuda.synchronize()
+
+        def fwd_lit():
+            glint.glint_shade_lit(gbn, mats, lights, out=out, lit=lit, probes=probes, rounding=1, workspace=ws)
+
+        def bwd():
+            glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb, lit=lit, probes=probes)
+
+        fwd_lit(); bwd(); torch.cuda.synchronize()
         n_fb = max(3, args.steps // 2)
-
-        def pairs(use_lit):
-            s0 = torch.cuda.Event(enable_timing=True); s1 = torch.cuda.Event(enable_timing=True)
-            s0.record(stream)
-            for _ in range(n_fb):
-                if use_lit:     # the forward records which lights and probes opened a gate; the adjoint skips the rest
-                    glint.glint_shade_lit(gbn, mats, lights, out=out, lit=lit, probes=probes, rounding=1, workspace=ws)
-                    glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb, lit=lit, probes=probes)
-                else:           # the adjoint re-evaluates every gate
-                    glint.glint_shade(gbn, mats, lights, out=out, rounding=1, workspace=ws)
-                    glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb)
-            s1.record(stream)
-            torch.cuda.synchronize()
-            return s0.elapsed_time(s1) / n_fb
-
-        fb_ms = pairs(True)
-        full_ms = pairs(False)
+        fb_ms = timed(stream, lambda: (fwd_lit(), bwd()), n_fb)
+        fwd_lit(); torch.cuda.synchronize()
+        bwd_ms = timed(stream, bwd, n_fb)
+        full_ms = timed(stream, lambda: (glint.glint_shade(gbn, mats, lights, out=out, rounding=1, workspace=ws),
+                                         glint.glint_shade_backward(gbn, mats, lights, go, workspace=wsb)), 3)
         extra["fwd_bwd_mpix_s"] = round(mpx / (fb_ms / 1e3), 2)
         extra["fwd_bwd_ms"] = round(fb_ms, 3)
+        extra["bwd_ms"] = round(bwd_ms, 3)
         extra["fwd_bwd_all_gates_ms"] = round(full_ms, 3)
-        log(f"forward+backward 4K: {fb_ms:.3f} ms -> {extra['fwd_bwd_mpix_s']} Mpixel/s "
-            f"(adjoint re-evaluating every gate: {full_ms:.3f} ms)")
-    except glint.GlintError as e:
-        log("backward not available:", e)
-        extra["fwd_bwd_mpix_s"] = None
+        log(f"forward+backward 4K: {fb_ms:.3f} ms -> {extra['fwd_bwd_mpix_s']} Mpixel/s (adjoint call {bwd_ms:.3f} ms; "
+            f"re-evaluating every gate: {full_ms:.3f} ms)")
+        if dbg_np is not None:
+            bu = costmodel.bwd_units(dbg_np, lit.cpu().numpy(), probes.cpu().numpy())
+            bslots = costmodel.slots(bu, costmodel.BWD_COST)
+            bach = bslots / (bwd_ms / 1e3)
+            roof_bwd = {"bound": "alu", "achieved": round(bach / 1e12, 3),
+                        "peak": round(costmodel.VALU_PEAK_SLOTS / 1e12, 3), "unit": "Tslot/s",
+                        "frac": round(bach / costmodel.VALU_PEAK_SLOTS, 4), "traffic": None,
+                        "kernel": "glint_shade_backward with lit masks (lit-pixel list, glint_bwd_unit_kernel, "
+                                  "reductions)", "kernel_ms": round(bwd_ms, 4),
+                        "slots_per_launch": int(bslots), "units_per_launch": bu}
+            log("adjoint units:", bu)
+        del go, wsb, lit, probes
 
-    if args.batched:
+    # the adjoint's own configuration: 1024^2, one material, one light
+    if not args.no_c5:
+        g5, m5, l5, _, _ = scenes.backward_scene(1024, 1024, seed=5)
+        d5 = glint.to_device(g5)
+        o5 = torch.empty((3, 1024, 1024), device="cuda")
+        lit5 = torch.empty((1024, 1024), dtype=torch.int16, device="cuda")
+        pr5 = torch.empty((1024, 1024), dtype=torch.int32, device="cuda")
+        go5 = torch.randn((3, 1024, 1024), device="cuda")
+        ws5 = torch.empty(max(1, glint.glint_backward_workspace_bytes(1024, 1024, 1, 1)), dtype=torch.uint8,
+                          device="cuda")
+
+        def fb5():
+            glint.glint_shade_lit(d5, m5, l5, out=o5, lit=lit5, probes=pr5, rounding=1)
+            glint.glint_shade_backward(d5, m5, l5, go5, workspace=ws5, lit=lit5, probes=pr5)
+
+        fb5(); torch.cuda.synchronize()
+        ms5 = timed(stream, fb5, 10)
+        extra["c5_fwd_bwd_ms"] = round(ms5, 4)
+        extra["c5_fwd_bwd_mpix_s"] = round(1.048576 / (ms5 / 1e3), 2)
+        log(f"forward+backward 1024^2: {ms5:.3f} ms -> {extra['c5_fwd_bwd_mpix_s']} Mpixel/s")
+        del d5, o5, lit5, pr5, go5, ws5
+
+    # many views of uneven size in one launch against one glint_shade per view
+    if not args.no_batched:
+        del out, ws
         views, bm, bl = scenes.batched_views(n_views=64, seed=4)
         dviews = [glint.to_device(v) for v in views]
+        del views
         outs = [torch.empty((3,) + v["u"].shape, device="cuda") for v in dviews]
         if args.batched_tune:
             best = tuple(int(x) for x in args.batched_tune.split(","))
@@ -252,24 +317,24 @@ def main():
         plan.run(use_graph=True)
         torch.cuda.synchronize()
         npx = sum(v["u"].numel() for v in dviews)
-        s0 = torch.cuda.Event(enable_timing=True); s1 = torch.cuda.Event(enable_timing=True)
-        s0.record(stream)
-        for _ in range(3):
-            plan.run(use_graph=True)
-        s1.record(stream)
-        torch.cuda.synchronize()
-        bt = s0.elapsed_time(s1) / 3
-        s0.record(stream)
-        for _ in range(3):
-            for v, o in zip(dviews, outs):
-                glint.glint_shade(v, bm, bl, out=o)
-        s1.record(stream)
-        torch.cuda.synchronize()
-        st = s0.elapsed_time(s1) / 3
+        bt = timed(stream, lambda: plan.run(use_graph=True), 5)
+        wss = [torch.empty(max(1, glint.glint_shade_workspace_bytes(v["u"].shape[1], v["u"].shape[0])),
+                           dtype=torch.uint8, device="cuda") for v in dviews]
+
+        def per_view():
+            for v, o, w in zip(dviews, outs, wss):
+                glint.glint_shade(v, bm, bl, out=o, workspace=w)
+
+        per_view(); torch.cuda.synchronize()
+        st = timed(stream, per_view, 5)
         extra["batched_mpix_s"] = round(npx / 1e6 / (bt / 1e3), 2)
+        extra["batched_ms"] = round(bt, 4)
         extra["per_view_mpix_s"] = round(npx / 1e6 / (st / 1e3), 2)
+        extra["per_view_ms"] = round(st, 4)
         extra["batched_pixels"] = int(npx)
         extra["batched_tune"] = list(best)
+        log(f"batched 64 views ({npx} px): {bt:.3f} ms -> {extra['batched_mpix_s']} Mpixel/s; "
+            f"64 glint_shade calls {st:.3f} ms -> {extra['per_view_mpix_s']} Mpixel/s")
         plan.close()
 
     cpu = None
@@ -294,6 +359,7 @@ def main():
                    "width": W, "height": H, "lights": len(lights), "materials": len(mats),
                    "k_max": 4, "n_probe_max": 21},
         "roofline": roof,
+        "roofline_bwd": roof_bwd,
         "cpu_baseline": cpu,
     }
     rec.update(extra)

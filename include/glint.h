@@ -150,13 +150,15 @@ typedef struct {
  *  n_lit      (probe, light) pairs with at least one open gate: only these
  *             need the light's Fresnel, shadowing and radiance terms (work
  *             counter, no parity field)
+ *  n_live_lit live gated binomials of those (probe, light) pairs: the gates
+ *             the adjoint re-evaluates (work counter, no parity field)
  * Asking for debug planes runs an instrumented kernel (slower, same image). */
 typedef struct {
     uint32_t *flags;
     int32_t *n_probe, *level;
     uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
-    uint32_t *n_live_small, *n_lit;
+    uint32_t *n_live_small, *n_lit, *n_live_lit;
 } glint_debug;
 
 /* Launch configuration of the batched path (autotuner output).

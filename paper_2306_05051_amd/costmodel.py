@@ -66,6 +66,23 @@ keys and gates):
       implicit form (sign s, a = -1/(s + n_z), s n_x) 17, <n,wi> and <wi,t>,
       <wi,b> from it 14, the 4 nodes' base hashes H(material, node) 36 = 660
 
+Adjoint (glint_shade_backward with the forward's lit masks): the minimal
+work to differentiate the relaxed forward is, per lit pixel (a light opened a
+gate in it) its set-up (pixel, above); per lit probe its texel keys (item);
+per lit (pixel, light) the light's set-up (pixel-light) and the gradient
+algebra below; per (probe, light) pair with an open gate its live gates
+again (to find the open ones); per open gate the forward's count and the
+derivative terms below.
+  lit pixel-light gradient algebra: Fresnel and Lambda(wo) 33, cos^2/sin^2
+      6, dp/dalpha and dp/d<n,h>^2 12, dLambda(wo)/d(c, alpha) 14, G 7,
+      dG/dalpha 10, the alpha and ln N sums 13, the unit half vector (FP64)
+      6, 1 - <wi,h> 6, the Fresnel, normal and frame terms 17, the frame
+      axes (FP64) 24, gradient w.r.t. h 21, the Lambda(wo) term 6, the chain
+      through h = (wi + wo)/|wi + wo| and wo = d/|d| 31 = 206
+  open gate derivative terms (extra): 1/(2 sigma) 6, dsigma/dp and
+      dsigma/dm 7, dm/d ln N 2, the five accumulations with their weights
+      15 = 30
+
 Units are counted exactly by the library's instrumented kernel (debug
 planes): pixel-lights from the gated binomials each light evaluates per
 probe, lit pixel-lights from the per-light count sums.  Loop control,
@@ -94,6 +111,15 @@ COST = {
     "pixel": (5 + 2 * (12 + FP64_RSQ + 6) + 24 + 6 + (12 + FP64_SQRT + 2 + FP64_DIV + 2) + 80
               + (26 + 2 * FP64_RSQ) + (8 + 2 * FP64_DIV + 2) + 6 + 180 + 56
               + (5 + FP64_RCP) + 6 + 8 + 4 * HASH),
+}
+
+
+BWD_COST = {
+    "pixel": COST["pixel"],
+    "item": COST["item"],
+    "pixel_light": COST["pixel_light"] + 206,
+    "live_gate": COST["live_gate"],
+    "open_gate": COST["open_gate"] + 30,
 }
 
 
@@ -131,5 +157,27 @@ def units_from_debug(dbg):
     }
 
 
-def slots(units):
-    return sum(COST[k] * units[k] for k in COST)
+def bwd_units(dbg, lit, probes):
+    """Units of the adjoint from the instrumented forward's planes and the
+    lit masks of glint_shade_lit (numpy arrays): lit pixels, lit probes
+    (set bits of the probe mask; bit 31 stands for probes 31 on, so it is
+    expanded from the pixel's probe count), lit (pixel, light) pairs, the live
+    gates of the (probe, light) pairs with an open gate, open gates."""
+    import numpy as np
+    lit = lit.astype(np.int64) & 0xFFFF
+    pm = probes.astype(np.int64) & 0xFFFFFFFF
+    npr = dbg["n_probe"].astype(np.int64)
+    low = np.unpackbits((pm & 0x7FFFFFFF).astype("<u4").view(np.uint8)).reshape(pm.shape + (32,)).sum(-1)
+    hi = np.where((pm >> 31) & 1, np.maximum(npr - 31, 1), 0)
+    return {
+        "pixel": int((lit != 0).sum()),
+        "item": int((low + hi).sum()),
+        "pixel_light": int(np.unpackbits(lit.astype("<u2").view(np.uint8)).sum()),
+        "live_gate": int((dbg["n_live_lit"].astype(np.int64) & 0xFFFFFFFF).sum()),
+        "open_gate": int((dbg["n_open"].astype(np.int64) & 0xFFFFFFFF).sum()),
+    }
+
+
+def slots(units, cost=None):
+    cost = COST if cost is None else cost
+    return sum(cost[k] * units[k] for k in cost)

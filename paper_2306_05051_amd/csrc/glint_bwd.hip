@@ -630,6 +630,18 @@ __device__ __forceinline__ void column_sums(const T *__restrict__ flat, int64_t 
 
 // list_len (nullable): with the lit-pixel list, only the rows of the
 // ceil(list_len / 64) chunks hold partial sums.
+// the gradients of an empty image: all zero
+__global__ __launch_bounds__(kReduceThreads) void glint_bwd_zero_grads(float *ga, float *gn, float *gd, int n_mat,
+                                                                       int n_light)
+{
+    const int i = threadIdx.x;
+    if (i < n_mat) {
+        ga[i] = 0.0f;
+        gn[i] = 0.0f;
+    }
+    if (i < 3 * n_light) gd[i] = 0.0f;
+}
+
 __global__ __launch_bounds__(kReduceThreads) void glint_bwd_reduce1(const float *partials, int64_t n_rows,
                                                                     const uint32_t *list_len, int stride,
                                                                     int64_t rpb, double *stage1)
@@ -879,10 +891,11 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
     const int64_t tiles = (int64_t)vw.width * vw.height > 0 ? bwd_tiles(vw.width, vw.height) : 0;
     hipStream_t st = (hipStream_t)stream;
     if (tiles == 0) {
-        // empty image: gradients are zero
-        hipError_t e = hipMemsetAsync(grad_alpha, 0, sizeof(float) * n_mat, st);
-        if (e == hipSuccess) e = hipMemsetAsync(grad_ln_density, 0, sizeof(float) * n_mat, st);
-        if (e == hipSuccess && n_light > 0) e = hipMemsetAsync(grad_light_dir, 0, sizeof(float) * 3 * n_light, st);
+        // empty image: gradients are zero (a kernel, not a memset node, so
+        // that the call stays safe to capture into a graph)
+        hipLaunchKernelGGL(glint_bwd_zero_grads, dim3(1), dim3(kReduceThreads), 0, st, grad_alpha, grad_ln_density,
+                           grad_light_dir, n_mat, n_light);
+        hipError_t e = hipGetLastError();
         return e == hipSuccess ? GLINT_OK : set_hip_error(e);
     }
     if (tiles > 0x7fffffffLL) return GLINT_ESHAPE;

@@ -82,7 +82,7 @@ struct DebugPlanes {
     int32_t *n_probe, *level;
     uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
-    uint32_t *n_live_small, *n_lit;
+    uint32_t *n_live_small, *n_lit, *n_live_lit;
 };
 
 enum : uint32_t {

@@ -41,7 +41,7 @@ int set_hip_error(hipError_t e)
 struct ItemOut {
     float rgb[3];
     uint32_t lit;              // bit l: a gate of light l opened (recorded by glint_shade_lit)
-    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate, n_live, n_live_small, n_lit;
+    uint32_t key_sum, theta_sum, count_sum, n_open, n_gate, n_live, n_live_small, n_lit, n_live_lit;
     float b[kMaxLight];
 };
 
@@ -217,6 +217,7 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
     if (LIT) o.lit = 0u;
     if (DEBUG) {
         o.key_sum = o.theta_sum = o.count_sum = o.n_open = o.n_gate = o.n_live = o.n_live_small = o.n_lit = 0;
+        o.n_live_lit = 0;
         for (int l = 0; l < kMaxLight; ++l) o.b[l] = 0.0f;
     }
     const uint32_t pk = sm.pk[ip];
@@ -370,7 +371,10 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
             }
             // a light without an open gate adds exactly +0 to the (non-negative) sums
             if ((mlo | mhi) == 0u) break;
-            if (DEBUG) o.n_lit += 1;
+            if (DEBUG) {
+                o.n_lit += 1;
+                for (int g = 0; g < nn; ++g) o.n_live_lit += K[g] ? 12u : 0u;
+            }
             if (LIT) o.lit |= 1u << li;
             const float p = __uint_as_float(lw[4 * kWave]);
             float fx, gx, fy, gy;
@@ -503,7 +507,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     __syncthreads();
     float acc[3] = {0.0f, 0.0f, 0.0f};
     uint32_t litacc = 0u, probeacc = 0u;
-    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0, dns = 0, dlt = 0;
+    uint32_t dks = 0, dts = 0, dcs = 0, dno = 0, dng = 0, dnl = 0, dns = 0, dlt = 0, dll = 0;
     float db[kMaxLight];
     if (DEBUG)
         for (int l = 0; l < kMaxLight; ++l) db[l] = 0.0f;
@@ -549,6 +553,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                 dnl += s.n_live;
                 dns += s.n_live_small;
                 dlt += s.n_lit;
+                dll += s.n_live_lit;
                 for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
             }
             __syncthreads();
@@ -595,6 +600,7 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             if (dp.n_live) dp.n_live[idx] = dnl;
             if (dp.n_live_small) dp.n_live_small[idx] = dns;
             if (dp.n_lit) dp.n_lit[idx] = dlt;
+            if (dp.n_live_lit) dp.n_live_lit[idx] = dll;
             if (dp.b_light)
                 for (int l = 0; l < sh.n_light; ++l) dp.b_light[l * npx + idx] = db[l];
         }
@@ -1081,7 +1087,7 @@ static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb,
         // the instrumented kernel reads a table through the caches: same words as from LDS
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light,
-                          dbg->n_live_small, dbg->n_lit};
+                          dbg->n_live_small, dbg->n_lit, dbg->n_live_lit};
         if (law == kLawZk)
             hipLaunchKernelGGL((glint_fwd_kernel<true, kRngHash, false, kLawZk>), grid, block, zk_b, st, vw, sh, dp,
                                kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);

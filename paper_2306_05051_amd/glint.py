@@ -70,7 +70,7 @@ DEBUG_FIELDS = (("flags", torch.int32), ("n_probe", torch.int32), ("level", torc
                 ("cell", torch.int32), ("key_sum", torch.int32), ("akey_sum", torch.int32),
                 ("theta_sum", torch.int32), ("count_sum", torch.int32), ("n_open", torch.int32),
                 ("n_gate", torch.int32), ("n_live", torch.int32))
-WORK_FIELDS = ("n_live_small", "n_lit")      # work counters of the instrumented kernel (after b_light)
+WORK_FIELDS = ("n_live_small", "n_lit", "n_live_lit")   # work counters of the instrumented kernel (after b_light)
 
 
 class _Debug(C.Structure):

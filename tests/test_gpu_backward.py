@@ -216,3 +216,24 @@ def test_backward_with_empty_lit_mask_is_zero(glint):
     for a, b in zip(full, fast):
         a, b = a.double(), b.double()
         assert float((a - b).abs().max()) <= 1e-5 * float(a.abs().max()) + 1e-30
+
+
+def test_backward_empty_image_overwrites_gradients(glint):
+    """An empty image has zero gradients, written over whatever the outputs
+    held (a zeroing kernel, so the call stays capturable)."""
+    import ctypes as C
+    gb, mats, lights = scenes.four_k(32, 8, seed=2, n_light=3, n_mat=2)
+    dgb = glint.to_device(gb)
+    g = glint.make_gbuffer(dgb)
+    g.width = 0
+    ga = torch.full((2,), float("nan"), device="cuda")
+    gn = torch.full((2,), float("nan"), device="cuda")
+    gd = torch.full((3, 3), float("nan"), device="cuda")
+    go = torch.zeros((3, 8, 32), device="cuda")
+    st = glint.lib().glint_shade_backward(C.byref(g), glint.make_materials(mats), 2, glint.make_lights(lights), 3,
+                                          C.byref(glint.make_params(rounding=1)), go.data_ptr(), None, None,
+                                          ga.data_ptr(), gn.data_ptr(), gd.data_ptr(), None, 0, None)
+    torch.cuda.synchronize()
+    assert st == glint.GLINT_OK
+    for t in (ga, gn, gd):
+        assert torch.equal(t, torch.zeros_like(t))
