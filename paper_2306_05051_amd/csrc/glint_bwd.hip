@@ -628,8 +628,6 @@ __device__ __forceinline__ void column_sums(const T *__restrict__ flat, int64_t 
     }
 }
 
-// list_len (nullable): with the lit-pixel list, only the rows of the
-// ceil(list_len / 64) chunks hold partial sums.
 // the gradients of an empty image: all zero
 __global__ __launch_bounds__(kReduceThreads) void glint_bwd_zero_grads(float *ga, float *gn, float *gd, int n_mat,
                                                                        int n_light)
@@ -642,6 +640,8 @@ __global__ __launch_bounds__(kReduceThreads) void glint_bwd_zero_grads(float *ga
     if (i < 3 * n_light) gd[i] = 0.0f;
 }
 
+// list_len (nullable): with the lit-pixel list, only the rows of the
+// ceil(list_len / 64) chunks hold partial sums.
 __global__ __launch_bounds__(kReduceThreads) void glint_bwd_reduce1(const float *partials, int64_t n_rows,
                                                                     const uint32_t *list_len, int stride,
                                                                     int64_t rpb, double *stage1)

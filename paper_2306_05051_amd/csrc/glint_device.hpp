@@ -345,6 +345,33 @@ __device__ __forceinline__ bool tangent_rotation(const double n[3], float tx, fl
     return true;
 }
 
+// atan2(y, x) in FP64 within about 1e-15 rad (the footprint orientation's
+// decisions have margins of 1e-5 cells): the ratio of the smaller to the
+// larger of |y|, |x| (t <= 1), reduced to |t'| <= tan(pi/8) by
+// atan t = pi/4 + atan((t - 1)/(t + 1)) above tan(pi/8), then the odd Taylor
+// series of atan through t'^37 (truncation below 1e-16), and the octant
+// restored.  Zero y gives exactly 0 or pi (x >= +0 or not), zero x exactly
+// +-pi/2, as the C library does; the series' coefficients are uniform
+// constants (scalar registers), unlike the library's table.
+__device__ __forceinline__ double atan2_d(double y, double x)
+{
+    const double ax = fabs(x), ay = fabs(y);
+    const bool swap = ay > ax;
+    const double num = swap ? ax : ay, den = swap ? ay : ax;
+    double t = den > 0.0 ? num * rcp_d(den) : 0.0;
+    const bool big = t > 0.41421356237309503;
+    if (big) t = (t - 1.0) * rcp_d(t + 1.0);
+    const double t2 = t * t;
+    double q = 1.0 / 37.0;
+#pragma unroll
+    for (int k = 17; k >= 0; --k) q = fma(q, -t2, 1.0 / (double)(2 * k + 1));
+    double a = fma(t, q, big ? 0.78539816339744831 : 0.0);
+    if (swap) a = 1.5707963267948966 - a;
+    if (x < 0.0 || (x == 0.0 && signbit(x))) a = 3.1415926535897932 - a;
+    if (ay == 0.0) a = (x < 0.0 || (x == 0.0 && signbit(x))) ? 3.1415926535897932 : 0.0;
+    return signbit(y) ? -a : a;
+}
+
 template <bool DEBUG>
 __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, const Shared &sh, Pixel &px)
 {
@@ -398,7 +425,7 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
     const double s0sq = 0.5 * (a + c) + R;
     double r = s0sq / P;
     if (r < 1.0) r = 1.0;
-    double phi = 0.5 * atan2(2.0 * b, a - c);
+    double phi = 0.5 * atan2_d(2.0 * b, a - c);
     if (phi < 0.0) phi += kPi;
     // sigma0 (cos phi, sin phi): the eigenvector of J J^T for sigma0^2 in its
     // well-conditioned form, (hd + R, b) or (b, R - hd), turned so that
