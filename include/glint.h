@@ -152,13 +152,41 @@ typedef struct {
  *             counter, no parity field)
  *  n_live_lit live gated binomials of those (probe, light) pairs: the gates
  *             the adjoint re-evaluates (work counter, no parity field)
- * Asking for debug planes runs an instrumented kernel (slower, same image). */
+ *
+ * Sampled per-texel dump (dump_slot NULL: none).  dump_slot [height*stride]
+ * names, per pixel, the slot s in [0, dump_capacity) that receives every
+ * texel-level decision of the pixel, or -1 (any value outside that range is
+ * ignored; two pixels naming one slot race).  A slot holds the pixel's probes
+ * k < dump_probes (1 <= dump_probes <= GLINT_MAX_PROBES), and for each its
+ * grid nodes g < 4 (Sec. 4.3), the three vertices e of the node's lattice
+ * triangle (Sec. 6.2) and, per light l, the four angular texels a of Eq. 14
+ * (a & 1 steps the angular x index, a >> 1 the y index):
+ *  dump_key   [cap][dump_probes][4][3]        texel key: the hash chain of
+ *             the material seed, the node's level, ratio and orientation
+ *             words and the vertex's lattice indices (Sec. 5.1 seeds)
+ *  dump_beta  [cap][dump_probes][4][3]        barycentric weight of the vertex
+ *  dump_theta [cap][dump_probes][n_light][4][3][4]  slot-0 word h whose
+ *             uniform (2 (h >> 9) + 1) 2^-24 decides the gate (Eq. 18); with
+ *             GLINT_FLAG_ZK_COUNT the word behind the texel's count
+ *  dump_count [cap][dump_probes][n_light][4][3][4]  count c of the texel
+ *             (Eq. 17; 0 when the gate stays closed; the baseline's count
+ *             with GLINT_FLAG_ZK_COUNT)
+ * Entries of probes k >= n_probe, nodes beyond the pixel's node count, lights
+ * below the pixel's horizon and pixels that are not shaded are written as 0
+ * (every entry of a named slot is written).  All four arrays are required
+ * with dump_slot; device memory, 4-byte aligned, owned by the caller. */
 typedef struct {
     uint32_t *flags;
     int32_t *n_probe, *level;
     uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
     uint32_t *n_live_small, *n_lit, *n_live_lit;
+    const int32_t *dump_slot;
+    int32_t dump_capacity, dump_probes;
+    uint32_t *dump_key;
+    float *dump_beta;
+    uint32_t *dump_theta;
+    float *dump_count;
 } glint_debug;
 
 /* Launch configuration of the batched path (autotuner output).
@@ -192,9 +220,12 @@ size_t glint_shade_workspace_bytes(int32_t width, int32_t height);
  * int32 tile indices, row-major tile numbering); with workspace == NULL they
  * are shaded in row-major order.
  * The image is bit-identical either way.
- * Errors: ENULL (gbuf, planes, mats, out_rgb, lights when n_light > 0),
+ * Errors: ENULL (gbuf, planes, mats, out_rgb, lights when n_light > 0, a
+ * dump array when dbg->dump_slot is set),
  * ESHAPE (width/height < 0, stride < width, workspace_bytes too small),
- * EINVAL (params or material values out of range, misaligned workspace),
+ * EINVAL (params or material values out of range, misaligned workspace,
+ * dump_capacity < 1, dump_probes outside [1, GLINT_MAX_PROBES], misaligned
+ * dump arrays),
  * EHIP (launch failure). */
 int glint_shade(const glint_gbuffer *gbuf, const glint_material *mats, int32_t n_mat,
                 const glint_light *lights, int32_t n_light, const glint_params *params,

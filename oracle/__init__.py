@@ -74,7 +74,10 @@ _DBG_FIELDS = [("flags", np.uint32), ("n_probe", np.int32), ("level", np.int32),
 
 
 class _Dbg(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n, _ in _DBG_FIELDS] + [("b_light", C.c_void_p), ("lit", C.c_void_p)]
+    _fields_ = ([(n, C.c_void_p) for n, _ in _DBG_FIELDS] + [("b_light", C.c_void_p), ("lit", C.c_void_p)]
+                + [("dump_slot", C.c_void_p), ("dump_capacity", C.c_int32), ("dump_probes", C.c_int32),
+                   ("dump_key", C.c_void_p), ("dump_beta", C.c_void_p), ("dump_theta", C.c_void_p),
+                   ("dump_count", C.c_void_p)])
 
 
 class _Nodes(C.Structure):
@@ -170,7 +173,7 @@ def _lights(lights):
 
 
 def shade(gb, materials, lights, k_max=4, n_probe_max=21, rounding=0, debug=False,
-          rows=None, n_threads=0, rng_table=None, count_law=0):
+          rows=None, n_threads=0, rng_table=None, count_law=0, dump_pixels=None, dump_probes=4):
     """FP64 radiance [3, H, W]; with debug=True also a dict of per-pixel planes.
 
     rng_table=None hashes every gate uniform from its keys; rng_table=(log2,
@@ -181,7 +184,14 @@ def shade(gb, materials, lights, k_max=4, n_probe_max=21, rounding=0, debug=Fals
     count_law=1 counts with the Zirr-Kaplanyan baseline (zk_count per texel,
     outputs mixed with the node weights); its debug planes then hold: n_open
     the counts on the Gaussian branch, n_live the Bernoulli trials drawn,
-    count_sum the sum of the integer counts, lit the lights with a count > 0."""
+    count_sum the sum of the integer counts, lit the lights with a count > 0.
+
+    dump_pixels: (y, x) pixels whose texel-level decisions are dumped (with
+    debug=True): planes["dump"] then holds, per listed pixel and probe
+    k < dump_probes, "key" and "beta" [n, dump_probes, 4, 3] (texel key and
+    barycentric weight of node g, vertex e) and "theta" and "count"
+    [n, dump_probes, n_light, 4, 3, 4] (slot-0 word and count of angular
+    texel a), zero where there is no texel."""
     L = lib()
     s, keep, H, W = _gbuf(gb)
     mats, lts = _mats(materials), _lights(lights)
@@ -201,6 +211,22 @@ def shade(gb, materials, lights, k_max=4, n_probe_max=21, rounding=0, debug=Fals
         dbg.b_light = planes["b_light"].ctypes.data
         planes["lit"] = np.zeros((H, W), np.uint32)
         dbg.lit = planes["lit"].ctypes.data
+        if dump_pixels is not None and len(dump_pixels):
+            yx = np.asarray(dump_pixels, np.int64).reshape(-1, 2)
+            slot = np.full((H, W), -1, np.int32)
+            slot[yx[:, 0], yx[:, 1]] = np.arange(len(yx), dtype=np.int32)
+            n, P, NL = len(yx), int(dump_probes), len(lights)
+            dump = {"slot": slot, "key": np.zeros((n, P, 4, 3), np.uint32),
+                    "beta": np.zeros((n, P, 4, 3), np.float64),
+                    "theta": np.zeros((n, P, NL, 4, 3, 4), np.uint32),
+                    "count": np.zeros((n, P, NL, 4, 3, 4), np.float64)}
+            dbg.dump_slot = slot.ctypes.data
+            dbg.dump_capacity, dbg.dump_probes = n, P
+            for k in ("key", "beta", "theta", "count"):
+                setattr(dbg, "dump_" + k, dump[k].ctypes.data)
+            planes["dump"] = dump
+    elif dump_pixels is not None:
+        raise ValueError("dump_pixels needs debug=True")
     r0, r1 = (0, H) if rows is None else rows
     rc = L.og_shade(C.byref(s), mats, len(materials), lts, len(lights), C.byref(prm),
                     out.ctypes.data, C.byref(dbg) if dbg is not None else None, r0, r1, n_threads)

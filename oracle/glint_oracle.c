@@ -101,6 +101,21 @@ typedef struct {                  /* every plane is [height*stride] or NULL */
     int32_t *margin_pos_kind;
     double *b_light;              /* [n_light][height*stride]: raw distributed counts */
     uint32_t *lit;                /* bit l: some gate of light l opened in some probe (l < 32) */
+    /* sampled per-texel dump (dump_slot NULL: none): dump_slot[height*stride]
+     * is -1 or the slot in [0, dump_capacity) of the pixel; per slot, probe
+     * k < dump_probes, node g < 4, lattice vertex e < 3, light l, angular
+     * texel a < 4 (a & 1: x step, a >> 1: y step):
+     *   dump_key  [cap][probes][4][3]       texel key
+     *   dump_beta [cap][probes][4][3]       barycentric weight
+     *   dump_theta[cap][probes][n_light][4][3][4]  slot-0 word of the texel
+     *   dump_count[cap][probes][n_light][4][3][4]  count (0: gate closed)
+     * every entry of a named slot is written (0 where there is no texel) */
+    const int32_t *dump_slot;
+    int32_t dump_capacity, dump_probes;
+    uint32_t *dump_key;
+    double *dump_beta;
+    uint32_t *dump_theta;
+    double *dump_count;
 } og_debug;
 
 /* flags */
@@ -683,9 +698,18 @@ typedef struct {
     double b[64];                  /* raw distributed count per light (first 64 lights) */
 } og_px_out;
 
+/* one pixel's slot of the per-texel dump (zero-filled by the caller) */
+typedef struct {
+    int probes;
+    uint32_t *key;                /* [probes][4][3] */
+    double *beta;
+    uint32_t *theta;              /* [probes][n_light][4][3][4] */
+    double *count;
+} og_dump;
+
 static void shade_pixel(const og_px_in *in, const og_material *mat, const og_light *lights,
                         int n_light, const og_params *prm, const og_perturb *pt,
-                        og_tape *T, og_px_out *o)
+                        og_tape *T, og_px_out *o, const og_dump *dd)
 {
     memset(o, 0, sizeof(*o));
     o->margin[0] = o->margin[1] = INFINITY;
@@ -791,17 +815,24 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
         int vi[OG_MAX_NODES][3], vj[OG_MAX_NODES][3];
         double beta[OG_MAX_NODES][3];
         uint32_t pre[OG_MAX_NODES][3];
+        /* this probe's part of the per-texel dump, or NULL */
+        const int dump = dd && kp < dd->probes;
+        uint32_t *dk = dump ? dd->key + (size_t)kp * 12 : NULL;
+        double *db = dump ? dd->beta + (size_t)kp * 12 : NULL;
         for (int g = 0; g < nodes.n; ++g) {
             og_simplex(cx, cy, nodes.l[g], nodes.k[g], nodes.m[g], vi[g], vj[g], beta[g], mg, mk);
             uint32_t base = og_hash_step(s0, node_word(nodes.l[g], nodes.k[g], nodes.m[g]));
             for (int e = 0; e < 3; ++e) {
                 pre[g][e] = og_hash_step(og_hash_step(base, (uint32_t)vi[g][e]), (uint32_t)vj[g][e]);
                 o->key_sum += pre[g][e];
+                if (dump) { dk[g * 3 + e] = pre[g][e]; db[g * 3 + e] = beta[g][e]; }
             }
         }
         for (int li = 0; li < NL; ++li) {
             if (!lv[li]) continue;
             double p = pl[li];
+            uint32_t *dt = dump ? dd->theta + ((size_t)kp * n_light + li) * 48 : NULL;
+            double *dc = dump ? dd->count + ((size_t)kp * n_light + li) * 48 : NULL;
             for (int g = 0; g < nodes.n; ++g) {
                 if (prm->count_law == 1) {
                     /* Eq. 7 baseline: node g counts its whole cell (N A_g
@@ -814,6 +845,7 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
                             o->n_gate++;
                             int gauss, trials;
                             double c = zk_count(nz, p, h0, mg, mk, &gauss, &trials);
+                            if (dump) { dt[g * 12 + e * 4 + a] = h0; dc[g * 12 + e * 4 + a] = c; }
                             o->n_open += (uint32_t)gauss;
                             o->n_live += (uint32_t)trials;
                             o->count_sum += (uint32_t)c;
@@ -862,6 +894,7 @@ static void shade_pixel(const og_px_in *in, const og_material *mat, const og_lig
                                 c = br ? x : 1.0;
                             }
                         }
+                        if (dump) { dt[g * 12 + e * 4 + a] = h0; dc[g * 12 + e * 4 + a] = c; }
                         bsum[li] += beta[g][e] * vw[li][a] * c;
                     }
             }
@@ -925,6 +958,10 @@ int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_
     if (prm->rng_log2 < 0 || prm->rng_log2 > 32) return -1;
     if (prm->count_law != 0 && !(prm->count_law == 1 && prm->rounding == 0)) return -1;
     if (gb->tx && (!gb->ty || !gb->tz)) return -1;
+    if (dbg && dbg->dump_slot &&
+        (!dbg->dump_key || !dbg->dump_beta || !dbg->dump_theta || !dbg->dump_count ||
+         dbg->dump_capacity < 1 || dbg->dump_probes < 1))
+        return -1;
     if (row0 < 0) row0 = 0;
     if (row1 > gb->height) row1 = gb->height;
     const int64_t npx = (int64_t)gb->height * gb->stride;
@@ -936,8 +973,23 @@ int og_shade(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_
             og_px_in in;
             og_px_out o;
             uint32_t lflags = 0;
+            og_dump dslot, *dd = NULL;
+            const int32_t slot = (dbg && dbg->dump_slot) ? dbg->dump_slot[idx] : -1;
+            if (slot >= 0 && slot < dbg->dump_capacity) {
+                const size_t P = (size_t)dbg->dump_probes, ks = P * 12, ts = P * (size_t)n_light * 48;
+                dslot.probes = dbg->dump_probes;
+                dslot.key = dbg->dump_key + (size_t)slot * ks;
+                dslot.beta = dbg->dump_beta + (size_t)slot * ks;
+                dslot.theta = dbg->dump_theta + (size_t)slot * ts;
+                dslot.count = dbg->dump_count + (size_t)slot * ts;
+                memset(dslot.key, 0, ks * sizeof(uint32_t));
+                memset(dslot.beta, 0, ks * sizeof(double));
+                memset(dslot.theta, 0, ts * sizeof(uint32_t));
+                memset(dslot.count, 0, ts * sizeof(double));
+                dd = &dslot;
+            }
             if (load_pixel(gb, mats, n_mat, idx, &in, &lflags)) {
-                shade_pixel(&in, &mats[in.mat], lights, n_light, prm, NULL, NULL, &o);
+                shade_pixel(&in, &mats[in.mat], lights, n_light, prm, NULL, NULL, &o, dd);
             } else {
                 memset(&o, 0, sizeof(o));
                 o.flags = lflags;
@@ -1027,7 +1079,7 @@ int og_grad(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_l
                 og_px_out op, om;
                 og_perturb pb = {0.0, 0.0, base_dirs};
                 tb.len = 0; tb.pos = 0; tb.mode = 1;
-                shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pb, &tb, &op);
+                shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pb, &tb, &op, NULL);
                 if (!(op.flags & OGF_SHADED)) continue;
                 int flipped = 0;
                 for (int pi = 0; pi < npp; ++pi) {
@@ -1040,14 +1092,14 @@ int og_grad(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_l
                     else { hs = step; dirs_p[pi - 2] += hs; dirs_m[pi - 2] -= hs; }
                     if (frozen) {
                         tb.mode = 2; tb.pos = 0;
-                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pp, &tb, &op);
+                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pp, &tb, &op, NULL);
                         tb.pos = 0;
-                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pm, &tb, &om);
+                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pm, &tb, &om, NULL);
                     } else {
                         tp.len = 0; tp.pos = 0; tp.mode = 1;
                         tm.len = 0; tm.pos = 0; tm.mode = 1;
-                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pp, &tp, &op);
-                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pm, &tm, &om);
+                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pp, &tp, &op, NULL);
+                        shade_pixel(&in, &mats[in.mat], lights, n_light, &prm, &pm, &tm, &om, NULL);
                         if (!same_tape(&tp, &tb) || !same_tape(&tm, &tb)) flipped = 1;
                     }
                     double d = 0.0;

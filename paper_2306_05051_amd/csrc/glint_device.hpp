@@ -83,6 +83,13 @@ struct DebugPlanes {
     uint32_t *cell, *key_sum, *akey_sum, *theta_sum, *count_sum, *n_open, *n_gate, *n_live;
     float *b_light;
     uint32_t *n_live_small, *n_lit, *n_live_lit;
+    // sampled per-texel dump: slot plane, capacity, probes per slot, arrays
+    const int32_t *dump_slot;
+    int32_t dump_cap, dump_probes;
+    uint32_t *dump_key;
+    float *dump_beta;
+    uint32_t *dump_theta;
+    float *dump_count;
 };
 
 enum : uint32_t {

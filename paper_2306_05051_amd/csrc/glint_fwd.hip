@@ -200,6 +200,35 @@ __device__ __forceinline__ uint32_t angular_key(uint32_t A, uint32_t B, int dx, 
                                    ((uint32_t)s << 30));
 }
 
+// One (pixel, probe) part of the sampled per-texel dump (instrumented kernel
+// only): key and beta [4][3], theta and count [n_light][4][3][4] at the
+// slot's probe; key == nullptr: the item is not dumped.
+struct DumpDst {
+    uint32_t *key;
+    float *beta;
+    uint32_t *theta;
+    float *count;
+};
+
+__device__ __forceinline__ DumpDst dump_dst(const DebugPlanes &dp, int slot, int kp, int n_light)
+{
+    const size_t sk = (size_t)slot * dp.dump_probes + kp;
+    return {dp.dump_key + sk * 12, dp.dump_beta + sk * 12, dp.dump_theta + sk * n_light * 48,
+            dp.dump_count + sk * n_light * 48};
+}
+
+__device__ void dump_zero(const DumpDst &d, int n_light)
+{
+    for (int i = 0; i < 12; ++i) {
+        d.key[i] = 0u;
+        d.beta[i] = 0.0f;
+    }
+    for (int i = 0; i < n_light * 48; ++i) {
+        d.theta[i] = 0u;
+        d.count[i] = 0.0f;
+    }
+}
+
 // LK = 2 shades one item on two lanes: the even lane takes the even lights,
 // the odd lane the odd ones, and after every pair of lights the even lane
 // (the item's owner) receives its partner's factor and extends the radiance
@@ -209,7 +238,8 @@ __device__ __forceinline__ uint32_t angular_key(uint32_t A, uint32_t B, int dx, 
 // bits.  p: the item's pixel in the tile, kp: its probe, (u, v): the pixel's uv.
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LK = 1, int LAW = kLawDistributed>
 __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint32_t *lrec, int ip, double u, double v,
-                                           int kp, const Shared &sh, ItemOut &o, const uint32_t *ltbl, float zN = 0.0f)
+                                           int kp, const Shared &sh, ItemOut &o, const uint32_t *ltbl, float zN = 0.0f,
+                                           const DumpDst dd = DumpDst{})
 {
     static_assert(LK == 1 || (LK == 2 && !DEBUG), "two lanes per item only in the production kernels");
     const int lane = threadIdx.x;
@@ -238,9 +268,18 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
     uint32_t pre[4][3];
     float beta[4][3];
     texel_keys(cx, cy, wd, M.root, sh, pre, beta);
+    const bool dump = DEBUG && dd.key != nullptr;
     if (DEBUG) {
         for (int g = 0; g < nn; ++g)
             for (int e = 0; e < 3; ++e) o.key_sum += pre[g][e];
+        if (dump) {
+            dump_zero(dd, sh.n_light);
+            for (int g = 0; g < nn; ++g)
+                for (int e = 0; e < 3; ++e) {
+                    dd.key[g * 3 + e] = pre[g][e];
+                    dd.beta[g * 3 + e] = beta[g][e];
+                }
+        }
     }
     const int n_light = sh.n_light;
     const int trips = LK == 1 ? n_light : (n_light + 1) >> 1;
@@ -292,6 +331,10 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                                 const float va = ((a & 1) ? fx : gx) * ((a & 2) ? fy : gy);
                                 bsum = fmaf(wb * va, c, bsum);
                                 if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_open += 1; o.count_sum += (uint32_t)c; }
+                                if (dump) {
+                                    dd.theta[li * 48 + g * 12 + e * 4 + a] = h0;
+                                    dd.count[li * 48 + g * 12 + e * 4 + a] = c;
+                                }
                             }
                         }
                     } else {
@@ -308,6 +351,10 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                                 const float va = ((a & 1) ? fx : gx) * ((a & 2) ? fy : gy);
                                 bsum = fmaf(wb * va, (float)c, bsum);
                                 if (DEBUG) { o.theta_sum += h0; o.n_gate += 1; o.n_live += (uint32_t)t; o.count_sum += c; }
+                                if (dump) {
+                                    dd.theta[li * 48 + g * 12 + e * 4 + a] = h0;
+                                    dd.count[li * 48 + g * 12 + e * 4 + a] = (float)c;
+                                }
                             }
                         }
                     }
@@ -341,6 +388,7 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                             const uint32_t h0 = rng_word<RNG>(pre[g][e], ak0[a], sh, ltbl);
                             o.theta_sum += h0; o.n_gate += 1; o.n_live += K[g] ? 1u : 0u;
                             o.n_live_small += (K[g] != 0u && K[g] <= 128u) ? 1u : 0u;
+                            if (dump) dd.theta[li * 48 + g * 12 + e * 4 + a] = h0;
                             const uint32_t bit = ((h0 >> 9) < K[g]) ? 1u : 0u;
                             if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
                             else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
@@ -396,6 +444,7 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                 const float va = ((a & 1) ? fx : gx) * ((a & 2) ? fy : gy);   // bilinear weight (Eq. 14)
                 bsum = fmaf(pick43(beta, g, e) * va, c, bsum);
                 if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
+                if (dump) dd.count[li * 48 + g * 12 + e * 4 + a] = c;
             }
             f = __uint_as_float(lw[7 * kWave]) * bsum;
             if (DEBUG) o.b[li] = bsum;
@@ -494,6 +543,11 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             dcell = npr ? px.cell : 0u;
             dlevel = npr ? px.level : 0;
             dakey = npr ? akey_fingerprint(px, sh) : 0u;
+            // dump slot: this lane zeroes the probes the pixel does not have,
+            // the items write the others
+            const int slot = (dp.dump_slot && inb) ? dp.dump_slot[idx] : -1;
+            if (slot >= 0 && slot < dp.dump_cap)
+                for (int k = npr; k < dp.dump_probes; ++k) dump_zero(dump_dst(dp, slot, k, sh.n_light), sh.n_light);
         }
     }
     int incl = npr;
@@ -528,7 +582,12 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
             ItemOut o;
             const float zN = LAW == kLawZk ? zden[p] : 0.0f;
             const double pu = (double)vw.u[pidx], pv = (double)vw.v[pidx];
-            if (DEBUG || lk == 1)
+            if constexpr (DEBUG) {
+                DumpDst dd = {};
+                const int slot = dp.dump_slot ? dp.dump_slot[pidx] : -1;
+                if (slot >= 0 && slot < dp.dump_cap && kp < dp.dump_probes) dd = dump_dst(dp, slot, kp, sh.n_light);
+                shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN, dd);
+            } else if (lk == 1)
                 shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
             else
                 shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
@@ -1066,6 +1125,15 @@ static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb,
                           uint32_t *lit_probes, void *stream, int law = kLawDistributed)
 {
     if (law == kLawZk && (rng != kRngHash || lit)) return GLINT_EUNSUPPORTED;
+    if (dbg && dbg->dump_slot) {
+        if (!dbg->dump_key || !dbg->dump_beta || !dbg->dump_theta || !dbg->dump_count) return GLINT_ENULL;
+        if (dbg->dump_capacity < 1 || dbg->dump_probes < 1 || dbg->dump_probes > GLINT_MAX_PROBES) return GLINT_EINVAL;
+        const uintptr_t al = reinterpret_cast<uintptr_t>(dbg->dump_slot) | reinterpret_cast<uintptr_t>(dbg->dump_key) |
+                             reinterpret_cast<uintptr_t>(dbg->dump_beta) |
+                             reinterpret_cast<uintptr_t>(dbg->dump_theta) |
+                             reinterpret_cast<uintptr_t>(dbg->dump_count);
+        if (al & 3u) return GLINT_EINVAL;
+    }
     ViewDesc vw;
     int rc = make_view(gbuf, out_rgb, vw);
     if (rc) return rc;
@@ -1087,7 +1155,9 @@ static int launch_forward(const glint_gbuffer *gbuf, Shared &sh, float *out_rgb,
         // the instrumented kernel reads a table through the caches: same words as from LDS
         DebugPlanes dp = {dbg->flags, dbg->n_probe, dbg->level, dbg->cell, dbg->key_sum, dbg->akey_sum,
                           dbg->theta_sum, dbg->count_sum, dbg->n_open, dbg->n_gate, dbg->n_live, dbg->b_light,
-                          dbg->n_live_small, dbg->n_lit, dbg->n_live_lit};
+                          dbg->n_live_small, dbg->n_lit, dbg->n_live_lit,
+                          dbg->dump_slot, dbg->dump_capacity, dbg->dump_probes, dbg->dump_key, dbg->dump_beta,
+                          dbg->dump_theta, dbg->dump_count};
         if (law == kLawZk)
             hipLaunchKernelGGL((glint_fwd_kernel<true, kRngHash, false, kLawZk>), grid, block, zk_b, st, vw, sh, dp,
                                kTileLw, tiles_x, order, (int32_t)nt, nullptr, nullptr);

@@ -75,7 +75,10 @@ WORK_FIELDS = ("n_live_small", "n_lit", "n_live_lit")   # work counters of the i
 
 class _Debug(C.Structure):
     _fields_ = ([(n, C.c_void_p) for n, _ in DEBUG_FIELDS] + [("b_light", C.c_void_p)]
-                + [(n, C.c_void_p) for n in WORK_FIELDS])
+                + [(n, C.c_void_p) for n in WORK_FIELDS]
+                + [("dump_slot", C.c_void_p), ("dump_capacity", C.c_int32), ("dump_probes", C.c_int32),
+                   ("dump_key", C.c_void_p), ("dump_beta", C.c_void_p), ("dump_theta", C.c_void_p),
+                   ("dump_count", C.c_void_p)])
 
 
 class _Tune(C.Structure):
@@ -248,8 +251,15 @@ def glint_shade_workspace_bytes(width, height):
 
 
 def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, out=None, debug=False,
-                workspace=None, stream=None, count_law=LAW_DISTRIBUTED):
+                workspace=None, stream=None, count_law=LAW_DISTRIBUTED, dump_pixels=None, dump_probes=4):
     """Radiance [3, H, W] float32 (and a dict of debug planes when debug=True).
+
+    dump_pixels (with debug=True): (y, x) pixels whose texel-level decisions
+    are dumped: planes["dump"] then holds, per listed pixel and probe
+    k < dump_probes, "key" (int32) and "beta" [n, dump_probes, 4, 3] (texel key
+    and barycentric weight of grid node g, lattice vertex e) and "theta"
+    (int32) and "count" [n, dump_probes, n_light, 4, 3, 4] (slot-0 word and
+    count of angular texel a), zero where there is no texel.
 
     workspace: None allocates the tile-order workspace (heaviest tiles first),
     False shades the tiles in row-major order without one, a uint8 CUDA tensor
@@ -257,7 +267,7 @@ def glint_shade(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, ou
     count_law: LAW_DISTRIBUTED (the method) or LAW_ZK (the Zirr-Kaplanyan
     baseline, GLINT_FLAG_ZK_COUNT; rounding must be 0)."""
     return _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, None,
-                  count_law)
+                  count_law, dump_pixels, dump_probes)
 
 
 def glint_shade_noalloc(gbuf, materials, lights, k_max=4, n_probe_max=21, rounding=0, out=None, stream=None,
@@ -307,7 +317,7 @@ def glint_shade_rng_table(gbuf, materials, lights, table, log2_words, placement=
 
 
 def _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, workspace, stream, rng,
-           count_law=LAW_DISTRIBUTED):
+           count_law=LAW_DISTRIBUTED, dump_pixels=None, dump_probes=4):
     L = lib()
     g = make_gbuffer(gbuf)
     H, W = gbuf["u"].shape
@@ -335,6 +345,23 @@ def _shade(gbuf, materials, lights, k_max, n_probe_max, rounding, out, debug, wo
         for n in WORK_FIELDS:
             planes[n] = _planes(0, H, W, S, torch.int32, dev, fill=0)
             setattr(dbg, n, planes[n].data_ptr())
+        if dump_pixels is not None and len(dump_pixels):
+            yx = torch.as_tensor(dump_pixels, dtype=torch.int64).reshape(-1, 2)
+            n, P, NL = yx.shape[0], int(dump_probes), len(lights)
+            slot = _planes(0, H, W, S, torch.int32, dev, fill=-1)
+            slot[yx[:, 0].to(dev), yx[:, 1].to(dev)] = torch.arange(n, dtype=torch.int32, device=dev)
+            dump = {"slot": slot,
+                    "key": torch.zeros((n, P, 4, 3), dtype=torch.int32, device=dev),
+                    "beta": torch.zeros((n, P, 4, 3), dtype=torch.float32, device=dev),
+                    "theta": torch.zeros((n, P, NL, 4, 3, 4), dtype=torch.int32, device=dev),
+                    "count": torch.zeros((n, P, NL, 4, 3, 4), dtype=torch.float32, device=dev)}
+            dbg.dump_slot = slot.data_ptr()
+            dbg.dump_capacity, dbg.dump_probes = n, P
+            for k in ("key", "beta", "theta", "count"):
+                setattr(dbg, "dump_" + k, dump[k].data_ptr())
+            planes["dump"] = dump
+    elif dump_pixels is not None:
+        raise ValueError("dump_pixels needs debug=True")
     prm = make_params(k_max, n_probe_max, rounding, count_law)
     if rng is None:
         st = glint_shade_raw(g, make_materials(materials), len(materials), make_lights(lights), len(lights),

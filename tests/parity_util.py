@@ -53,4 +53,32 @@ def compare(gpu_rgb, gpu_dbg, ref_rgb, ref_dbg, exact_fields=EXACT, rtol=RTOL, l
 
 
 def dbg_to_numpy(d):
-    return {k: v.cpu().numpy() for k, v in d.items()}
+    return {k: dbg_to_numpy(v) if isinstance(v, dict) else v.cpu().numpy() for k, v in d.items()}
+
+
+def compare_dump(gpu_dump, ref_dump, ref_dbg, yx, relaxed=False, beta_atol=2e-6, count_rtol=RTOL, label=""):
+    """Per-texel dump of sampled pixels: texel keys and gate words bit-exact,
+    integer counts exact (relaxed counts within count_rtol), barycentric
+    weights within beta_atol (FP32 against FP64), on every sampled pixel that
+    is not shaded or none of whose decisions is within MARGIN of its
+    boundary.  Returns the number of pixels compared."""
+    n = 0
+    for s, (y, x) in enumerate(yx):
+        shaded = (ref_dbg["flags"][y, x] & 1) > 0
+        if shaded and not ref_dbg["margin_pos"][y, x] >= MARGIN:
+            continue
+        for k in ("key", "theta"):
+            a = gpu_dump[k][s].astype(np.int64) & 0xFFFFFFFF
+            b = ref_dump[k][s].astype(np.int64) & 0xFFFFFFFF
+            assert np.array_equal(a, b), f"{label}: dump {k} differs at pixel {(y, x)} ({np.sum(a != b)} entries)"
+        gb, rb = gpu_dump["beta"][s].astype(np.float64), ref_dump["beta"][s]
+        assert np.all(np.abs(gb - rb) <= beta_atol), f"{label}: beta off at {(y, x)}"
+        assert np.array_equal(gb == 0, rb == 0), f"{label}: beta support differs at {(y, x)}"
+        gc, rc = gpu_dump["count"][s].astype(np.float64), ref_dump["count"][s]
+        assert np.array_equal(gc != 0, rc != 0), f"{label}: open gates differ at {(y, x)}"
+        if relaxed:
+            assert np.all(np.abs(gc - rc) <= count_rtol * np.abs(rc)), f"{label}: relaxed count off at {(y, x)}"
+        else:
+            assert np.array_equal(gc, rc), f"{label}: count differs at {(y, x)}"
+        n += 1
+    return n

@@ -128,6 +128,22 @@ def test_host_validation_without_device(lib):
                                   fake, fake, fake, 1 << 20, None) == glint.GLINT_EINVAL
     assert L.glint_shade_backward(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake, fake, C.c_void_p(4098), fake,
                                   fake, fake, fake, 1 << 20, None) == glint.GLINT_EINVAL
+    # sampled per-texel dump: every array with the slot plane, capacity and probes in range, alignment
+    def dump_dbg(**kw):
+        d = glint._Debug()
+        d.dump_slot, d.dump_capacity, d.dump_probes = 4096, 4, 2
+        d.dump_key = d.dump_beta = d.dump_theta = d.dump_count = 8192
+        for k, v in kw.items():
+            setattr(d, k, v)
+        return C.byref(d)
+    dshade = lambda d: L.glint_shade(C.byref(g), mats, 1, lts, 1, C.byref(prm), fake_out, d, None, 0, None)
+    assert dshade(dump_dbg(dump_beta=None)) == glint.GLINT_ENULL
+    assert dshade(dump_dbg(dump_count=None)) == glint.GLINT_ENULL
+    assert dshade(dump_dbg(dump_capacity=0)) == glint.GLINT_EINVAL
+    assert dshade(dump_dbg(dump_probes=0)) == glint.GLINT_EINVAL
+    assert dshade(dump_dbg(dump_probes=glint.GLINT_MAX_PROBES + 1)) == glint.GLINT_EINVAL
+    assert dshade(dump_dbg(dump_theta=8194)) == glint.GLINT_EINVAL
+    assert dshade(dump_dbg(dump_slot=4098)) == glint.GLINT_EINVAL
     # allocation-free forward: arguments and its size limit are checked before any device call
     na = L.glint_shade_noalloc
     assert na(None, mats, 1, lts, 1, C.byref(prm), fake_out, None) == glint.GLINT_ENULL
