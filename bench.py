@@ -42,7 +42,8 @@ COUNTERS = os.path.join(ROOT, "profiles", "glint_fwd_4k_counters.txt")
 
 
 def sources_sha256():
-    """SHA-256 over the library's kernel sources and C header."""
+    """SHA-256 over the library's kernel sources, C header and build script
+    (its compiler flags shape the kernels too)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2306_05051_amd", "csrc")
@@ -51,6 +52,7 @@ def sources_sha256():
             h.update(f.encode())
             h.update(open(os.path.join(csrc, f), "rb").read())
     h.update(open(os.path.join(ROOT, "include", "glint.h"), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2306_05051_amd", "build.py"), "rb").read())
     return h.hexdigest()
 
 

@@ -31,11 +31,28 @@
 
 namespace glint {
 
+// v + (v moved across lanes by the DPP control CTRL); lanes that the row
+// mask leaves out, or whose source lane does not exist, add 0
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_add(float v)
+{
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+
+// Sum over the 64 lanes (every lane active), in a fixed order, with data
+// moves between lanes inside the VALU instructions (no LDS round trips):
+// pairs, quads, 8 and 16 lanes of a row, then row 0 into row 1 and row 2
+// into row 3, then rows 0-1 into row 3; lane 63 holds the total, which is
+// returned to every lane.
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v = dpp_add<0xB1>(v);          // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E>(v);          // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141>(v);         // row_half_mirror
+    v = dpp_add<0x140>(v);         // row_mirror
+    v = dpp_add<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Per-wave LDS (10176 bytes: 16 workgroups per CU).  As in the forward,

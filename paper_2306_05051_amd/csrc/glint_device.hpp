@@ -567,14 +567,15 @@ __device__ __forceinline__ void setup_pixel(const ViewDesc &vw, int64_t idx, con
 }
 
 // Per-pixel record staged in LDS for the (pixel, probe) items: everything an
-// item needs that does not depend on the probe (56 bytes).
+// item needs that does not depend on the probe (48 bytes).
 //   pk     n_pr (bits 0-6) | node count (7-9) | material (10-14) | l + 1024 (15-25)
 //   nd[2]  per node 9 bits, two nodes per word at bits 0 and 16:
 //          top level (bit 0: level l + 1) | k << 1 | m << 4
 // The bottom area level l lies in [-300, 256] for FP32 derivatives (|det J|
 // is a product of two FP32 values), so l + 1024 takes 11 bits.
 struct PixelRec {
-    double ex, ey;             // sigma0 * major axis direction
+    float ex, ey;              // sigma0 * major axis direction, rounded to FP32 (every kernel places the
+                               // probes from these same values)
     uint32_t pk;
     float alpha, kpx, lam_i;   // roughness, D(n)/(R N P 4 <wi,n>), Smith Lambda of the view
     uint32_t nd[2];
@@ -779,8 +780,8 @@ __device__ __forceinline__ PixelRec make_rec(const Pixel &px, const Shared &sh)
 {
     PixelRec r;
     const DevMaterial &M = sh.mats[px.mat];
-    r.ex = px.ex;
-    r.ey = px.ey;
+    r.ex = (float)px.ex;
+    r.ey = (float)px.ey;
     r.pk = (uint32_t)px.npr | ((uint32_t)px.n_nodes << 7) | ((uint32_t)px.mat << 10) |
            ((uint32_t)(px.level + 1024) << 15);
     r.alpha = px.alpha;
@@ -844,7 +845,7 @@ __device__ __forceinline__ void probe_texels(const PixelRec &R, double u, double
     const int lane = threadIdx.x;
     const int npr = rec_npr(R), nn = rec_nodes(R);
     double cx, cy;
-    probe_centre(u, v, R.ex, R.ey, kp, npr, cx, cy);
+    probe_centre(u, v, (double)R.ex, (double)R.ey, kp, npr, cx, cy);
     uint32_t w[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) w[g] = rec_node_word(R, g);

@@ -30,7 +30,7 @@ inline int64_t tiles_of(int32_t width, int32_t height)
 // Heaviest-first order of the kTileW x kTileH tiles of a view (row-major tile numbering),
 // built on `st` in `ws` (tile_order_bytes(width, height) bytes, 4-byte
 // aligned).  On success *order points at n_tiles int32 tile indices inside
-// ws.  Defined with the forward kernels.
+// ws.  Defined in glint_order.hip.
 size_t tile_order_bytes(int32_t width, int32_t height);
 int enqueue_tile_order(const ViewDesc &vw, const Shared &sh, void *ws, size_t ws_bytes, const int32_t **order,
                        hipStream_t st);
