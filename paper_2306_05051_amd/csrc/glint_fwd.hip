@@ -12,8 +12,9 @@
 //     for every light 48 gated binomials (4 grids x 3 texels x 4 angular
 //     texels, Sec. 6.2); gates whose probability is below the smallest
 //     uniform 2^-24 cannot open and are skipped without hashing.
-//  4. item contributions go through LDS and each pixel lane sums its own
-//     probes in probe order (deterministic), then writes RGB planes.
+//  4. per batch, a segmented scan across the item lanes sums each pixel's
+//     items in a fixed order (deterministic); the pixel lane adds the batch
+//     sum to its RGB and finally writes the RGB planes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -468,6 +469,52 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
     if (LIT && LK == 2) o.lit |= __shfl_xor(o.lit, 1);
 }
 
+// ---------------------------------------------------------------------------
+// Per-pixel sums of a batch's item results.  Item j of the batch sits on lane
+// j, and the items of one pixel are consecutive lanes seg..last.  A segmented
+// inclusive scan (Hillis-Steele: lane j adds lane j - d when that lane is in
+// its segment, for d = 1, 2, 4, 8 inside each 16-lane row, then the last
+// lane of row 0 into row 1 and of row 2 into row 3, then lane 31 into rows 2
+// and 3) leaves on the segment's last lane the sum of its items, in a fixed
+// tree order.  Lane data moves inside VALU instructions (DPP), so the scan
+// costs about 60 instructions per batch, against a loop of cross-lane reads
+// as long as the longest segment.  All lanes must be active.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS, bool LIT>
+__device__ __forceinline__ void seg_step(float (&v)[3], uint32_t &l, uint32_t &m, bool take)
+{
+    float t[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[c] = __uint_as_float(dpp_mov<CTRL, ROWS>(__float_as_uint(v[c])));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = take ? v[c] + t[c] : v[c];
+    if constexpr (LIT) {
+        const uint32_t tl = dpp_mov<CTRL, ROWS>(l), tm = dpp_mov<CTRL, ROWS>(m);
+        l = take ? (l | tl) : l;
+        m = take ? (m | tm) : m;
+    }
+}
+
+// v: the lane's item RGB (0 past the last item), l, m: its lit-light and
+// probe bits (LIT); seg: the lane of its pixel's first item in the batch
+template <bool LIT>
+__device__ __forceinline__ void segmented_sums(float (&v)[3], uint32_t &l, uint32_t &m, int seg)
+{
+    const int j = threadIdx.x, jr = j & 15, r = j >> 4;
+    seg_step<0x111, 0xf, LIT>(v, l, m, jr >= 1 && j - 1 >= seg);   // row_shr:1
+    seg_step<0x112, 0xf, LIT>(v, l, m, jr >= 2 && j - 2 >= seg);   // row_shr:2
+    seg_step<0x114, 0xf, LIT>(v, l, m, jr >= 4 && j - 4 >= seg);   // row_shr:4
+    seg_step<0x118, 0xf, LIT>(v, l, m, jr >= 8 && j - 8 >= seg);   // row_shr:8
+    seg_step<0x142, 0xa, LIT>(v, l, m, (r & 1) != 0 && 16 * r - 1 >= seg);   // row_bcast:15, rows 1 and 3
+    seg_step<0x143, 0xc, LIT>(v, l, m, r >= 2 && 31 >= seg);                // row_bcast:31, rows 2 and 3
+}
+
 // per-pixel angular fingerprint (debug only): sum of slot-0 angular keys
 __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 {
@@ -489,8 +536,9 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 //     LDS fields, and one record per light (make_light_rec).
 //  2. a wave prefix sum flattens the tile's (pixel, probe) items; lanes take
 //     them 64 at a time (two lanes per item in a last batch of at most 32).
-//  3. each pixel lane sums its own items' RGB in probe order, read from the
-//     item lanes' registers (cross-lane reads in a loop every lane runs).
+//  3. per batch, segmented_sums leaves each pixel's item sum on the lane of
+//     its last item, and the pixel lane adds it to its RGB (one cross-lane
+//     read per channel).
 // lrec: the tile's dynamic LDS, n_light * kLightRecBytes.
 // ---------------------------------------------------------------------------
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LAW = kLawDistributed>
@@ -594,23 +642,52 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                 shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
             else
                 shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
-            if constexpr (DEBUG) {
-                sm.dslot[lane] = o;
-            } else {
-                o0 = o.rgb[0];
-                o1 = o.rgb[1];
-                o2 = o.rgb[2];
-                if (LIT) ol = o.lit;
+            o0 = o.rgb[0];
+            o1 = o.rgb[1];
+            o2 = o.rgb[2];
+            if (LIT) ol = o.lit;
+            if constexpr (DEBUG) sm.dslot[lane] = o;
+        }
+        // item j of the batch onto lane j (two lanes per item: from lane 2j),
+        // then the per-pixel sums of the batch (segmented_sums)
+        float v[3] = {o0, o1, o2};
+        uint32_t vl = ol, vm = (LIT && ol) ? 1u << min(kp, 31) : 0u;   // probe bit 31: probe 31 or a later one
+        int kj = kp;
+        if (lk == 2) {
+            const int src = (2 * lane) & (kWave - 1);
+            const bool in = lane < kWave / 2;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c] = __shfl(v[c], src);
+            kj = __shfl(kj, src);
+            if (LIT) {
+                vl = (uint32_t)__shfl((int)vl, src);
+                vm = (uint32_t)__shfl((int)vm, src);
+            }
+            if (!in) {
+                v[0] = v[1] = v[2] = 0.0f;
+                vl = vm = 0u;
+                kj = 0;
             }
         }
+        segmented_sums<LIT>(v, vl, vm, lane - min(kj, lane));
+        // pixel lane: its items i0..i1-1 of this batch end on lane i1-1-base
         const int i0 = max(off, base), i1 = min(off + npr, base + kWave);
+        const int src = i1 > i0 ? i1 - 1 - base : lane;
+        const float r0 = __shfl(v[0], src), r1 = __shfl(v[1], src), r2 = __shfl(v[2], src);
+        const uint32_t rl = LIT ? (uint32_t)__shfl((int)vl, src) : 0u, rm = LIT ? (uint32_t)__shfl((int)vm, src) : 0u;
+        if (i1 > i0) {
+            acc[0] += r0;
+            acc[1] += r1;
+            acc[2] += r2;
+            if (LIT) {
+                litacc |= rl;
+                probeacc |= rm;
+            }
+        }
         if constexpr (DEBUG) {
             __syncthreads();
             for (int i = i0; i < i1; ++i) {
                 const ItemOut &s = sm.dslot[i - base];
-                acc[0] += s.rgb[0];
-                acc[1] += s.rgb[1];
-                acc[2] += s.rgb[2];
                 dks += s.key_sum; dts += s.theta_sum; dcs += s.count_sum; dno += s.n_open; dng += s.n_gate;
                 dnl += s.n_live;
                 dns += s.n_live_small;
@@ -619,24 +696,6 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                 for (int l = 0; l < kMaxLight; ++l) db[l] += s.b[l];
             }
             __syncthreads();
-        } else {
-            // every lane runs the loop (the reads need all lanes); lane k of a
-            // pixel's range reads the item's owner lane
-            const int cnt = i1 > i0 ? i1 - i0 : 0;
-            for (int k = 0; __ballot(k < cnt) != 0ull; ++k) {
-                const int src = k < cnt ? (i0 + k - base) * lk : lane;
-                const float r0 = __shfl(o0, src), r1 = __shfl(o1, src), r2 = __shfl(o2, src);
-                const uint32_t rl = LIT ? (uint32_t)__shfl((int)ol, src) : 0u;
-                if (k < cnt) {
-                    acc[0] += r0;
-                    acc[1] += r1;
-                    acc[2] += r2;
-                    if (LIT) {
-                        litacc |= rl;
-                        probeacc |= rl ? 1u << min(i0 + k - off, 31) : 0u;   // bit 31: probe 31 or a later one
-                    }
-                }
-            }
         }
     }
     if (inb) {
