@@ -9,8 +9,9 @@
 // (straight-through floor).  Parameters: each material's roughness alpha
 // and log flake density ln N, each light's raw direction.
 //
-// Reduction (deterministic): per light, a butterfly wave sum (every lane ends
-// with the same bits); per material, fixed-order LDS sums; per tile, one
+// Reduction (deterministic): per light, a fixed-order wave sum by DPP lane
+// moves (wave_sum); per material, fixed-order LDS sums in the tile kernel and
+// wave sums in the work-unit kernel; per tile or work unit, one
 // partial row in the workspace (row index = tile index, so the sums do not
 // depend on the order in which tiles run); two FP64 kernels then sum the rows
 // in a fixed order.  Tiles run heaviest first (the forward's tile order).
@@ -31,12 +32,11 @@
 
 namespace glint {
 
-// v + (v moved across lanes by the DPP control CTRL); lanes that the row
-// mask leaves out, or whose source lane does not exist, add 0
+// v + (v moved across lanes by the DPP control CTRL, dpp_mov)
 template <int CTRL, int ROWS = 0xf>
 __device__ __forceinline__ float dpp_add(float v)
 {
-    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+    return v + __uint_as_float(dpp_mov<CTRL, ROWS>(__float_as_uint(v)));
 }
 
 // Sum over the 64 lanes (every lane active), in a fixed order, with data
@@ -347,13 +347,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
             }
         }
     }
-    int incl = npr;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int t = __shfl_up(incl, d);
-        if (lane >= d) incl += t;
-    }
-    const int S = __shfl(incl, kWave - 1);
+    const int incl = wave_inclusive_sum(npr);
+    const int S = __builtin_amdgcn_readlane(incl, kWave - 1);
     sm.off[lane] = incl - npr;
     if (lane < kMaxLight * 3) (&sm.dd[0][0])[lane] = 0.0f;
     __syncthreads();
@@ -520,13 +515,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
                 if (px.flags & F_SHADED) sm.rec[lane] = make_rec(px, sh);
                 else sm.rec[lane].pk = 0u;
                 const int cnt = has ? lit_probe_count(pm, px.npr) * __popc(litm) : 0;
-                int incl = cnt;
-#pragma unroll
-                for (int d = 1; d < kWave; d <<= 1) {
-                    const int t = __shfl_up(incl, d);
-                    if (lane >= d) incl += t;
-                }
-                S = __shfl(incl, kWave - 1);
+                const int incl = wave_inclusive_sum(cnt);
+                S = __builtin_amdgcn_readlane(incl, kWave - 1);
                 sm.off[lane] = incl - cnt;
                 cur = (int)c;
                 __syncthreads();
@@ -731,12 +721,7 @@ __device__ __forceinline__ uint32_t block_prefix(uint32_t v, uint32_t &total)
 {
     __shared__ uint32_t wsum[kLitThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    uint32_t incl = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = __shfl_up(incl, d);
-        if (lane >= d) incl += t;
-    }
+    const uint32_t incl = (uint32_t)wave_inclusive_sum((int)v);
     if (lane == kWave - 1) wsum[w] = incl;
     __syncthreads();
     uint32_t before = 0;

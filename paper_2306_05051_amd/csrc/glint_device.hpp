@@ -67,6 +67,28 @@ __device__ __forceinline__ int item_pixel(int off, int q)
     return p;
 }
 
+// Lane v moved by the DPP control CTRL within the rows of the mask ROWS;
+// lanes whose source lies outside their 16-lane row, or in rows the mask
+// leaves out, get 0.  Every lane of the wave must be active.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+// inclusive prefix sum over the 64 lanes (all active): row shifts by 1, 2,
+// 4, 8, then the row broadcasts 15 and 31
+__device__ __forceinline__ int wave_inclusive_sum(int x)
+{
+    x += (int)dpp_mov<0x111, 0xf>((uint32_t)x);   // row_shr:1
+    x += (int)dpp_mov<0x112, 0xf>((uint32_t)x);   // row_shr:2
+    x += (int)dpp_mov<0x114, 0xf>((uint32_t)x);   // row_shr:4
+    x += (int)dpp_mov<0x118, 0xf>((uint32_t)x);   // row_shr:8
+    x += (int)dpp_mov<0x142, 0xa>((uint32_t)x);   // row_bcast:15 into rows 1 and 3
+    x += (int)dpp_mov<0x143, 0xc>((uint32_t)x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 struct ViewDesc {
     int32_t width, height;
     int64_t stride;
