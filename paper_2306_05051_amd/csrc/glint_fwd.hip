@@ -230,19 +230,19 @@ __device__ void dump_zero(const DumpDst &d, int n_light)
     }
 }
 
-// LK = 2 shades one item on two lanes: the even lane takes the even lights,
-// the odd lane the odd ones, and after every pair of lights the even lane
-// (the item's owner) receives its partner's factor and extends the radiance
-// chain with both, in light order.  With LK = 1 one lane takes every light.
-// Either way the chain is o.rgb = fma(E_l, f_l, o.rgb) over l = 0, 1, ...
-// with f_l = +0 for a light without an open gate, so the image has the same
-// bits.  p: the item's pixel in the tile, kp: its probe, (u, v): the pixel's uv.
+// LK = 2 or 4 shades one item on LK lanes of a quad: lane r of the group
+// takes the lights l = r (mod LK), and after every LK lights the group's
+// first lane (the item's owner) receives its partners' factors (DPP quad
+// moves) and extends the radiance chain with them, in light order.  With
+// LK = 1 one lane takes every light.  Either way the chain is
+// o.rgb = fma(E_l, f_l, o.rgb) over l = 0, 1, ... with f_l = +0 for a light
+// without an open gate, so the image has the same bits.  p: the item's pixel in the tile, kp: its probe, (u, v): the pixel's uv.
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LK = 1, int LAW = kLawDistributed>
 __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint32_t *lrec, int ip, double u, double v,
                                            int kp, const Shared &sh, ItemOut &o, const uint32_t *ltbl, float zN = 0.0f,
                                            const DumpDst dd = DumpDst{})
 {
-    static_assert(LK == 1 || (LK == 2 && !DEBUG), "two lanes per item only in the production kernels");
+    static_assert(LK == 1 || ((LK == 2 || LK == 4) && !DEBUG), "several lanes per item only in the production kernels");
     const int lane = threadIdx.x;
     o.rgb[0] = o.rgb[1] = o.rgb[2] = 0.0f;
     if (LIT) o.lit = 0u;
@@ -283,12 +283,12 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
         }
     }
     const int n_light = sh.n_light;
-    const int trips = LK == 1 ? n_light : (n_light + 1) >> 1;
+    const int trips = (n_light + LK - 1) / LK;
     for (int j = 0; j < trips; ++j) {
-        const int li = LK == 1 ? j : 2 * j + (lane & 1);
+        const int li = LK * j + (lane & (LK - 1));
         float f = 0.0f;                        // this light's radiance factor F G D_P / (4 <wi,n>)
         do {
-            if (LK == 2 && li >= n_light) break;
+            if (LK > 1 && li >= n_light) break;
             const uint32_t *lw = lrec + (size_t)li * kLightRecWords * kWave + ip;
             uint32_t K[4];
 #pragma unroll
@@ -455,18 +455,30 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
 #pragma unroll
             for (int c = 0; c < 3; ++c) o.rgb[c] = fmaf(L.rad[c], f, o.rgb[c]);
         } else {
-            const float f1 = __shfl_xor(f, 1);     // the partner's light: 2j + 1 for the even lane
-            const DevLight &L0 = sh.lights[2 * j];
+            // the owner's partners' factors: lights LK j + r (DPP quad moves
+            // [1,1,3,3] for pairs, [r,r,r,r] for quads)
+            float fr[LK];
+            fr[0] = f;
+            if constexpr (LK == 2) {
+                fr[1] = __uint_as_float(dpp_mov<0xF5>(__float_as_uint(f)));
+            } else {
+                fr[1] = __uint_as_float(dpp_mov<0x55>(__float_as_uint(f)));
+                fr[2] = __uint_as_float(dpp_mov<0xAA>(__float_as_uint(f)));
+                fr[3] = __uint_as_float(dpp_mov<0xFF>(__float_as_uint(f)));
+            }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) o.rgb[c] = fmaf(L0.rad[c], f, o.rgb[c]);
-            if (2 * j + 1 < n_light) {
-                const DevLight &L1 = sh.lights[2 * j + 1];
+            for (int r = 0; r < LK; ++r) {
+                if (LK * j + r >= n_light) break;
+                const DevLight &L = sh.lights[LK * j + r];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) o.rgb[c] = fmaf(L1.rad[c], f1, o.rgb[c]);
+                for (int c = 0; c < 3; ++c) o.rgb[c] = fmaf(L.rad[c], fr[r], o.rgb[c]);
             }
         }
     }
-    if (LIT && LK == 2) o.lit |= __shfl_xor(o.lit, 1);
+    if constexpr (LIT && LK > 1) {
+        o.lit |= dpp_mov<0xB1>(o.lit);             // quad_perm [1,0,3,2]
+        if (LK == 4) o.lit |= dpp_mov<0x4E>(o.lit);   // quad_perm [2,3,0,1]
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -529,7 +541,8 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 //  1. lane = pixel: footprint, probes, grid nodes (setup_pixel), the pixel's
 //     LDS fields, and one record per light (make_light_rec).
 //  2. a wave prefix sum flattens the tile's (pixel, probe) items; lanes take
-//     them 64 at a time (two lanes per item in a last batch of at most 32).
+//     them 64 at a time (two or four lanes per item in a last batch of at
+//     most 32 or 16 items).
 //  3. per batch, segmented_sums leaves each pixel's item sum on the lane of
 //     its last item, and the pixel lane adds it to its RGB (one cross-lane
 //     read per channel).
@@ -617,11 +630,13 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
     if (DEBUG)
         for (int l = 0; l < kMaxLight; ++l) db[l] = 0.0f;
     for (int base = 0; base < S; base += kWave) {
-        // a last batch of at most 32 items takes two lanes per item, each
-        // shading half of the lights (the even or the odd ones); the item's
-        // result is on its even lane
-        const int lk = (!DEBUG && S - base <= kWave / 2 && sh.n_light > 1) ? 2 : 1;
-        const int q = base + (lk == 2 ? lane >> 1 : lane);
+        // a last batch of at most 32 (16) items takes two (four) lanes per
+        // item, lane r of the group shading the lights l = r mod 2 (4); the
+        // item's result is on the group's first lane
+        const int lkl = DEBUG ? 0 : (S - base <= kWave / 4 && sh.n_light > 2) ? 2 :
+                                    (S - base <= kWave / 2 && sh.n_light > 1) ? 1 : 0;
+        const int lk = 1 << lkl;
+        const int q = base + (lane >> lkl);
         float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f;
         uint32_t ol = 0u;
         // the item's pixel and probe, with every lane active (cross-lane reads)
@@ -640,22 +655,24 @@ __device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlan
                 shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN, dd);
             } else if (lk == 1)
                 shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
-            else
+            else if (lk == 2)
                 shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
+            else
+                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 4, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
             o0 = o.rgb[0];
             o1 = o.rgb[1];
             o2 = o.rgb[2];
             if (LIT) ol = o.lit;
             if constexpr (DEBUG) sm.dslot[lane] = o;
         }
-        // item j of the batch onto lane j (two lanes per item: from lane 2j),
+        // item j of the batch onto lane j (lk lanes per item: from lane lk j),
         // then the per-pixel sums of the batch (segmented_sums)
         float v[3] = {o0, o1, o2};
         uint32_t vl = ol, vm = (LIT && ol) ? 1u << min(kp, 31) : 0u;   // probe bit 31: probe 31 or a later one
         int kj = kp;
-        if (lk == 2) {
-            const int src = (2 * lane) & (kWave - 1);
-            const bool in = lane < kWave / 2;
+        if (lk > 1) {
+            const int src = (lane << lkl) & (kWave - 1);
+            const bool in = lane < (kWave >> lkl);
 #pragma unroll
             for (int c = 0; c < 3; ++c) v[c] = __shfl(v[c], src);
             kj = __shfl(kj, src);
