@@ -371,9 +371,27 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
             for (int g = 0; g < 4; ++g)
                 if (g < nn) anyK |= K[g];
             if (!DEBUG && anyK == 0u) break;   // no gate of this light can open
+            // slot-0 angular keys.  Inside a tile the light's angular cell is
+            // nearly always the same for every item of the batch (95% of the
+            // batch-light iterations of the 4K frame): then the four keys are
+            // hashed once, in scalar registers (scalar ALU, beside the vector
+            // work), instead of once per lane.
             uint32_t ak0[4];
+            const uint32_t cu = __builtin_amdgcn_readfirstlane(code);
+            if (__ballot(code != cu) == 0ull) {
+                const uint32_t Au = cu & 0x7FFFu, Bu = (cu >> 15) & 0x7FFFu;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) ak0[a] = angular_key(A, B, a & 1, a >> 1, 0);
+                for (int a = 0; a < 4; ++a) {
+                    ak0[a] = angular_key(Au, Bu, a & 1, a >> 1, 0);
+                    // pinned to a scalar register here, so that the compiler
+                    // does not merge this branch's hashing with the other's
+                    // (vector) one after the branches join
+                    asm volatile("" : "+s"(ak0[a]));
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) ak0[a] = angular_key(A, B, a & 1, a >> 1, 0);
+            }
             uint32_t mlo = 0u, mhi = 0u;       // open gates: bit g*16 + e*4 + a (g < 2 in mlo)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
