@@ -153,22 +153,38 @@ def test_maximum_materials_and_lights(glint):
     _check(glint, gb, mats, lights, "32 materials, 16 lights")
 
 
-@pytest.mark.parametrize("n_light", [2, 3, 5])
+@pytest.mark.parametrize("n_light", [2, 3, 4, 5])
 def test_two_lanes_per_item_in_short_batches(glint, n_light):
-    """A tile's last batch of at most 32 items runs each item on two lanes
-    (even and odd lights); the radiance chain keeps light order, so the image
-    equals the instrumented kernel's (one lane per item) bit for bit, also for
-    an odd number of lights."""
+    """A tile's last batch of at most 32 (16) items runs each item on two
+    (four, with more than two lights) lanes, lane r taking the lights
+    l = r mod 2 (4); the radiance chain keeps light order, so the image
+    equals the instrumented kernel's (one lane per item) bit for bit, also
+    when the lights do not fill the last group.  The lit masks of
+    glint_shade_lit equal the instrumented kernel's per-light counts."""
     gb, mats, lights = scenes.four_k(200, 90, seed=12, n_light=n_light)
     grgb, gdbg = _run(glint, gb, mats, lights)
     H, W = gb["u"].shape
     npr = np.zeros(((H + 1) // 2 * 2, (W + 31) // 32 * 32), np.int64)
     npr[:H, :W] = gdbg["n_probe"]
     S = npr.reshape(npr.shape[0] // 2, 2, npr.shape[1] // 32, 32).sum((1, 3)).ravel()
-    short = int(np.sum((S > 0) & ((S - 1) % 64 < 32)))
-    print(f"  tiles with a last batch of <= 32 items: {short} of {int(np.sum(S > 0))}", flush=True)
-    assert short > 20 and np.sum(S > 64) > 20
-    _check(glint, gb, mats, lights, f"two lanes per item, {n_light} lights")
+    last = (S - 1) % 64
+    short = int(np.sum((S > 0) & (last < 32)))
+    quad = int(np.sum((S > 0) & (last < 16)))
+    print(f"  tiles with a last batch of <= 32 (16) items: {short} ({quad}) of {int(np.sum(S > 0))}", flush=True)
+    assert short > 20 and quad > 10 and np.sum(S > 64) > 20
+    _check(glint, gb, mats, lights, f"short batches, {n_light} lights")
+    dgb = glint.to_device(gb)
+    rgb_l, lit, probes = glint.glint_shade_lit(dgb, mats, lights, rounding=0)
+    torch.cuda.synchronize()
+    assert np.array_equal(rgb_l.cpu().numpy(), grgb)
+    lit = lit.cpu().numpy().astype(np.int64) & 0xFFFF
+    want = sum(((gdbg["b_light"][l] > 0).astype(np.int64) << l) for l in range(n_light))
+    assert np.array_equal(lit, want)
+    # probe bits only below the pixel's probe count (bit 31: probe 31 or later), set iff a light is lit
+    pm = probes.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    npx = gdbg["n_probe"].astype(np.int64)
+    assert np.all((pm & ~((1 << np.minimum(npx, 32)) - 1)) == 0)
+    assert np.array_equal(pm != 0, lit != 0)
 
 
 @pytest.mark.parametrize("k_max,n_probe_max", [(0, 21), (1, 21), (2, 8), (4, 1), (3, 64)])
