@@ -236,7 +236,8 @@ __device__ void dump_zero(const DumpDst &d, int n_light)
 // moves) and extends the radiance chain with them, in light order.  With
 // LK = 1 one lane takes every light.  Either way the chain is
 // o.rgb = fma(E_l, f_l, o.rgb) over l = 0, 1, ... with f_l = +0 for a light
-// without an open gate, so the image has the same bits.  p: the item's pixel in the tile, kp: its probe, (u, v): the pixel's uv.
+// without an open gate, so the image has the same bits.  ip: the item's
+// pixel in the tile, kp: its probe, (u, v): the pixel's uv.
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LK = 1, int LAW = kLawDistributed>
 __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint32_t *lrec, int ip, double u, double v,
                                            int kp, const Shared &sh, ItemOut &o, const uint32_t *ltbl, float zN = 0.0f,
