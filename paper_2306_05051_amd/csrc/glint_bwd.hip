@@ -498,6 +498,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
         uint32_t c = lo;
         uint32_t b = u - (uint32_t)__builtin_amdgcn_readfirstlane((int)unit_off[c]);
         int cur = -1, S = 0;
+        // the chunk lane's pixel: its first item, list entry and masks
+        int offr = 0;
+        uint32_t pixr = 0u, pmr = 0u, litr = 0u;
         while (u < u_end && c < n_chunks) {
             if ((int)c != cur) {
                 // the chunk's pixel set-up: records (probe count 0 for a pixel
@@ -517,7 +520,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
                 const int cnt = has ? lit_probe_count(pm, px.npr) * __popc(litm) : 0;
                 const int incl = wave_inclusive_sum(cnt);
                 S = __builtin_amdgcn_readlane(incl, kWave - 1);
-                sm.off[lane] = incl - cnt;
+                offr = incl - cnt;
+                pixr = pix;
+                pmr = pm;
+                litr = litm;
                 cur = (int)c;
                 __syncthreads();
             }
@@ -529,19 +535,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
             // batch b of chunk c: item r -> pixel p (the last with off <= r),
             // then probe rank r' / nl and light rank r' % nl, r' = r - off
             const int r = (int)b * kWave + lane;
-            int p = 0;
-#pragma unroll
-            for (int st = 32; st > 0; st >>= 1)
-                if (sm.off[p + st] <= r) p += st;
+            // cross-lane reads from the chunk lanes, every lane active
+            const int p = item_pixel(offr, r < S ? r : S - 1);
+            const int offp = __shfl(offr, p);
+            const uint32_t pidx = (uint32_t)__shfl((int)pixr, p), pm = (uint32_t)__shfl((int)pmr, p);
+            const uint32_t litm = (uint32_t)__shfl((int)litr, p);
             const bool live = r < S && rec_npr(sm.rec[p]) > 0;
             int kp = 0, li = 0;
             float g3[3] = {0.0f, 0.0f, 0.0f};
             double n[3] = {0, 0, 1}, wi[3] = {0, 0, 1}, uu = 0.0, vv = 0.0, rc = 1.0, rs = 0.0;
             if (live) {
-                const uint32_t pidx = list[c * kWave + (uint32_t)p];
-                const uint32_t pm = lit_probes[pidx], litm = (uint32_t)lit[pidx] & lmask;
                 const int nl = __popc(litm);
-                const int rr = r - sm.off[p];
+                const int rr = r - offp;
                 const int pr = rr / nl, lr = rr - pr * nl;
                 const uint32_t low = pm & 0x7fffffffu;
                 const int nlow = __popc(low);
