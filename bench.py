@@ -19,8 +19,11 @@ stream; roofline_bwd does the same for the adjoint call of the 4K
 forward+backward step.  Extra keys: the rate over shaded pixels only, the 4K
 forward+backward rate, the batched path on 64 views of 128^2..2048^2 against
 64 glint_shade calls on the same stream, and the 1024^2 forward+backward
-(the adjoint's configuration).  cpu_baseline times the FP64 oracle on the
-host cores (model and thread count stated).
+(the adjoint's configuration), and two further fractions of the forward
+call: FP32 FLOP/s over the 157.3 TFLOP/s vector peak and VALU instructions
+per clock per SIMD over the rate valu_probe measures (both from the
+committed counters while the kernel sources match them).  cpu_baseline
+times the FP64 oracle on the host cores (model and thread count stated).
 """
 import argparse
 import json
@@ -70,6 +73,51 @@ def recorded_traffic():
     if not (sha and val) or sha.group(1) != sources_sha256():
         return None
     return int(val.group(1))
+
+
+# v_mul_f32 wavefront instructions per clock per SIMD that valu_probe
+# sustains with 16 waves per SIMD (profiles/valu_issue_rates.txt)
+PROBE_ISSUE_PER_CLK = 0.452
+
+
+def recorded_instruction_counts():
+    """(VALU wavefront instructions, FP32 FLOP instructions) of one 4K
+    shading kernel from the committed counter summary (SQ_INSTS_VALU and
+    SQ_INSTS_VALU_FLOPS_FP32: an add, multiply or transcendental counts 1, an
+    FMA 2), or None when the kernel sources have changed since."""
+    import re
+    try:
+        txt = open(COUNTERS).read()
+    except OSError:
+        return None
+    sha = re.search(r"^sources_sha256: ([0-9a-f]{64})$", txt, re.M)
+    valu = re.search(r"^\s+SQ_INSTS_VALU\s+([0-9.e+]+)$", txt, re.M)
+    flops = re.search(r"^\s+SQ_INSTS_VALU_FLOPS_FP32\s+([0-9.e+]+)$", txt, re.M)
+    if not (sha and valu and flops) or sha.group(1) != sources_sha256():
+        return None
+    return float(valu.group(1)), float(flops.group(1))
+
+
+def other_fractions(kernel_ms):
+    """The two further fractions of the forward call: (i) FP32 FLOP/s (64
+    lanes per counted instruction, an upper bound: idle lanes do no work)
+    over the 157.3 TFLOP/s vector peak; (ii) VALU wavefront instructions per
+    clock per SIMD over the rate valu_probe sustains for v_mul_f32 (every
+    instruction counted once, so half- and quarter-rate ones make this a
+    lower bound).  Both from the committed counters and the live call time."""
+    from paper_2306_05051_amd import costmodel
+    rec = recorded_instruction_counts()
+    if rec is None:
+        return None
+    valu, flop_inst = rec
+    t = kernel_ms / 1e3
+    flops = 64.0 * flop_inst / t
+    per_clk = valu / (costmodel.CU * costmodel.SIMD_PER_CU * costmodel.CLOCK_HZ * t)
+    return {"fp32_flop": {"achieved": round(flops / 1e12, 3), "peak": costmodel.FP32_PEAK_FLOPS / 1e12,
+                          "unit": "TFLOP/s", "frac": round(flops / costmodel.FP32_PEAK_FLOPS, 4)},
+            "valu_issue": {"achieved": round(per_clk, 4), "peak": PROBE_ISSUE_PER_CLK,
+                           "unit": "wave-instructions/clock/SIMD", "frac": round(per_clk / PROBE_ISSUE_PER_CLK, 4),
+                           "valu_instructions_per_launch": int(valu)}}
 
 
 def cpu_baseline(gb, mats, lights, target_s=10.0):
@@ -235,6 +283,11 @@ def main():
                 "frac": round(achieved / costmodel.VALU_PEAK_SLOTS, 4), "traffic": recorded_traffic(),
                 "kernel": "glint_fwd_kernel<false> + tile-order pre-pass", "kernel_ms": round(kernel_ms, 4),
                 "slots_per_launch": int(slots), "units_per_launch": units}
+    # the two other fractions the survey asks for; roofline.frac (algorithmic
+    # slots over the issue peak) is the headline one
+    fr = other_fractions(kernel_ms)
+    if fr is not None:
+        extra["fractions"] = fr
 
     # forward + backward on the same frame (relaxed counts): the forward records
     # which lights and probes opened a gate, the adjoint skips the rest
