@@ -59,6 +59,8 @@ enum {
 #define GLINT_RNG_CACHED 0           /* table read from device memory through L1/L2    */
 #define GLINT_RNG_LDS 1              /* each tile's wave copies the table into LDS     */
 #define GLINT_NOALLOC_WORKSPACE_BYTES 2097152  /* static workspace of glint_shade_noalloc, per GPU */
+#define GLINT_TILE_W 16              /* glint_shade's tile: GLINT_TILE_W x GLINT_TILE_H pixels, */
+#define GLINT_TILE_H 4               /* one 64-lane wave each                                 */
 
 /* G-buffer of one view (Sec. 5.1 reads footprints from screen derivatives).
  * u, v: texture coordinates; dudx..dvdy: their screen-space derivatives
@@ -213,8 +215,8 @@ size_t glint_shade_workspace_bytes(int32_t width, int32_t height);
  * workspace: device memory of at least glint_shade_workspace_bytes(width,
  * height) bytes, 4-byte aligned, owned by the caller and used by this call
  * only (calls that overlap on the device need their own).  The view is
- * shaded in tiles of 32 x 2 pixels (one 64-lane wave each; n_tiles =
- * ceil(width/32) * ceil(height/2)).  With a workspace the tiles are shaded
+ * shaded in tiles of GLINT_TILE_W x GLINT_TILE_H = 16 x 4 pixels (one
+ * 64-lane wave each; n_tiles = ceil(width/16) * ceil(height/4)).  With a workspace the tiles are shaded
  * heaviest first (a cost pre-pass over the derivatives orders them by their
  * number of probe items; the first 4*n_tiles bytes then hold that order as
  * int32 tile indices, row-major tile numbering); with workspace == NULL they
@@ -312,7 +314,7 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * reduced in a fixed order (deterministic).  Per-pixel overrides
  * (alpha_px, log10_density_px) are not supported (EUNSUPPORTED).
  * workspace: device memory of at least glint_backward_workspace_bytes()
- * bytes (about 4 bytes per pixel plus one partial row per 32x2 tile),
+ * bytes (about 4 bytes per pixel plus one partial row per 16x4 tile),
  * 8-byte aligned, owned by the caller and used by this call only (tile
  * order, partial rows, FP64 reduction stage, lit-pixel list).  Without a
  * mask, tiles run heaviest first; the sums are reduced in a fixed order over
@@ -344,7 +346,7 @@ int glint_shade_backward(const glint_gbuffer *gbuf, const glint_material *mats, 
  * glint_plan_create copies the view descriptors (device pointers inside
  * gbufs/out_rgb stay owned by the caller and must outlive the plan), the
  * materials, lights and params, builds the tile table on the device, and
- * (tune may be NULL: 32 x 2 tiles, one workgroup per tile) fixes the launch
+ * (tune may be NULL: 16 x 4 tiles, one workgroup per tile) fixes the launch
  * shape.
  * glint_shade_batched enqueues [counter reset kernel, persistent kernel]
  * (or, with blocks_per_cu = 0, one kernel with a workgroup per tile) on

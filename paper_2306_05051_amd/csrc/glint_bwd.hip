@@ -277,7 +277,7 @@ __device__ __forceinline__ void grad_item_light(bool live, const PixelRec &R, do
                sm, da, dn, gd);
 }
 
-// Work units: without a lit mask, workgroup b shades the 32x2 tile order[b]
+// Work units: without a lit mask, workgroup b shades the tile order[b]
 // (heaviest first); with one, workgroup b takes the lit pixels
 // list[64 b .. 64 b + 63] (raster order, built by the compaction passes
 // below), so that the few lit pixels fill whole waves.  The partial row is

@@ -28,6 +28,7 @@ PLANES = ("u", "v", "dudx", "dvdx", "dudy", "dvdy", "nx", "ny", "nz", "wx", "wy"
 GLINT_OK, GLINT_EINVAL, GLINT_ENULL, GLINT_ESHAPE = 0, -1, -2, -3
 GLINT_EHIP, GLINT_EUNSUPPORTED, GLINT_ENOMEM, GLINT_ELIMIT = -4, -5, -6, -7
 GLINT_NOALLOC_WORKSPACE_BYTES = 2097152
+GLINT_TILE_W, GLINT_TILE_H = 16, 4           # glint_shade's tile (one 64-lane wave)
 GLINT_MAX_MATERIALS, GLINT_MAX_LIGHTS, GLINT_MAX_K, GLINT_MAX_PROBES = 32, 16, 4, 64
 GLINT_RNG_TABLE_MIN_LOG2, GLINT_RNG_TABLE_MAX_LOG2, GLINT_RNG_LDS_MAX_LOG2 = 8, 32, 13
 GLINT_RNG_CACHED, GLINT_RNG_LDS = 0, 1

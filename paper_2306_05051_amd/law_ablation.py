@@ -14,7 +14,7 @@ paper's performance setting (1920x1080, Beckmann alpha = 1.0, one light;
 plane views and scattered anisotropy; K in {0, 4}; flake densities 10^3 ...
 10^8), and reports per configuration the rate of each law, and for the
 baseline its work from one instrumented run: Gaussian draws and Bernoulli
-trials per pixel, and the mean over 32x2 tiles of the tile's largest trial
+trials per pixel, and the mean over the library's tiles of the tile's largest trial
 count (a wave waits for its slowest lane).  Prints one JSON object on stdout
 and a table on stderr.
 """
@@ -30,7 +30,7 @@ DENSITIES = (3.0, 4.0, 5.0, 6.0, 7.0, 8.0)
 K_LEVELS = (0, 4)
 
 
-def _tile_max_mean(a, tw=32, th=2):
+def _tile_max_mean(a, tw=16, th=4):
     H, W = a.shape
     Hp, Wp = (H + th - 1) // th * th, (W + tw - 1) // tw * tw
     b = np.zeros((Hp, Wp), np.float64)

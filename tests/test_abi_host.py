@@ -38,7 +38,8 @@ def test_limits_match_header():
     txt = open(HEADER).read()
     for name in ("GLINT_MAX_MATERIALS", "GLINT_MAX_LIGHTS", "GLINT_MAX_K", "GLINT_MAX_PROBES",
                  "GLINT_RNG_TABLE_MIN_LOG2", "GLINT_RNG_TABLE_MAX_LOG2", "GLINT_RNG_LDS_MAX_LOG2",
-                 "GLINT_RNG_CACHED", "GLINT_RNG_LDS", "GLINT_FLAG_ZK_COUNT", "GLINT_NOALLOC_WORKSPACE_BYTES"):
+                 "GLINT_RNG_CACHED", "GLINT_RNG_LDS", "GLINT_FLAG_ZK_COUNT", "GLINT_NOALLOC_WORKSPACE_BYTES",
+                 "GLINT_TILE_W", "GLINT_TILE_H"):
         m = re.search(r"#define " + name + r"\s+(\d+)", txt)
         assert m and int(m.group(1)) == getattr(glint, name), name
 
@@ -74,7 +75,7 @@ def test_host_validation_without_device(lib):
     assert L.glint_shade(C.byref(g), badm, 1, lts, 1, C.byref(prm), out, None, None, 0, None) == glint.GLINT_EINVAL
     # tile-order workspace: size formula, too small, misaligned (rejected before any launch)
     assert L.glint_shade_workspace_bytes(0, 5) == 0
-    tiles = 120 * 1080                       # 32 x 2 tiles
+    tiles = (3840 // glint.GLINT_TILE_W) * (2160 // glint.GLINT_TILE_H)
     assert L.glint_shade_workspace_bytes(3840, 2160) >= 5 * tiles
     assert L.glint_shade_workspace_bytes(3840, 2160) < 6 * tiles + 4096
     need = L.glint_shade_workspace_bytes(4, 4)

@@ -164,9 +164,10 @@ def test_two_lanes_per_item_in_short_batches(glint, n_light):
     gb, mats, lights = scenes.four_k(200, 90, seed=12, n_light=n_light)
     grgb, gdbg = _run(glint, gb, mats, lights)
     H, W = gb["u"].shape
-    npr = np.zeros(((H + 1) // 2 * 2, (W + 31) // 32 * 32), np.int64)
+    TW, TH = glint.GLINT_TILE_W, glint.GLINT_TILE_H
+    npr = np.zeros(((H + TH - 1) // TH * TH, (W + TW - 1) // TW * TW), np.int64)
     npr[:H, :W] = gdbg["n_probe"]
-    S = npr.reshape(npr.shape[0] // 2, 2, npr.shape[1] // 32, 32).sum((1, 3)).ravel()
+    S = npr.reshape(npr.shape[0] // TH, TH, npr.shape[1] // TW, TW).sum((1, 3)).ravel()
     last = (S - 1) % 64
     short = int(np.sum((S > 0) & (last < 32)))
     quad = int(np.sum((S > 0) & (last < 16)))
@@ -318,11 +319,11 @@ def test_tile_order_is_a_heaviest_first_permutation(glint):
     """The cost-ordered tile schedule: the order is a permutation of the
     tiles, sorted by cost class (heaviest first, ties in row-major order),
     and the image is bit-identical to the row-major schedule.  Ragged size:
-    a partial last count block and partial edge tiles (32 x 2 tiles)."""
+    a partial last count block and partial edge tiles."""
     gb, mats, lights = scenes.four_k(645, 363, seed=5)
     dgb = glint.to_device(gb)
     H, W = gb["u"].shape
-    TW, TH = 32, 2
+    TW, TH = glint.GLINT_TILE_W, glint.GLINT_TILE_H
     tx, ty = (W + TW - 1) // TW, (H + TH - 1) // TH
     n = tx * ty
     nb = glint.glint_shade_workspace_bytes(W, H)
