@@ -96,6 +96,9 @@ def lib():
         L.og_grad.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), C.c_int, C.POINTER(_Light), C.c_int,
                               C.POINTER(_Params), C.c_void_p, C.c_double, C.c_int, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.og_grad_dual.argtypes = [C.POINTER(_GBuf), C.POINTER(_Mat), C.c_int, C.POINTER(_Light), C.c_int,
+                                   C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int]
         L.og_fmix32.argtypes = [C.c_uint32]
         L.og_fmix32.restype = C.c_uint32
         L.og_hash_step.argtypes = [C.c_uint32, C.c_uint32]
@@ -254,6 +257,25 @@ def grad(gb, materials, lights, grad_out, step=1e-6, frozen=True, k_max=4, n_pro
         raise ValueError(f"og_grad failed ({rc})")
     del keep
     return ga, gn, gd.reshape(len(lights), 3), flip
+
+
+def grad_dual(gb, materials, lights, grad_out, k_max=4, n_probe_max=21, n_threads=0):
+    """The same gradient as grad(frozen=True) by forward-mode derivatives (dual
+    numbers carried through the relaxed forward, decisions taken on the
+    values).  Returns (g_alpha, g_lnN, g_dir, loss) with loss = sum(grad_out * L)."""
+    L = lib()
+    s, keep, H, W = _gbuf(gb)
+    mats, lts = _mats(materials), _lights(lights)
+    prm = _Params(k_max, n_probe_max, 1, 0, 0)
+    go = np.ascontiguousarray(grad_out, dtype=np.float64).reshape(3, H, W)
+    ga = np.zeros(len(materials)); gn = np.zeros(len(materials)); gd = np.zeros(3 * len(lights))
+    loss = np.zeros(1)
+    rc = L.og_grad_dual(C.byref(s), mats, len(materials), lts, len(lights), C.byref(prm), go.ctypes.data,
+                        ga.ctypes.data, gn.ctypes.data, gd.ctypes.data, loss.ctypes.data, n_threads)
+    if rc != 0:
+        raise ValueError(f"og_grad_dual failed ({rc})")
+    del keep
+    return ga, gn, gd.reshape(len(lights), 3), float(loss[0])
 
 
 # ---- scalar entry points used by the pin tests ------------------------------------------

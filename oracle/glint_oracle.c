@@ -42,7 +42,8 @@
  * bilinear weights reconstructing the projected half vector, and the
  * distributed count as the bilinear blend of its values at the angular
  * texel centres (Eq. 14); frozen-branch finite differences
- * against free finite differences; the tangent frame orthonormal and
+ * against free finite differences and against the forward-mode
+ * (dual-number) derivatives of the same relaxed forward; the tangent frame orthonormal and
  * right-handed; the probe centres splitting the major axis into equal
  * segments; the Zirr-Kaplanyan baseline's branches against the binomial
  * and the floored-Gaussian closed forms, and its variance deficit.  The
@@ -1121,5 +1122,253 @@ int og_grad(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_l
     for (int m = 0; m < n_mat; ++m) { g_alpha[m] = acc[2 * m]; g_lnN[m] = acc[2 * m + 1]; }
     for (int i = 0; i < 3 * n_light; ++i) g_dir[i] = acc[2 * n_mat + i];
     free(acc); free(rows); free(base_dirs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Forward-mode derivatives of the relaxed forward (dual numbers): a    */
+/* second route to the gradient og_grad takes by central differences.  */
+/* Every quantity that depends on a parameter carries its derivatives   */
+/* with respect to the pixel's alpha (slot 0), its ln N (slot 1) and    */
+/* the three raw direction components of the light being evaluated      */
+/* (slots 2-4), through the same steps as shade_pixel (Eqs. 1-4, 10,    */
+/* 14, 16-18; Schlick Fresnel, Smith masking).  Every discrete decision */
+/* (light validity, p clamp, angular cell, gates, the max(1, x) clamp)  */
+/* is taken on the values: the result is the derivative with those      */
+/* decisions held fixed, as the adjoint defines it.                     */
+/* ------------------------------------------------------------------ */
+#define OGD_N 5
+typedef struct { double v, d[OGD_N]; } ogd;
+
+static ogd dconst(double v) { ogd r; r.v = v; for (int i = 0; i < OGD_N; ++i) r.d[i] = 0.0; return r; }
+static ogd dvar(double v, int slot) { ogd r = dconst(v); r.d[slot] = 1.0; return r; }
+static ogd dadd(ogd a, ogd b) { ogd r; r.v = a.v + b.v; for (int i = 0; i < OGD_N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+static ogd dsub(ogd a, ogd b) { ogd r; r.v = a.v - b.v; for (int i = 0; i < OGD_N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+static ogd dmul(ogd a, ogd b)
+{
+    ogd r;
+    r.v = a.v * b.v;
+    for (int i = 0; i < OGD_N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+    return r;
+}
+static ogd ddiv(ogd a, ogd b)
+{
+    ogd r;
+    r.v = a.v / b.v;
+    for (int i = 0; i < OGD_N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
+    return r;
+}
+static ogd dscale(ogd a, double s) { for (int i = 0; i < OGD_N; ++i) a.d[i] *= s; a.v *= s; return a; }
+static ogd daddc(ogd a, double c) { a.v += c; return a; }
+/* f(a) with f(a.v) = fv and f'(a.v) = dfv (chain rule) */
+static ogd dchain(ogd a, double fv, double dfv)
+{
+    ogd r;
+    r.v = fv;
+    for (int i = 0; i < OGD_N; ++i) r.d[i] = dfv * a.d[i];
+    return r;
+}
+static ogd dsqrt(ogd a) { double s = sqrt(a.v); return dchain(a, s, 0.5 / s); }
+static ogd dexp(ogd a) { double e = exp(a.v); return dchain(a, e, e); }
+static ogd derf(ogd a) { return dchain(a, erf(a.v), 2.0 / sqrt(OG_PI) * exp(-a.v * a.v)); }
+static ogd ddot3c(const ogd a[3], const double b[3])
+{
+    return dadd(dadd(dscale(a[0], b[0]), dscale(a[1], b[1])), dscale(a[2], b[2]));
+}
+/* a / |a|; 0 when the length is not finite and positive */
+static int dnormalize3(ogd a[3])
+{
+    ogd l2 = dadd(dadd(dmul(a[0], a[0]), dmul(a[1], a[1])), dmul(a[2], a[2]));
+    if (!(l2.v > 0.0) || !isfinite(l2.v)) return 0;
+    ogd l = dsqrt(l2);
+    for (int c = 0; c < 3; ++c) a[c] = ddiv(a[c], l);
+    return 1;
+}
+
+/* og_ndf and og_smith_lambda with dual arguments (same formulas) */
+static ogd d_ndf(int ndf, ogd alpha, ogd cm)
+{
+    if (cm.v <= 0.0) return dconst(0.0);
+    ogd a2 = dmul(alpha, alpha), c2 = dmul(cm, cm);
+    if (ndf == 0) {
+        ogd d = daddc(dmul(c2, daddc(a2, -1.0)), 1.0);
+        return ddiv(a2, dscale(dmul(d, d), OG_PI));
+    }
+    ogd tan2 = ddiv(dsub(dconst(1.0), c2), c2);
+    return ddiv(dexp(dscale(ddiv(tan2, a2), -1.0)), dscale(dmul(a2, dmul(c2, c2)), OG_PI));
+}
+
+static ogd d_smith_g1(int ndf, ogd alpha, ogd c)
+{
+    ogd lam = dconst(0.0);
+    if (c.v < 1.0) {
+        ogd c2 = dmul(c, c);
+        ogd tan2 = ddiv(dsub(dconst(1.0), c2), c2);
+        if (ndf == 0) {
+            lam = dscale(daddc(dsqrt(daddc(dmul(dmul(alpha, alpha), tan2), 1.0)), -1.0), 0.5);
+        } else {
+            ogd a = ddiv(dconst(1.0), dmul(alpha, dsqrt(tan2)));
+            lam = dadd(dscale(daddc(derf(a), -1.0), 0.5),
+                       ddiv(dexp(dscale(dmul(a, a), -1.0)), dscale(a, 2.0 * sqrt(OG_PI))));
+        }
+    }
+    return ddiv(dconst(1.0), daddc(lam, 1.0));
+}
+
+/* one pixel: adds sum_rgb go_rgb L_rgb to *loss and its derivatives to
+ * ga (alpha), gn (ln N) and gd[3 li + c] (light li's raw direction) */
+static void grad_pixel_dual(const og_px_in *in, const og_material *mat, const og_light *lights, int n_light,
+                            const og_params *prm, const double go[3], double *loss, double *ga, double *gn,
+                            double *gd)
+{
+    double mgd[2] = {INFINITY, INFINITY};
+    int mkd[2] = {MK_NONE, MK_NONE};
+    const int K = prm->k_max;
+    double nrm[3] = {in->n[0], in->n[1], in->n[2]};
+    double wi[3] = {in->wi[0], in->wi[1], in->wi[2]};
+    if (!normalize3(nrm) || !normalize3(wi)) return;
+    double tt[3], bb[3];
+    if (!tangent_frame(nrm, in->has_t ? in->t : NULL, tt, bb, mgd, mkd)) return;
+    double P, r, phi, sigma0;
+    if (!og_footprint(in->dudx, in->dvdx, in->dudy, in->dvdy, &P, &r, &phi, &sigma0)) return;
+    const double cos_i = dot3(nrm, wi);
+    if (!(cos_i > 0.0)) return;
+    int n_pr = (int)ceil(r / ldexp(1.0, K));
+    if (n_pr < 1) n_pr = 1;
+    if (n_pr > prm->n_probe_max) n_pr = prm->n_probe_max;
+    double Pk = P / n_pr, rk = r / n_pr;
+    if (rk > ldexp(1.0, K)) rk = ldexp(1.0, K);
+    og_nodes nodes;
+    og_grid_nodes(Pk, rk, phi, K, &nodes, mgd, mkd);
+
+    /* the probes' texel keys and weights do not depend on the parameters */
+    enum { PMAX = 64 };
+    static _Thread_local uint32_t pre[PMAX][OG_MAX_NODES][3];
+    static _Thread_local double beta[PMAX][OG_MAX_NODES][3];
+    const uint32_t s0 = og_hash_step(0x243F6A88u, mat->seed);
+    for (int kp = 0; kp < n_pr && kp < PMAX; ++kp) {
+        double cx, cy;
+        probe_centre(in->u, in->v, phi, sigma0, n_pr, kp, &cx, &cy);
+        for (int g = 0; g < nodes.n; ++g) {
+            int vi[3], vj[3];
+            og_simplex(cx, cy, nodes.l[g], nodes.k[g], nodes.m[g], vi, vj, beta[kp][g], mgd, mkd);
+            uint32_t base = og_hash_step(s0, node_word(nodes.l[g], nodes.k[g], nodes.m[g]));
+            for (int e = 0; e < 3; ++e)
+                pre[kp][g][e] = og_hash_step(og_hash_step(base, (uint32_t)vi[e]), (uint32_t)vj[e]);
+        }
+    }
+
+    const ogd alpha = dvar(in->alpha, 0);
+    const ogd lnN = dvar(in->log10N * log(10.0), 1);
+    const ogd N = dexp(lnN);
+    const double R = mat->R;
+    const ogd Dn = ddiv(dconst(1.0), dscale(dmul(alpha, alpha), OG_PI));
+    const ogd cosi = dconst(cos_i);
+    const ogd G1i = d_smith_g1(mat->ndf, alpha, cosi);
+    const double mr = mat->micro_roughness;
+
+    for (int li = 0; li < n_light; ++li) {
+        ogd wo[3];
+        for (int c = 0; c < 3; ++c) wo[c] = dvar((double)lights[li].dir[c], 2 + c);
+        if (!dnormalize3(wo)) continue;
+        const ogd cos_o = ddot3c(wo, nrm);
+        if (!(cos_o.v > 0.0)) continue;
+        ogd h[3];
+        for (int c = 0; c < 3; ++c) h[c] = daddc(wo[c], wi[c]);
+        if (!dnormalize3(h)) continue;
+        const ogd cos_h = ddot3c(h, nrm);
+        /* Eq. 4 */
+        const ogd praw = ddiv(dscale(d_ndf(mat->ndf, alpha, cos_h), R), Dn);
+        const ogd p = praw.v > 1.0 ? dconst(1.0) : praw;
+        /* Eq. 14: the cell from the values, the weights as duals */
+        const ogd ax = daddc(dscale(ddot3c(h, tt), 1.0 / mr), -0.5);
+        const ogd ay = daddc(dscale(ddot3c(h, bb), 1.0 / mr), -0.5);
+        const int ai = (int)floor(ax.v), aj = (int)floor(ay.v);
+        const ogd fx = daddc(ax, -(double)ai), fy = daddc(ay, -(double)aj);
+        const ogd gx = dsub(dconst(1.0), fx), gy = dsub(dconst(1.0), fy);
+        ogd vw[4] = {dmul(gx, gy), dmul(fx, gy), dmul(gx, fy), dmul(fx, fy)};
+        uint32_t ak[4][2];
+        for (int a = 0; a < 4; ++a)
+            for (int s = 0; s < 2; ++s)
+                ak[a][s] = og_hash_step(0x13198A2Eu, angular_word(ai + (a & 1), aj + (a >> 1), s));
+        /* Schlick Fresnel and Smith masking (Eq. 2) */
+        const ogd ch = ddot3c(h, wi);
+        const ogd om = dsub(dconst(1.0), ch);
+        const ogd om2 = dmul(om, om);
+        const ogd F = daddc(dscale(dmul(dmul(om2, om2), om), 1.0 - mat->F0), mat->F0);
+        const ogd G = dmul(G1i, d_smith_g1(mat->ndf, alpha, cos_o));
+        /* Eqs. 10, 16-18 over the probes, nodes, texels and angular texels */
+        ogd bsum = dconst(0.0);
+        for (int kp = 0; kp < n_pr && kp < PMAX; ++kp)
+            for (int g = 0; g < nodes.n; ++g) {
+                const ogd ng = dscale(N, nodes.w[g] * ldexp(1.0, nodes.l[g]));
+                double pg;
+                if (!(ng.v > 0.0) || !(p.v > 0.0)) pg = 0.0;
+                else if (p.v >= 1.0) pg = 1.0;
+                else pg = -expm1(ng.v * log1p(-p.v));
+                const ogd mm = ng.v - 1.0 > 0.0 ? daddc(ng, -1.0) : dconst(0.0);
+                const ogd mu = dmul(mm, p);
+                const ogd var = dmul(mu, dsub(dconst(1.0), p));
+                const ogd sg = var.v > 0.0 ? dsqrt(var) : dconst(0.0);
+                for (int e = 0; e < 3; ++e)
+                    for (int a = 0; a < 4; ++a) {
+                        const uint32_t h0 = gate_word(prm, pre[kp][g][e], ak[a][0]);
+                        if (!(uniform_of(h0) < pg)) continue;
+                        const uint32_t h1 = gate_word(prm, pre[kp][g][e], ak[a][1]);
+                        const double z = og_ndtri(uniform_of(h1));
+                        const ogd x = daddc(dadd(mu, dscale(sg, z)), 1.0);
+                        const ogd c = x.v >= 1.0 ? x : dconst(1.0);
+                        bsum = dadd(bsum, dscale(dmul(vw[a], c), beta[kp][g][e]));
+                    }
+            }
+        /* Eqs. 1-4 */
+        const ogd DP = ddiv(dmul(Dn, bsum), dscale(N, R * P));
+        const ogd f = dscale(dmul(dmul(F, G), DP), 1.0 / (4.0 * cos_i));
+        double w = 0.0;
+        for (int c = 0; c < 3; ++c) w += go[c] * (double)lights[li].radiance[c];
+        *loss += w * f.v;
+        *ga += w * f.d[0];
+        *gn += w * f.d[1];
+        for (int c = 0; c < 3; ++c) gd[3 * li + c] += w * f.d[2 + c];
+    }
+}
+
+/* Gradients of  sum_px sum_rgb g_rgb(px) L_rgb(px)  (relaxed counts) by  */
+/* forward-mode derivatives; same outputs as og_grad (frozen), plus the   */
+/* loss itself.  Pixel sums are reduced row by row in a fixed order.     */
+int og_grad_dual(const og_gbuffer *gb, const og_material *mats, int n_mat, const og_light *lights,
+                 int n_light, const og_params *prm_in, const double *grad_out, double *g_alpha,
+                 double *g_lnN, double *g_dir, double *loss_out, int n_threads)
+{
+    if (!gb || !mats || n_mat <= 0 || n_light <= 0 || n_light > 64 || !grad_out) return -1;
+    if (prm_in->count_law != 0 || prm_in->n_probe_max > 64) return -1;
+    og_params prm = *prm_in;
+    prm.rounding = 1;
+    const int64_t npx = (int64_t)gb->height * gb->stride;
+    const int np = 2 * n_mat + 3 * n_light + 1;           /* the last column: the loss */
+    double *rows = (double *)calloc((size_t)np * (size_t)gb->height, sizeof(double));
+    if (!rows) return -2;
+    set_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = 0; y < gb->height; ++y) {
+        double *racc = rows + (size_t)y * np;
+        for (int x = 0; x < gb->width; ++x) {
+            const int64_t idx = (int64_t)y * gb->stride + x;
+            og_px_in in;
+            uint32_t lflags = 0;
+            if (!load_pixel(gb, mats, n_mat, idx, &in, &lflags)) continue;
+            const double go[3] = {grad_out[idx], grad_out[npx + idx], grad_out[2 * npx + idx]};
+            grad_pixel_dual(&in, &mats[in.mat], lights, n_light, &prm, go, &racc[np - 1], &racc[2 * in.mat],
+                            &racc[2 * in.mat + 1], &racc[2 * n_mat]);
+        }
+    }
+    double *acc = (double *)calloc((size_t)np, sizeof(double));
+    if (!acc) { free(rows); return -2; }
+    for (int y = 0; y < gb->height; ++y)
+        for (int i = 0; i < np; ++i) acc[i] += rows[(size_t)y * np + i];
+    for (int m = 0; m < n_mat; ++m) { g_alpha[m] = acc[2 * m]; g_lnN[m] = acc[2 * m + 1]; }
+    for (int i = 0; i < 3 * n_light; ++i) g_dir[i] = acc[2 * n_mat + i];
+    if (loss_out) *loss_out = acc[np - 1];
+    free(acc); free(rows);
     return 0;
 }

@@ -123,17 +123,8 @@ enum : uint32_t {
 // Per-texel random numbers.  H(h, w) = fmix32((h ^ w) + golden), fmix32 the
 // MurmurHash3 finaliser; chains absorb one key word per step.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t fmix32(uint32_t h)
-{
-    h ^= h >> 16;
-    h *= 0x85ebca6bu;
-    h ^= h >> 13;
-    h *= 0xc2b2ae35u;
-    h ^= h >> 16;
-    return h;
-}
-
-__host__ __device__ __forceinline__ uint32_t fmix32_hd(uint32_t h)
+// (host and device: the host derives each material's root state with it)
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
 {
     h ^= h >> 16;
     h *= 0x85ebca6bu;

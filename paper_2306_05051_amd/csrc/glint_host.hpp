@@ -67,7 +67,7 @@ inline int prepare_shared(const glint_material *mats, int32_t n_mat, const glint
         d.R = m.R;
         d.log10N = m.log10_density;
         d.F0 = m.F0;
-        d.root = fmix32_hd((kRootSalt ^ m.seed) + 0x9E3779B9u);
+        d.root = fmix32((kRootSalt ^ m.seed) + 0x9E3779B9u);
         d.inv_micro = 1.0 / (double)m.micro_roughness;
     }
     for (int i = 0; i < n_light; ++i) {

@@ -1,6 +1,7 @@
 """GPU adjoint (glint_shade_backward, through the C ABI and the autograd
-Function) against the FP64 oracle's frozen-branch gradient and against GPU
-central differences of the relaxed forward."""
+Function) against the FP64 oracle's two gradients -- central differences with
+the branches frozen, and forward-mode dual numbers -- and against GPU central
+differences of the relaxed forward."""
 import math
 
 import numpy as np
@@ -50,6 +51,11 @@ def test_adjoint_matches_oracle_gradient(glint, size, seed):
     _close(ga.cpu().numpy(), ra, 1e-3, "alpha")
     _close(gn.cpu().numpy(), rn, 1e-3, "lnN")
     _close(gd.cpu().numpy(), rd, 1e-3, "dir")
+    # the dual-number gradient: no step size, no shared code with the above
+    ja, jn, jd, _ = oracle.grad_dual(gb, mats, lights, go.cpu().numpy().astype(np.float64))
+    _close(ga.cpu().numpy(), ja, 1e-3, "alpha (dual)")
+    _close(gn.cpu().numpy(), jn, 1e-3, "lnN (dual)")
+    _close(gd.cpu().numpy(), jd, 1e-3, "dir (dual)")
 
 
 def test_adjoint_multi_material_multi_light(glint):
@@ -63,6 +69,10 @@ def test_adjoint_multi_material_multi_light(glint):
     _close(ga.cpu().numpy(), ra, 2e-3, "alpha")
     _close(gn.cpu().numpy(), rn, 2e-3, "lnN")
     _close(gd.cpu().numpy(), rd, 2e-3, "dir")
+    ja, jn, jd, _ = oracle.grad_dual(gb, mats, lights, go.astype(np.float64))
+    _close(ga.cpu().numpy(), ja, 2e-3, "alpha (dual)")
+    _close(gn.cpu().numpy(), jn, 2e-3, "lnN (dual)")
+    _close(gd.cpu().numpy(), jd, 2e-3, "dir (dual)")
 
 
 def test_autograd_function_and_gpu_central_differences(glint):

@@ -138,6 +138,11 @@ def test_backward_1024(glint):
     print(f"  oracle  {g_or}", flush=True)
     scale = np.abs(g_or).max()
     assert np.all(np.abs(g_ad - g_or) <= 1e-3 * np.abs(g_or) + 2e-5 * scale), (g_ad, g_or)
+    # and its forward-mode dual-number gradient
+    ja, jn, jd, _ = oracle.grad_dual(gb, mats, lights, go)
+    g_du = np.concatenate([ja, jn, jd.ravel()])
+    print(f"  dual    {g_du}", flush=True)
+    assert np.all(np.abs(g_ad - g_du) <= 1e-3 * np.abs(g_du) + 2e-5 * scale), (g_ad, g_du)
     # central differences of the GPU's relaxed forward on the pixels none of
     # whose decisions flips within +-h, against the adjoint of that masked loss
     a0, n0 = float(a), float(n)
@@ -276,3 +281,6 @@ def test_tangent_planes_parity(glint):
     g_or = np.concatenate([ra, rn, rd.ravel()])
     print(f"  adjoint {g_ad}\n  oracle  {g_or}", flush=True)
     assert np.all(np.abs(g_ad - g_or) <= 1e-3 * np.abs(g_or) + 2e-5 * np.abs(g_or).max())
+    ja, jn, jd, _ = oracle.grad_dual(gs, ms, ls, go.cpu().numpy().astype(np.float64))
+    g_du = np.concatenate([ja, jn, jd.ravel()])
+    assert np.all(np.abs(g_ad - g_du) <= 1e-3 * np.abs(g_du) + 2e-5 * np.abs(g_du).max()), (g_ad, g_du)
