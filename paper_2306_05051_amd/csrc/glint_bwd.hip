@@ -757,8 +757,9 @@ __global__ __launch_bounds__(kLitScan) void glint_lit_scan(const uint32_t *__res
                                                            uint32_t *__restrict__ offs, uint32_t *__restrict__ len,
                                                            const uint32_t *__restrict__ n_dev)
 {
-    __shared__ uint32_t ws[kLitScan];
-    const int t = threadIdx.x;
+    constexpr int kScanWaves = kLitScan / kWave;
+    __shared__ uint32_t ws[kScanWaves];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     if (n_dev) {
         const int64_t m = ((int64_t)n_dev[0] + kWave - 1) / kWave;
         n = m < n ? m : n;
@@ -776,15 +777,19 @@ __global__ __launch_bounds__(kLitScan) void glint_lit_scan(const uint32_t *__res
         for (int k = 0; k < 8; ++k) own += v[k];
     }
     for (; i < b1; ++i) own += counts[i];
-    ws[t] = own;
+    // exclusive prefix of the per-thread sums: DPP scan within the wave, then
+    // the totals of the waves before this one
+    const uint32_t incl = (uint32_t)wave_inclusive_sum((int)own);
+    if (lane == kWave - 1) ws[w] = incl;
     __syncthreads();
-    for (int d = 1; d < kLitScan; d <<= 1) {        // inclusive scan of the per-thread sums
-        const uint32_t v = t >= d ? ws[t - d] : 0u;
-        __syncthreads();
-        ws[t] += v;
-        __syncthreads();
+    uint32_t pre = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kScanWaves; ++k) {
+        const uint32_t x = ws[k];
+        total += x;
+        pre += k < w ? x : 0u;
     }
-    uint32_t run = ws[t] - own;
+    uint32_t run = pre + incl - own;
     i = b0;
     for (; i + 8 <= b1; i += 8) {
         uint32_t v[8];
@@ -800,7 +805,7 @@ __global__ __launch_bounds__(kLitScan) void glint_lit_scan(const uint32_t *__res
         offs[i] = run;
         run += counts[i];
     }
-    if (t == kLitScan - 1) len[0] = ws[t];
+    if (t == kLitScan - 1) len[0] = total;
 }
 
 __global__ __launch_bounds__(kLitThreads) void glint_lit_scatter(const uint16_t *__restrict__ lit, int32_t width,

@@ -113,7 +113,10 @@ __global__ __launch_bounds__(kWave * kOrderWaves) void glint_order_count(ViewDes
 }
 
 // counts cnt[block][class] -> offs[block][class]: class c's tiles of block b
-// start at (tiles of heavier classes) + (class-c tiles of blocks before b)
+// start at (tiles of heavier classes) + (class-c tiles of blocks before b).
+// Each thread sums a contiguous run of blocks; the runs are scanned per
+// class by DPP lane moves within each wave, then across the waves through
+// one LDS exchange.
 __global__ __launch_bounds__(kScanThreads) void glint_order_scan(const uint32_t *__restrict__ cnt,
                                                                  uint32_t *__restrict__ offs, int64_t n_blk)
 {
@@ -121,36 +124,34 @@ __global__ __launch_bounds__(kScanThreads) void glint_order_scan(const uint32_t 
     __shared__ uint32_t s_wt[kOrderClasses][kScanWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t per = (n_blk + kScanThreads - 1) / kScanThreads;
-    const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < n_blk ? b0 + per : n_blk;
+    const int64_t b0 = (int64_t)threadIdx.x * per < n_blk ? (int64_t)threadIdx.x * per : n_blk;
+    const int64_t b1 = b0 + per < n_blk ? b0 + per : n_blk;
     uint32_t loc[kOrderClasses];
 #pragma unroll
     for (int c = 0; c < kOrderClasses; ++c) loc[c] = 0;
     for (int64_t b = b0; b < b1; ++b)
 #pragma unroll
         for (int c = 0; c < kOrderClasses; ++c) loc[c] += cnt[b * kOrderClasses + c];
-    // exclusive prefix of this thread's chunk within its wave, per class
+    // exclusive prefix of this thread's run within its wave, per class
+    uint32_t excl[kOrderClasses];
 #pragma unroll
     for (int c = 0; c < kOrderClasses; ++c) {
-        uint32_t v = loc[c];
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t u = __shfl_up(v, d);
-            if (lane >= d) v += u;
-        }
-        if (lane == kWave - 1) s_wt[c][w] = v;
-        loc[c] = v - loc[c];
+        const uint32_t incl = (uint32_t)wave_inclusive_sum((int)loc[c]);
+        if (lane == kWave - 1) s_wt[c][w] = incl;
+        excl[c] = incl - loc[c];
     }
     __syncthreads();
     uint32_t base = 0, run[kOrderClasses];
 #pragma unroll
     for (int c = kOrderClasses - 1; c >= 0; --c) {
         uint32_t tot = 0, pre = 0;
+#pragma unroll
         for (int j = 0; j < kScanWaves; ++j) {
             const uint32_t x = s_wt[c][j];
             tot += x;
-            if (j < w) pre += x;
+            pre += j < w ? x : 0u;
         }
-        run[c] = base + pre + loc[c];
+        run[c] = base + pre + excl[c];
         base += tot;
     }
     for (int64_t b = b0; b < b1; ++b) {
