@@ -414,26 +414,27 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                             else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
                         }
                     }
-                } else if (RNG == kRngHash && HEAD && __ballot(K[g] > 128u) == 0ull) {
-                    // every lane's threshold is below 2^16: compare the hash head
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) {
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const uint32_t bit = (hstep_head(pre[g][e], ak0[a]) <= thr) ? 1u : 0u;
-                            if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
-                            else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
-                        }
-                    }
                 } else {
+                    uint32_t h[12];
+                    if (RNG == kRngHash && HEAD && __ballot(K[g] > 128u) == 0ull) {
+                        // every lane's threshold is below 2^16: compare the hash head
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) {
+                        for (int k = 0; k < 12; ++k) h[k] = hstep_head(pre[g][k >> 2], ak0[k & 3]);
+                    } else {
 #pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const uint32_t bit = (rng_word<RNG>(pre[g][e], ak0[a], sh, ltbl) <= thr) ? 1u : 0u;
-                            if (g < 2) mlo |= bit << (g * 16 + e * 4 + a);
-                            else mhi |= bit << ((g - 2) * 16 + e * 4 + a);
-                        }
+                        for (int k = 0; k < 12; ++k) h[k] = rng_word<RNG>(pre[g][k >> 2], ak0[k & 3], sh, ltbl);
+                    }
+                    // gates open rarely: the smallest of the node's twelve words
+                    // decides whether any opened, and the per-gate bits are only
+                    // formed when one did in some lane of the wave
+                    const uint32_t hmin = min(min(min(h[0], min(h[1], h[2])), min(h[3], min(h[4], h[5]))),
+                                              min(min(h[6], min(h[7], h[8])), min(h[9], min(h[10], h[11]))));
+                    if (__ballot(hmin <= thr) != 0ull) {
+                        uint32_t bits = 0u;
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) bits |= (h[k] <= thr ? 1u : 0u) << k;
+                        if (g < 2) mlo |= bits << (g * 16);
+                        else mhi |= bits << ((g - 2) * 16);
                     }
                 }
             }
