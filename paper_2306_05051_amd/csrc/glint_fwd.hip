@@ -124,29 +124,25 @@ __device__ __forceinline__ void unpack_frac(uint32_t bits, float &f, float &g)
 }
 
 // element (g, e) of a per-lane [4][3] register array for a per-lane (g, e):
-// a tree of selects (registers cannot be indexed per lane).  Each element
-// passes through an empty register constraint first, so that the compiler
-// cannot fold the selects into one load from a per-lane address (which would
-// move the array to scratch memory).
+// a tree of selects (registers cannot be indexed per lane).  The twelve
+// values arrive as arguments, not through a reference to the array, so that
+// the compiler has no loads that it could fold into one load from a per-lane
+// address (which would move the array to scratch memory).
 template <typename T>
-__device__ __forceinline__ T pick43(const T (&a)[4][3], int g, int e)
+__device__ __forceinline__ T pick43v(T a00, T a01, T a02, T a10, T a11, T a12, T a20, T a21, T a22, T a30, T a31,
+                                     T a32, int g, int e)
 {
-    T v[4][3];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            v[i][k] = a[i][k];
-            asm("" : "+v"(v[i][k]));
-        }
     const bool e1 = e == 1, e2 = e == 2;
-    const T x0 = e2 ? v[0][2] : (e1 ? v[0][1] : v[0][0]);
-    const T x1 = e2 ? v[1][2] : (e1 ? v[1][1] : v[1][0]);
-    const T x2 = e2 ? v[2][2] : (e1 ? v[2][1] : v[2][0]);
-    const T x3 = e2 ? v[3][2] : (e1 ? v[3][1] : v[3][0]);
+    const T x0 = e2 ? a02 : (e1 ? a01 : a00);
+    const T x1 = e2 ? a12 : (e1 ? a11 : a10);
+    const T x2 = e2 ? a22 : (e1 ? a21 : a20);
+    const T x3 = e2 ? a32 : (e1 ? a31 : a30);
     const bool g0 = (g & 1) != 0;
     return (g & 2) ? (g0 ? x3 : x2) : (g0 ? x1 : x0);
 }
+#define GLINT_PICK43(a, g, e)                                                                                     \
+    pick43v((a)[0][0], (a)[0][1], (a)[0][2], (a)[1][0], (a)[1][1], (a)[1][2], (a)[2][0], (a)[2][1], (a)[2][2], \
+            (a)[3][0], (a)[3][1], (a)[3][2], (g), (e))
 
 // ---------------------------------------------------------------------------
 // One (pixel, probe) item: simplex texels of every grid node, then per light
@@ -456,14 +452,14 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                 else { idx = 32 + __builtin_ctz(mhi); mhi &= mhi - 1u; }
                 const int g = idx >> 4, e = (idx >> 2) & 3, a = idx & 3;
                 const uint32_t ak1 = angular_key(A, B, a & 1, a >> 1, 1);
-                const uint32_t h1 = rng_word<RNG>(pick43(pre, g, e), ak1, sh, ltbl);
+                const uint32_t h1 = rng_word<RNG>(GLINT_PICK43(pre, g, e), ak1, sh, ltbl);
                 // Eq. 17 for node g: m = max(n - 1, 0), 1 + mu, sigma (the adjoint repeats this arithmetic)
                 const float ng = sm.ng[g][ip];
                 const float m = fmaxf(ng - 1.0f, 0.0f);
                 const float x = fmaf(__builtin_amdgcn_sqrtf(m * p * (1.0f - p)), ndtri_bits(h1), 1.0f + m * p);
                 const float c = sh.rounding ? fmaxf(x, 1.0f) : fmaxf(floorf(x), 1.0f);
                 const float va = ((a & 1) ? fx : gx) * ((a & 2) ? fy : gy);   // bilinear weight (Eq. 14)
-                bsum = fmaf(pick43(beta, g, e) * va, c, bsum);
+                bsum = fmaf(GLINT_PICK43(beta, g, e) * va, c, bsum);
                 if (DEBUG) { o.n_open += 1; o.count_sum += sh.rounding ? 0u : (uint32_t)c; }
                 if (dump) dd.count[li * 48 + g * 12 + e * 4 + a] = c;
             }
