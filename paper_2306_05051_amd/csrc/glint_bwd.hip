@@ -413,14 +413,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void gl
 // no lane waits on a light another lane needs.  Chunk c is the lit-list
 // entries [64c, 64c + 64); its items are numbered pixel by pixel (probe
 // rank major, light rank minor) and cut into batches of 64, the work units.
-// A fixed grid of kUnitGroups workgroups (two per wave slot of the chip, so
-// that slots freed early take a second range) takes contiguous ranges of
+// A fixed grid of kUnitGroups workgroups (four per wave slot of the chip, so
+// that slots freed early take further ranges) takes contiguous ranges of
 // units (the same number each), redoes a chunk's pixel set-up only when its
 // range enters that chunk, and writes one partial row per workgroup: the
 // sums run in a fixed order whatever the schedule.
 // ---------------------------------------------------------------------------
 constexpr int kUnitWaves = 4;          // chunks per workgroup of the count pass
-constexpr int kUnitGroups = 8192;      // workgroups (partial rows) of the unit kernel: two per wave slot
+constexpr int kUnitGroups = 16384;     // workgroups (partial rows) of the unit kernel: four per wave slot
 
 // probe items of a lit pixel: its probes with an open gate (bit k: probe k;
 // bit 31: probes 31 to npr - 1)
