@@ -565,7 +565,7 @@ __device__ uint32_t akey_fingerprint(const Pixel &px, const Shared &sh)
 // lrec: the tile's dynamic LDS, n_light * kLightRecBytes.
 // ---------------------------------------------------------------------------
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LAW = kLawDistributed>
-__device__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
+__device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh, const DebugPlanes &dp, int x0, int y0,
                            int lw, TileSmem<DEBUG> &sm, uint32_t *lrec, const uint32_t *ltbl = nullptr,
                            uint16_t *lit = nullptr, uint32_t *lit_probes = nullptr, float *zden = nullptr)
 {
