@@ -402,3 +402,21 @@ def test_batched_bit_identical_to_per_view(glint):
                 assert torch.equal(a, b)
         p2.close()
     plan.close()
+
+
+def test_batched_more_views_than_a_wave(glint):
+    """70 small views (more views than lanes in a wave, 16-72 pixels a side):
+    the per-tile and the persistent kernel against per-view glint_shade."""
+    views, mats, lights = scenes.batched_views(n_views=70, seed=2, side_min=16, side_max=72)
+    dviews = [glint.to_device(v) for v in views]
+    ref = [glint.glint_shade(v, mats, lights) for v in dviews]
+    outs = [torch.full((3,) + v["u"].shape, -1.0, device="cuda") for v in dviews]
+    for tune in ((16, 4, 0), (16, 4, 2)):
+        plan = glint.GlintPlan(dviews, outs, mats, lights, tune=tune)
+        for o in outs:
+            o.fill_(-1.0)
+        plan.run(use_graph=False)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(ref, outs)):
+            assert torch.equal(a, b), (tune, i)
+        plan.close()
