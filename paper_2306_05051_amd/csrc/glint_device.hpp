@@ -831,15 +831,16 @@ __device__ __forceinline__ void probe_centre(double u, double v, double ex, doub
 // root.  All four nodes are computed without branching (almost every pixel has
 // four, and straight-line code lets the nodes' FP64 and hash chains
 // interleave); the keys of nodes past the pixel's node count are never used.
-__device__ __forceinline__ void texel_keys(double cx, double cy, const uint32_t w[4], uint32_t root, const Shared &sh,
-                                           uint32_t pre[4][3], float beta[4][3])
+// base[g] = H(root, w[g]), the node's key prefix (it depends on the pixel only)
+__device__ __forceinline__ void texel_keys_from(double cx, double cy, const uint32_t w[4], const uint32_t base_g[4],
+                                                const Shared &sh, uint32_t pre[4][3], float beta[4][3])
 {
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int l = (int)(w[g] & 0x7ffu) - 1024, k = (w[g] >> 11) & 7, m = w[g] >> 14;
         int vi[3], vj[3];
         simplex_locate(cx, cy, l, k, m, sh, vi, vj, beta[g]);
-        const uint32_t base = hstep(root, w[g]);
+        const uint32_t base = base_g[g];
         // vertex keys H(H(base, i), j): the triangle's vertices span two
         // columns i0 = vi[0] and i0 + 1 = vi[2], so two inner steps serve all three
         const uint32_t h0 = hstep(base, (uint32_t)vi[0]), h1 = hstep(base, (uint32_t)vi[2]);
@@ -847,6 +848,15 @@ __device__ __forceinline__ void texel_keys(double cx, double cy, const uint32_t 
         pre[g][1] = hstep(vi[1] == vi[0] ? h0 : h1, (uint32_t)vj[1]);
         pre[g][2] = hstep(h1, (uint32_t)vj[2]);
     }
+}
+
+__device__ __forceinline__ void texel_keys(double cx, double cy, const uint32_t w[4], uint32_t root, const Shared &sh,
+                                           uint32_t pre[4][3], float beta[4][3])
+{
+    uint32_t base[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) base[g] = hstep(root, w[g]);
+    texel_keys_from(cx, cy, w, base, sh, pre, beta);
 }
 
 // texel keys and barycentric weights of one probe's simplex texels (Sec. 6.2),

@@ -236,8 +236,8 @@ __device__ void dump_zero(const DumpDst &d, int n_light)
 // pixel in the tile, kp: its probe, (u, v): the pixel's uv.
 template <bool DEBUG, bool HEAD = true, int RNG = kRngHash, bool LIT = false, int LK = 1, int LAW = kLawDistributed>
 __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint32_t *lrec, int ip, double u, double v,
-                                           int kp, const Shared &sh, ItemOut &o, const uint32_t *ltbl, float zN = 0.0f,
-                                           const DumpDst dd = DumpDst{})
+                                           int kp, const uint32_t (&nbase)[4], const Shared &sh, ItemOut &o,
+                                           const uint32_t *ltbl, float zN = 0.0f, const DumpDst dd = DumpDst{})
 {
     static_assert(LK == 1 || ((LK == 2 || LK == 4) && !DEBUG), "several lanes per item only in the production kernels");
     const int lane = threadIdx.x;
@@ -265,7 +265,7 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
     probe_centre(u, v, (double)sm.ex[ip], (double)sm.ey[ip], kp, npr, cx, cy);
     uint32_t pre[4][3];
     float beta[4][3];
-    texel_keys(cx, cy, wd, M.root, sh, pre, beta);
+    texel_keys_from(cx, cy, wd, nbase, sh, pre, beta);
     const bool dump = DEBUG && dd.key != nullptr;
     if (DEBUG) {
         for (int g = 0; g < nn; ++g)
@@ -580,6 +580,7 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
     const int64_t idx = (int64_t)y * vw.stride + x;
     int npr = 0;
     float pxu = 0.0f, pxv = 0.0f;              // the pixel's uv (its items read them across lanes)
+    uint32_t pxb[4] = {0u, 0u, 0u, 0u};        // its nodes' key prefixes H(root, node), likewise
     uint32_t dflags = 0, dcell = 0, dakey = 0;
     int dlevel = 0;
     {
@@ -592,6 +593,8 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
             pxu = (float)px.u;
             pxv = (float)px.v;
             const PixelRec r = make_rec(px, sh);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) pxb[g] = hstep(sh.mats[px.mat].root, rec_node_word(r, g));
             sm.ex[lane] = r.ex;
             sm.ey[lane] = r.ey;
             {
@@ -660,6 +663,9 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
         const int p = item_pixel(off, qc);
         const int kp = qc - __shfl(off, p);
         const double pu = (double)__shfl(pxu, p), pv = (double)__shfl(pxv, p);
+        uint32_t nb[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) nb[g] = (uint32_t)__shfl((int)pxb[g], p);
         if (q < S) {
             ItemOut o;
             const float zN = LAW == kLawZk ? zden[p] : 0.0f;
@@ -668,13 +674,13 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
                 DumpDst dd = {};
                 const int slot = dp.dump_slot ? dp.dump_slot[pidx] : -1;
                 if (slot >= 0 && slot < dp.dump_cap && kp < dp.dump_probes) dd = dump_dst(dp, slot, kp, sh.n_light);
-                shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN, dd);
+                shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, nb, sh, o, ltbl, zN, dd);
             } else if (lk == 1)
-                shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
+                shade_item<DEBUG, HEAD, RNG, LIT, 1, LAW>(sm, lrec, p, pu, pv, kp, nb, sh, o, ltbl, zN);
             else if (lk == 2)
-                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
+                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 2, LAW>(sm, lrec, p, pu, pv, kp, nb, sh, o, ltbl, zN);
             else
-                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 4, LAW>(sm, lrec, p, pu, pv, kp, sh, o, ltbl, zN);
+                shade_item<DEBUG, HEAD, RNG, LIT, DEBUG ? 1 : 4, LAW>(sm, lrec, p, pu, pv, kp, nb, sh, o, ltbl, zN);
             o0 = o.rgb[0];
             o1 = o.rgb[1];
             o2 = o.rgb[2];
