@@ -132,6 +132,36 @@ def test_gated_pmf_closed_form(n, p):
     assert np.max(np.abs(hist[1:] - pmf[1:] / pg)) < 3.0 / th1.size + 1e-9
 
 
+@pytest.mark.parametrize("n,p", [(6.0, 0.3), (30.0, 0.2), (3.3, 0.7)])
+def test_gated_count_histogram_from_hashed_uniforms(n, p):
+    """The whole chain of one texel's count: gate and count uniforms hashed
+    from texel keys and the slot-0 / slot-1 angular keys (H(prefix, angular
+    key), theta = (2 (h >> 9) + 1) 2^-24), then the gated binomial.  The
+    realised histogram over 60000 texels, zeros included, against the closed
+    form through Phi (chi-squared)."""
+    from scipy import stats
+    ang = [oracle.hash_step(0x13198A2E, (5 + 16384) | ((7 + 16384) << 15) | (s << 30)) for s in (0, 1)]
+    root = oracle.hash_step(0x243F6A88, 11)
+    c = np.empty(60000, np.int64)
+    k = 0
+    for i in range(300):
+        hi = oracle.hash_step(root, i)
+        for j in range(200):
+            pre = oracle.hash_step(hi, j)
+            th0, th1 = [((oracle.hash_step(pre, a) >> 9) * 2 + 1) / 2.0**24 for a in ang]
+            c[k] = int(oracle.gated_count(n, p, th0, th1))
+            k += 1
+    pmf = bf.gated_pmf(n, p)
+    obs = np.bincount(c, minlength=pmf.size)
+    assert obs.size == pmf.size, "count beyond the closed form's support"
+    exp = pmf * c.size
+    keep = exp >= 5.0
+    chi2 = float(np.sum((obs[keep] - exp[keep]) ** 2 / exp[keep])) + \
+        float((obs[~keep].sum() - exp[~keep].sum()) ** 2 / max(exp[~keep].sum(), 1.0))
+    dof = int(keep.sum())
+    assert stats.chi2.sf(chi2, dof) > 1e-4, (obs, exp)
+
+
 # ---------------------------------------------------------------------------
 # Hash: uniformity and independence of the per-texel uniforms
 # ---------------------------------------------------------------------------
