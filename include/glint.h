@@ -314,7 +314,8 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * reduced in a fixed order (deterministic).  Per-pixel overrides
  * (alpha_px, log10_density_px) are not supported (EUNSUPPORTED).
  * workspace: device memory of at least glint_backward_workspace_bytes()
- * bytes (about 4 bytes per pixel plus one partial row per 16x4 tile),
+ * bytes (about 4 bytes per pixel plus one partial row per 16x4 tile, or
+ * per unit workgroup for small images),
  * 8-byte aligned, owned by the caller and used by this call only (tile
  * order, partial rows, FP64 reduction stage, lit-pixel list).  Without a
  * mask, tiles run heaviest first; the sums are reduced in a fixed order over
@@ -330,7 +331,7 @@ size_t glint_backward_workspace_bytes(int32_t width, int32_t height, int32_t n_m
  * raster order into waves of 64 (each chunk has its own partial row).  With
  * both masks (and n_light > 0) the work is cut into units of 64
  * (pixel, lit probe, lit light) items, one light per lane (bit 31 of the
- * probe mask stands for probes 31 to n_pr - 1), and 8192 workgroups take
+ * probe mask stands for probes 31 to n_pr - 1), and 16384 workgroups take
  * equal contiguous ranges of units, each with its own partial row.  NULL
  * evaluates every gate of every pixel.  Errors as glint_shade, plus ENULL
  * (workspace, gradient outputs), EINVAL (misaligned workspace, lit_lights
