@@ -708,7 +708,9 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
                 kj = 0;
             }
         }
-        segmented_sums<LIT>(v, vl, vm, lane - min(kj, lane));
+        // a batch whose items are all first probes has one item per pixel:
+        // every segment is a single lane and the sums are the items themselves
+        if (__ballot(kj != 0) != 0ull) segmented_sums<LIT>(v, vl, vm, lane - min(kj, lane));
         // pixel lane: its items i0..i1-1 of this batch end on lane i1-1-base
         const int i0 = max(off, base), i1 = min(off + npr, base + kWave);
         const int src = i1 > i0 ? i1 - 1 - base : lane;
