@@ -283,8 +283,9 @@ def main():
                 "frac": round(achieved / costmodel.VALU_PEAK_SLOTS, 4), "traffic": recorded_traffic(),
                 "kernel": "glint_fwd_kernel<false> + tile-order pre-pass", "kernel_ms": round(kernel_ms, 4),
                 "slots_per_launch": int(slots), "units_per_launch": units}
-    # the two other fractions the survey asks for; roofline.frac (algorithmic
-    # slots over the issue peak) is the headline one
+    # two further fractions of the forward call (FP32 FLOP/s, VALU issue
+    # rate); roofline.frac (algorithmic slots over the issue peak) is the
+    # headline one
     fr = other_fractions(kernel_ms)
     if fr is not None:
         extra["fractions"] = fr
