@@ -74,6 +74,22 @@ def test_ndf_normalisation(kind, alpha):
     assert val == pytest.approx(1.0, rel=2e-7)
 
 
+@pytest.mark.parametrize("alpha", [0.05, 0.3, 1.0])
+def test_ndf_textbook_closed_forms(alpha):
+    """Sec. 3 names the standard NDFs GGX and Beckmann; their textbook forms
+    (Walter et al. 2007) in the half-angle theta_m:
+    GGX D = alpha^2 / (pi cos^4 (alpha^2 + tan^2)^2),
+    Beckmann D = exp(-tan^2 / alpha^2) / (pi alpha^2 cos^4).
+    Normalisation alone holds for any consistent roughness convention; this
+    fixes the convention (alpha, not alpha^2, is the roughness)."""
+    for th in np.linspace(0.0, 1.45, 30):
+        c, t2 = math.cos(th), math.tan(th) ** 2
+        ggx = alpha**2 / (math.pi * c**4 * (alpha**2 + t2) ** 2)
+        beck = math.exp(-t2 / alpha**2) / (math.pi * alpha**2 * c**4)
+        assert oracle.ndf(0, alpha, c) == pytest.approx(ggx, rel=1e-12, abs=1e-300)
+        assert oracle.ndf(1, alpha, c) == pytest.approx(beck, rel=1e-12, abs=1e-300)
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("alpha", [0.1, 0.4, 0.9])
 @pytest.mark.parametrize("theta_deg", [20.0, 60.0, 80.0])
