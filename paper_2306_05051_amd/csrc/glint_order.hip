@@ -18,10 +18,13 @@ namespace glint {
 // many probes) start early instead of trailing at the end of the grid.  The
 // order only schedules work; every tile's arithmetic is unchanged.
 //   count:   tile cost S = sum of the pixels' probe counts (an FP32 estimate
-//            of the forward's n_pr), class of ceil(S / 64) item batches;
+//            of the forward's n_pr), class of ceil(S / 64) item batches (with
+//            an even number of tile columns, the heavier class of the two
+//            tiles that share the same 128-byte lines for both);
 //            per block of kOrderTiles tiles, the count of each class
 //   scan:    one workgroup turns the counts into output offsets
-//   scatter: one workgroup per block ranks its tiles within each class
+//   scatter: one workgroup per block ranks its tiles within each class; the
+//            two tiles of such a pair get workgroups b and b + 8 (one XCD)
 // ---------------------------------------------------------------------------
 constexpr int kOrderClasses = 8;
 constexpr int kOrderTiles = 64;       // tiles per count block
@@ -50,7 +53,7 @@ __device__ __forceinline__ int probe_estimate(float dux, float dvx, float duy, f
 
 __global__ __launch_bounds__(kWave * kOrderWaves) void glint_order_count(ViewDesc vw, int lw, int tiles_x, int32_t n_tiles,
                                                                          int n_mat, float inv_rmax,
-                                                                         int n_probe_max, uint8_t *cls,
+                                                                         int n_probe_max, bool paired, uint8_t *cls,
                                                                          uint32_t *cnt)
 {
     constexpr int kPerWave = kOrderTiles / kOrderWaves;
@@ -91,16 +94,31 @@ __global__ __launch_bounds__(kWave * kOrderWaves) void glint_order_count(ViewDes
 #pragma unroll
     for (int i = 0; i < kPerWave; ++i)
         S[i] = ok[i] ? probe_estimate(d[i][0], d[i][1], d[i][2], d[i][3], inv_rmax, n_probe_max) : 0;
-    uint32_t mine = 0;                    // lane c < 8: this wave's count of class c
+    int c[kPerWave];
 #pragma unroll
     for (int i = 0; i < kPerWave; ++i) {
         int v = S[i];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-        const int c = cost_class(v);
+        c[i] = cost_class(v);
+    }
+    // paired: the two tiles of a pair (columns 2m and 2m + 1 of a row, the
+    // two halves of the same 128-byte lines) take the heavier class, so that
+    // they stay adjacent in the order (t0 is a multiple of 4, so pairs lie
+    // inside the wave's tiles)
+    if (paired) {
+#pragma unroll
+        for (int i = 0; i < kPerWave; i += 2) {
+            const int m = c[i] > c[i + 1] ? c[i] : c[i + 1];
+            c[i] = c[i + 1] = m;
+        }
+    }
+    uint32_t mine = 0;                    // lane c < 8: this wave's count of class c
+#pragma unroll
+    for (int i = 0; i < kPerWave; ++i) {
         if (t0 + i < n_tiles) {
-            if (lane == 0) cls[t0 + i] = (uint8_t)c;
-            if (lane == c) ++mine;
+            if (lane == 0) cls[t0 + i] = (uint8_t)c[i];
+            if (lane == c[i]) ++mine;
         }
     }
     if (lane < kOrderClasses) s_cnt[w][lane] = mine;
@@ -168,7 +186,8 @@ __global__ __launch_bounds__(kScanThreads) void glint_order_scan(const uint32_t 
 
 __global__ __launch_bounds__(kOrderTiles) void glint_order_scatter(const uint8_t *__restrict__ cls,
                                                                    const uint32_t *__restrict__ offs,
-                                                                   int32_t n_tiles, int32_t *__restrict__ order)
+                                                                   int32_t n_tiles, bool paired,
+                                                                   int32_t *__restrict__ order)
 {
     __shared__ uint32_t s_wc[kScatterWaves][kOrderClasses];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -186,6 +205,12 @@ __global__ __launch_bounds__(kOrderTiles) void glint_order_scatter(const uint8_t
     if (c >= 0) {
         uint32_t pos = offs[(int64_t)blockIdx.x * kOrderClasses + c] + rank;
         for (int j = 0; j < w; ++j) pos += s_wc[j][c];
+        // paired: position 16q + 2j + i (pair j of group q, member i) goes to
+        // workgroup 16q + j + 8i, so that both tiles of a pair run on the same
+        // XCD (workgroups go to the 8 XCDs in turn) at about the same time and
+        // the second finds the shared lines in that XCD's L2; the last, partial
+        // group of 16 keeps its positions
+        if (paired && pos < ((uint32_t)n_tiles & ~15u)) pos = (pos & ~15u) + ((pos & 15u) >> 1) + ((pos & 1u) << 3);
         order[pos] = (int32_t)t;
     }
 }
@@ -227,11 +252,12 @@ int enqueue_tile_order(const ViewDesc &vw, const Shared &sh, void *ws, size_t ws
     uint32_t *cnt = (uint32_t *)(w + L.cnt_off);
     uint32_t *offs = (uint32_t *)(w + L.offs_off);
     const float inv_rmax = 1.0f / (float)(1 << sh.k_max);
+    const bool paired = (tiles_x & 1) == 0;   // every row splits into whole pairs
     hipLaunchKernelGGL(glint_order_count, dim3((unsigned)L.n_blk), dim3(kWave * kOrderWaves), 0, st, vw, kTileLw, tiles_x,
-                       (int32_t)L.n_tiles, sh.n_mat, inv_rmax, sh.n_probe_max, cls, cnt);
+                       (int32_t)L.n_tiles, sh.n_mat, inv_rmax, sh.n_probe_max, paired, cls, cnt);
     hipLaunchKernelGGL(glint_order_scan, dim3(1), dim3(kScanThreads), 0, st, cnt, offs, L.n_blk);
     hipLaunchKernelGGL(glint_order_scatter, dim3((unsigned)L.n_blk), dim3(kOrderTiles), 0, st, cls, offs,
-                       (int32_t)L.n_tiles, ord);
+                       (int32_t)L.n_tiles, paired, ord);
     *order = ord;
     return GLINT_OK;
 }

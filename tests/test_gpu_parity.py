@@ -315,20 +315,24 @@ def test_deterministic(glint):
     assert torch.equal(a, b)
 
 
-def test_tile_order_is_a_heaviest_first_permutation(glint):
+@pytest.mark.parametrize("W,H", [(645, 363), (640, 363)], ids=["odd_columns", "paired"])
+def test_tile_order_is_a_heaviest_first_permutation(glint, W, H):
     """The cost-ordered tile schedule: the order is a permutation of the
     tiles, sorted by cost class (heaviest first, ties in row-major order),
     and the image is bit-identical to the row-major schedule.  Ragged size:
-    a partial last count block and partial edge tiles."""
-    gb, mats, lights = scenes.four_k(645, 363, seed=5)
+    a partial last count block and partial edge tiles.  With an even number
+    of tile columns the two tiles of each pair (columns 2m, 2m + 1: the two
+    halves of the same 128-byte lines) share the heavier class, are adjacent
+    in the sorted order, and run on workgroups b and b + 8 (one XCD)."""
+    gb, mats, lights = scenes.four_k(W, H, seed=5)
     dgb = glint.to_device(gb)
-    H, W = gb["u"].shape
     TW, TH = glint.GLINT_TILE_W, glint.GLINT_TILE_H
     tx, ty = (W + TW - 1) // TW, (H + TH - 1) // TH
     n = tx * ty
+    paired = tx % 2 == 0
     nb = glint.glint_shade_workspace_bytes(W, H)
     ws = torch.full((nb,), 0xAB, dtype=torch.uint8, device="cuda")
-    print(f"  tile order: {W}x{H}, {n} tiles, workspace {nb} B", flush=True)
+    print(f"  tile order: {W}x{H}, {n} tiles, paired {paired}, workspace {nb} B", flush=True)
     a = glint.glint_shade(dgb, mats, lights, workspace=ws)
     order = ws[:4 * n].view(torch.int32).cpu().numpy().astype(np.int64)
     b = glint.glint_shade(dgb, mats, lights, workspace=False)
@@ -343,14 +347,33 @@ def test_tile_order_is_a_heaviest_first_permutation(glint):
     S = npr.reshape(ty, TH, tx, TW).transpose(0, 2, 1, 3).reshape(n, 64).sum(1)
     bt = (S + 63) // 64
     cls = np.select([bt < 4, bt < 6, bt < 9, bt < 14], [bt, 4, 5, 6], 7)
-    seq = cls[order]
+    seq_order = order
+    if paired:
+        pair_cls = np.maximum(cls[0::2], cls[1::2])
+        cls = np.repeat(pair_cls, 2)
+        # undo the slot mapping: workgroup 16q + r holds sorted position
+        # 16q + 2r (r < 8) or 16q + 2(r - 8) + 1 (r >= 8); the last partial
+        # group of 16 is not mapped
+        w = np.arange(n)
+        q, r = w // 16, w % 16
+        pos = np.where(r < 8, 16 * q + 2 * r, 16 * q + 2 * (r - 8) + 1)
+        pos = np.where(w < (n & ~15), pos, w)
+        seq_order = np.empty(n, np.int64)
+        seq_order[pos] = order
+        # line-mates adjacent in the sorted order and on workgroups b, b + 8
+        ev, od = seq_order[0::2], seq_order[1::2]
+        assert np.all(ev % 2 == 0) and np.all(od == ev + 1)
+        full = (n & ~15)
+        wg = np.arange(full).reshape(-1, 16)
+        assert np.all(order[wg[:, 8:]] == order[wg[:, :8]] + 1)
+    seq = cls[seq_order]
     inversions = int(np.sum(seq[1:] > seq[:-1]))
     print(f"  classes {np.bincount(cls, minlength=8).tolist()}, inversions {inversions}", flush=True)
     assert len(np.unique(cls)) >= 3
     assert inversions <= max(2, n // 500)
     # within a class, tiles keep row-major order (stable sort)
     for c in np.unique(seq):
-        idx = order[seq == c]
+        idx = seq_order[seq == c]
         assert np.mean(np.diff(idx) > 0) > 0.99
 
 
