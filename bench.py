@@ -205,8 +205,9 @@ def main():
                     help="run one 1 GiB device copy (HBM byte-counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the path shards by pixels/views "
-              "with no exchange (see the design notes), but no multi-GPU run is provided.", file=sys.stderr)
+        print("bench.py runs on one GPU only: the shading path would shard by pixels or views with no "
+              "exchange (the adjoint with one all-reduce of its partial sums), but no multi-GPU run is "
+              "provided.", file=sys.stderr)
         sys.exit(2)
 
     import torch
