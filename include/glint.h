@@ -44,7 +44,7 @@ enum {
     GLINT_ENULL = -2,         /* a required pointer is NULL                        */
     GLINT_ESHAPE = -3,        /* width/height/stride/count inconsistent             */
     GLINT_EHIP = -4,          /* a HIP runtime call failed (glint_last_hip_error)  */
-    GLINT_EUNSUPPORTED = -5,  /* valid request this build does not implement       */
+    GLINT_EUNSUPPORTED = -5,  /* valid request the library does not implement      */
     GLINT_ENOMEM = -6,        /* device allocation inside a plan failed            */
     GLINT_ELIMIT = -7         /* view larger than glint_shade_noalloc's static workspace */
 };

@@ -10,8 +10,8 @@
  *
  * Every step follows the paper in its own order and notation, in FP64, from
  * the same FP32 inputs the GPU reads.  Where the paper leaves a choice open,
- * the reading taken is the one written next to the step (the design notes
- * list all of them).  Nothing here is blocked, fused or reordered for speed.
+ * the reading taken is the one written next to the step.  Nothing here is
+ * blocked, fused or reordered for speed.
  *
  *   step                                        paper passage
  *   footprint ellipse from screen derivatives   Sec. 5.1 (major/minor axes, rotation, ratio)
