@@ -56,7 +56,9 @@ keys and gates):
   lit pixel-light (extra, when at least one gate of the light opened in
       some probe of the pixel; otherwise the light adds exactly nothing):
       Fresnel 13, Smith Lambda(wo) 20, radiance factor and RGB 13 = 46
-  item (one pixel, probe: only what depends on the probe's centre): probe
+  item (one pixel, probe, for the pixels where some gate of some light can
+      open: the others shade to exactly 0 and need no probe work; only what
+      depends on the probe's centre): probe
       centre 28, 4 x (key unpack 5, trig table index 3, rotation 8,
       anisotropic scales 14, lattice shear/floor/fractions 18, triangle 2,
       vertex selects 6, barycentrics 10, texel keys H(H(node, i), j) of the
@@ -150,9 +152,12 @@ def units_from_debug(dbg):
     live = int((dbg["n_live"].astype(np.int64) & 0xFFFFFFFF).sum())
     small = int((dbg["n_live_small"].astype(np.int64) & 0xFFFFFFFF).sum()) if "n_live_small" in dbg else 0
     lit_pl = int(((dbg["b_light"] > 0) & shaded[None]).sum()) if "b_light" in dbg else 0
+    # items only of pixels where some gate can open: the others shade to
+    # exactly 0 and need no item (their light set-up decides it)
+    n_live = dbg["n_live"].astype(np.int64) & 0xFFFFFFFF
     return {
         "pixel": int(shaded.sum()),
-        "item": int(n_probe[shaded].sum()),
+        "item": int(n_probe[shaded & (n_live > 0)].sum()),
         "pixel_light": int(pixel_lights.sum()),
         "pixel_light_lit": lit_pl,
         "live_gate": live - small,

@@ -579,6 +579,7 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
     const bool inb = (x < vw.width) && (y < vw.height);
     const int64_t idx = (int64_t)y * vw.stride + x;
     int npr = 0;
+    bool plive = true;                         // some light of the pixel has a gate that can open
     float pxu = 0.0f, pxv = 0.0f;              // the pixel's uv (its items read them across lanes)
     uint32_t pxb[4] = {0u, 0u, 0u, 0u};        // its nodes' key prefixes H(root, node), likewise
     uint32_t dflags = 0, dcell = 0, dakey = 0;
@@ -610,6 +611,8 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
             const DevMaterial &M = sh.mats[px.mat];
             ViewFrame fr;
             view_frame(px.n, px.wi, px.rc, px.rs, fr);
+            const int nn = rec_nodes(r);
+            bool live = false;                 // some light above the horizon has a gate that can open
             for (int li = 0; li < sh.n_light; ++li) {
                 uint32_t w[kLightRecWords];
                 bool pclamp;
@@ -617,7 +620,12 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
                 if (pclamp) px.flags |= F_CLAMP_P;
 #pragma unroll
                 for (int k = 0; k < kLightRecWords; ++k) lrec[((size_t)li * kLightRecWords + k) * kWave + lane] = w[k];
+                // words 0-3: the nodes' gate thresholds (low 24 bits); bit 30 of
+                // word 3: the light is above the horizon
+                const uint32_t kor = w[0] | (nn > 1 ? w[1] : 0u) | (nn > 2 ? w[2] : 0u) | (nn > 3 ? w[3] : 0u);
+                live = live || (((w[3] >> 30) & 1u) != 0u && (kor & 0xFFFFFFu) != 0u);
             }
+            plive = live;
         }
         if (DEBUG) {
             dflags = px.flags;
@@ -631,15 +639,6 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
                 for (int k = npr; k < dp.dump_probes; ++k) dump_zero(dump_dst(dp, slot, k, sh.n_light), sh.n_light);
         }
     }
-    // (cross-lane reads: measured faster here than wave_inclusive_sum)
-    int incl = npr;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int t = __shfl_up(incl, d);
-        if (lane >= d) incl += t;
-    }
-    const int off = incl - npr;
-    const int S = __shfl(incl, kWave - 1);
     __syncthreads();
     if (!DEBUG) __builtin_amdgcn_s_setprio(0);
     float acc[3] = {0.0f, 0.0f, 0.0f};
@@ -648,6 +647,25 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
     float db[kMaxLight];
     if (DEBUG)
         for (int l = 0; l < kMaxLight; ++l) db[l] = 0.0f;
+    // A pixel where no gate of any light can open has radiance exactly 0 and
+    // no lit light: in production it has no items.  The instrumented kernel
+    // shades the items of such pixels after the others, in batches of their
+    // own (phase 1), for its counters; the other pixels' items then fall into
+    // the same batches as in production, so the per-pixel sums, and the
+    // image, have the same bits.
+    constexpr bool kSkipDead = LAW == kLawDistributed;
+    constexpr int kPhases = (DEBUG && kSkipDead) ? 2 : 1;
+    for (int phase = 0; phase < kPhases; ++phase) {
+    const int nph = !kSkipDead ? npr : (((phase == 0) == plive) ? npr : 0);
+    // (cross-lane reads: measured faster here than wave_inclusive_sum)
+    int incl = nph;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+    }
+    const int off = incl - nph;
+    const int S = __shfl(incl, kWave - 1);
     for (int base = 0; base < S; base += kWave) {
         // a last batch of at most 32 (16) items takes two (four) lanes per
         // item, lane r of the group shading the lights l = r mod 2 (4); the
@@ -712,7 +730,7 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
         // every segment is a single lane and the sums are the items themselves
         if (__ballot(kj != 0) != 0ull) segmented_sums<LIT>(v, vl, vm, lane - min(kj, lane));
         // pixel lane: its items i0..i1-1 of this batch end on lane i1-1-base
-        const int i0 = max(off, base), i1 = min(off + npr, base + kWave);
+        const int i0 = max(off, base), i1 = min(off + nph, base + kWave);
         const int src = i1 > i0 ? i1 - 1 - base : lane;
         const float r0 = __shfl(v[0], src), r1 = __shfl(v[1], src), r2 = __shfl(v[2], src);
         const uint32_t rl = LIT ? (uint32_t)__shfl((int)vl, src) : 0u, rm = LIT ? (uint32_t)__shfl((int)vm, src) : 0u;
@@ -738,6 +756,7 @@ __device__ __forceinline__ void shade_tile(const ViewDesc &vw, const Shared &sh,
             }
             __syncthreads();
         }
+    }
     }
     if (inb) {
         const int64_t npx = (int64_t)vw.height * vw.stride;

@@ -22,7 +22,9 @@ def test_units_count_pixel_lights_once():
         valid += (np.einsum("chw,c->hw", n, wo) > 0.0) & shaded
     npr = d["n_probe"].astype(np.int64)
     assert u["pixel"] == int(shaded.sum())
-    assert u["item"] == int(npr[shaded].sum())
+    # items of the pixels where some gate can open (the others shade to 0)
+    live_px = shaded & ((d["n_live"].astype(np.int64) & 0xFFFFFFFF) > 0)
+    assert u["item"] == int(npr[live_px].sum()) and 0 < u["item"] <= int(npr[shaded].sum())
     assert u["pixel_light"] == int(valid.sum())
     assert u["item_light"] == int((valid * npr).sum())
     # split footprints make the difference: more item-lights than pixel-lights
