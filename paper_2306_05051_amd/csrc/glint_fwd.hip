@@ -412,10 +412,15 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                     }
                 } else {
                     uint32_t h[12];
-                    if (RNG == kRngHash && HEAD && __ballot(K[g] > 128u) == 0ull) {
-                        // every lane's threshold is below 2^16: compare the hash head
+                    if constexpr (RNG == kRngHash) {
 #pragma unroll
                         for (int k = 0; k < 12; ++k) h[k] = hstep_head(pre[g][k >> 2], ak0[k & 3]);
+                        // the last step of fmix32, in place; skipped when every
+                        // lane's threshold is below 2^16 (the head decides then)
+                        if (!HEAD || __ballot(K[g] > 128u) != 0ull) {
+#pragma unroll
+                            for (int k = 0; k < 12; ++k) h[k] ^= h[k] >> 16;
+                        }
                     } else {
 #pragma unroll
                         for (int k = 0; k < 12; ++k) h[k] = rng_word<RNG>(pre[g][k >> 2], ak0[k & 3], sh, ltbl);
