@@ -46,10 +46,11 @@
  * (dual-number) derivatives of the same relaxed forward; the tangent frame orthonormal and
  * right-handed; the probe centres splitting the major axis into equal
  * segments; the Zirr-Kaplanyan baseline's branches against the binomial
- * and the floored-Gaussian closed forms, and its variance deficit.  The
- * hash and the angular cell size are definitions of this implementation:
- * parity unpinned beyond their statistical tests (uniformity,
- * independence) and the bit-exact match.
+ * and the floored-Gaussian closed forms, and its variance deficit; fmix32
+ * to MurmurHash3's published test vectors.  The hash's key layout and
+ * chaining and the angular cell size are definitions of this
+ * implementation: parity unpinned beyond their statistical tests
+ * (uniformity, independence) and the bit-exact match.
  */
 #include <math.h>
 #include <stdint.h>

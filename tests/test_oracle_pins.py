@@ -222,6 +222,45 @@ def test_rng_table_entries_uniform_and_uncorrelated():
     assert abs(np.corrcoef(u[: 1 << 10], ((other >> 9) * 2 + 1) / 2.0**24)[0, 1]) < 0.1
 
 
+def _murmur3_x86_32(data, seed):
+    """MurmurHash3_x86_32 (Appleby): 4-byte little-endian blocks mixed with
+    k *= c1, rotl 15, k *= c2 into h (h ^= k, rotl 13, h = 5 h + n), the tail
+    bytes mixed the same way without the h steps, h ^= length, and the
+    finaliser, which here is the oracle's."""
+    m32 = 0xFFFFFFFF
+    c1, c2 = 0xCC9E2D51, 0x1B873593
+
+    def rotl(x, r):
+        return ((x << r) | (x >> (32 - r))) & m32
+
+    def mix(k):
+        return (rotl((k * c1) & m32, 15) * c2) & m32
+
+    h, nb = seed, len(data) // 4
+    for i in range(nb):
+        h = rotl(h ^ mix(int.from_bytes(data[4 * i:4 * i + 4], "little")), 13)
+        h = (h * 5 + 0xE6546B64) & m32
+    tail = data[4 * nb:]
+    if tail:
+        h ^= mix(int.from_bytes(tail, "little"))
+    return oracle.fmix32(h ^ len(data))
+
+
+def test_fmix32_is_the_murmur3_finaliser():
+    """The oracle's fmix32 against MurmurHash3_x86_32's published test vectors
+    (tests/golden/murmur3_x86_32_vectors.txt): the empty-input ones are
+    fmix32(seed) exactly; a wrong shift, multiplier or step order fails them."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "murmur3_x86_32_vectors.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 13
+    for data, seed, want in rows:
+        b = b"" if data == "-" else bytes.fromhex(data)
+        assert _murmur3_x86_32(b, int(seed, 16)) == int(want, 16), (data, seed)
+        if data == "-":
+            assert oracle.fmix32(int(seed, 16)) == int(want, 16)
+
+
 def _table_scene():
     gb, mats, lights = scenes.four_k(48, 24, seed=13, n_mat=3, n_light=2)
     return gb, mats, lights
