@@ -31,18 +31,20 @@ keys and gates):
   hash step H(h, w) = fmix32((h ^ w) + c): xor-add, xor-shift, mul_lo, shift,
       xor, mul_lo, xor-shift = 5 + 2 x 2 = 9
   live gate (its node's gate probability reaches the smallest uniform 2^-24;
-      the others provably cannot open and need no work): H, then a share of
-      the node's test whether any of its twelve gates opened (five
-      three-input minimums and one compare per twelve gates, 0.5, rounded
-      up to 1) = 10; when the gate threshold is below 2^16 the hash head (H
-      without fmix32's last xor-shift, which is the identity on values below
-      2^16) decides the gate exactly: 9.  Gates open rarely, so which of a
-      node's gates opened is worked out only for an open gate (below).
-  open gate (extra): locating it among its node's twelve words (12
-      compares) 12, slot-1 angular key (pack 3 + H) 12, H 9, inverse normal
-      CDF (bits to x, 1-x, 1+x 7, log 6, select 1, polynomial 9, scale 2) 25,
-      node mean/sigma 11, Gaussian 1, count 2, bilinear weight and
-      accumulate 5 = 77
+      the others provably cannot open and need no work): the hash head (H
+      without fmix32's last xor-shift, which keeps the top 16 bits, so
+      H <= t implies head <= t | 0xFFFF, and for t below 2^16 the head
+      decides the gate exactly) 8, then a share of the node's test whether
+      any of its twelve gates can have opened (five three-input minimums
+      and one compare per twelve gates, 0.5, rounded up to 1) = 9, with
+      thresholds below 2^16 (live_gate_small) or not.  Gates open rarely,
+      so which of a node's gates opened is worked out only for an open gate
+      (below).
+  open gate (extra): locating it among its node's twelve words (the
+      twelve hashes' last steps and 12 compares) 24, slot-1 angular key
+      (pack 3 + H) 12, H 9, inverse normal CDF (bits to x, 1-x, 1+x 7,
+      log 6, select 1, polynomial 9, scale 2) 25, node mean/sigma 11,
+      Gaussian 1, count 2, bilinear weight and accumulate 5 = 89
   pixel-light (one pixel and one light: everything here depends on the
       pixel and the light only, never on the probe, so it is credited once
       per valid (pixel, light) pair however many probes the pixel has; the
@@ -78,7 +80,7 @@ gate in it) its set-up (pixel, above); per lit probe its texel keys (item);
 per lit (pixel, light) the light's set-up (pixel-light) and the gradient
 algebra below; per (probe, light) pair with an open gate its live gates
 again (to find the open ones: hash, compare and bit, 12 each); per open gate
-the forward's count (without the forward's locating compares) and the
+the forward's count (without the forward's locating steps and compares) and the
 derivative terms below.
   lit pixel-light gradient algebra: Fresnel and Lambda(wo) 33, cos^2/sin^2
       6, dp/dalpha and dp/d<n,h>^2 12, dLambda(wo)/d(c, alpha) 14, G 7,
@@ -109,9 +111,9 @@ FP64_RSQ = 8 + 4 * 2
 FP64_RCP = 8 + 2 * 2
 FP64_DIV, FP64_SQRT = 20, 24
 COST = {
-    "live_gate": HASH + 1,
+    "live_gate": HASH - 1 + 1,
     "live_gate_small": HASH - 1 + 1,
-    "open_gate": 12 + (3 + HASH) + HASH + 25 + 11 + 1 + 2 + 5,
+    "open_gate": 12 + 12 + (3 + HASH) + HASH + 25 + 11 + 1 + 2 + 5,
     "pixel_light": 8 + 6 + 4 + FP64_RSQ + 4 + 8 + 12 + 46 + 21 + 4 * 28 + 4 * (3 + HASH),
     "pixel_light_lit": 13 + 20 + 13,
     "item": (8 + FP64_RCP + 8) + 4 * (5 + 3 + 8 + 14 + 18 + 2 + 6 + 10 + 5 * HASH + 2) + 3,
@@ -129,7 +131,7 @@ BWD_COST = {
     # hashed, compared and its bit inserted (H + 3), and the open gates are
     # then located from the bits (no extra compares)
     "live_gate": HASH + 1 + 2,
-    "open_gate": (COST["open_gate"] - 12) + 30,
+    "open_gate": (COST["open_gate"] - 24) + 30,
 }
 
 

@@ -411,13 +411,17 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                         }
                     }
                 } else {
+                    // With the hash head (HEAD), the words are fmix32 without its
+                    // last step x ^= x >> 16, which keeps the top 16 bits:
+                    // H <= thr implies head <= thr | 0xFFFF, so a node whose
+                    // heads all exceed that bound opens no gate, and the last
+                    // step is only taken in the rare nodes that pass it.
+                    constexpr bool kHead = RNG == kRngHash && HEAD;
                     uint32_t h[12];
                     if constexpr (RNG == kRngHash) {
 #pragma unroll
                         for (int k = 0; k < 12; ++k) h[k] = hstep_head(pre[g][k >> 2], ak0[k & 3]);
-                        // the last step of fmix32, in place; skipped when every
-                        // lane's threshold is below 2^16 (the head decides then)
-                        if (!HEAD || __ballot(K[g] > 128u) != 0ull) {
+                        if constexpr (!HEAD) {
 #pragma unroll
                             for (int k = 0; k < 12; ++k) h[k] ^= h[k] >> 16;
                         }
@@ -426,11 +430,15 @@ __device__ __forceinline__ void shade_item(const TileSmem<DEBUG> &sm, const uint
                         for (int k = 0; k < 12; ++k) h[k] = rng_word<RNG>(pre[g][k >> 2], ak0[k & 3], sh, ltbl);
                     }
                     // gates open rarely: the smallest of the node's twelve words
-                    // decides whether any opened, and the per-gate bits are only
-                    // formed when one did in some lane of the wave
+                    // decides whether any can have opened, and the per-gate bits
+                    // are only formed when one may have in some lane of the wave
                     const uint32_t hmin = min(min(min(h[0], min(h[1], h[2])), min(h[3], min(h[4], h[5]))),
                                               min(min(h[6], min(h[7], h[8])), min(h[9], min(h[10], h[11]))));
-                    if (__ballot(hmin <= thr) != 0ull) {
+                    if (__ballot(hmin <= (kHead ? (thr | 0xFFFFu) : thr)) != 0ull) {
+                        if constexpr (kHead) {
+#pragma unroll
+                            for (int k = 0; k < 12; ++k) h[k] ^= h[k] >> 16;
+                        }
                         uint32_t bits = 0u;
 #pragma unroll
                         for (int k = 0; k < 12; ++k) bits |= (h[k] <= thr ? 1u : 0u) << k;
